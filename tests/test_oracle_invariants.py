@@ -1,0 +1,360 @@
+"""Whole-lattice pins of the FP64 oracle: exact invariants and discrete
+recurrences of the method, symmetry of the update, and a brute-force
+re-derivation of single steps on tiny grids through a different route
+(tensor contractions, a library pseudo-inverse, array rolls for streaming).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.test_oracle_pins import C2, C3, CS2, constraint_matrix, weights
+
+
+def smooth_fields(d, shape, seed, amp_u=0.02, amp_tau=1e-3, amp_p=1e-3):
+    """Seeded, smooth periodic fields (a few low Fourier modes)."""
+    rng = np.random.default_rng(seed)
+    grids = np.meshgrid(*[2 * np.pi * np.arange(n) / n for n in shape[::-1]],
+                        indexing="xy" if d == 2 else "ij")
+    if d == 3:
+        grids = np.meshgrid(*[2 * np.pi * np.arange(n) / n for n in shape],
+                            indexing="ij")[::-1]
+    N = int(np.prod(shape))
+    nc = 3 if d == 2 else 6
+
+    def field(scale):
+        out = np.zeros(shape)
+        for _ in range(3):
+            k = rng.integers(0, 2, size=d)
+            ph = rng.uniform(0, 2 * np.pi, size=d)
+            term = np.ones(shape)
+            for a in range(d):
+                term = term * np.cos(k[a] * grids[a] + ph[a])
+            out += rng.normal() * term
+        return scale * out.reshape(N)
+
+    u = np.stack([field(amp_u) for _ in range(d)], -1)
+    tau = np.stack([field(amp_tau) for _ in range(nc)], -1)
+    p = field(amp_p)
+    return u, tau, p
+
+
+def make(d, shape, tau_f=0.8, tau_h=0.501, lam=50.0, eta_p=0.05, walls=(0, 0, 0)):
+    nx = shape[-1]
+    ny = shape[-2]
+    nz = shape[0] if d == 3 else 1
+    s = O.OracleSim(d, nx, ny, nz)
+    s.set_params(tau_f, tau_h, lam, eta_p)
+    s.set_walls(walls)
+    return s
+
+
+@pytest.mark.parametrize("d,shape,walls", [(2, (8, 8), (0, 0, 0)), (2, (8, 6), (0, 1, 0)),
+                                           (3, (4, 5, 6), (0, 0, 0)), (3, (4, 5, 6), (0, 1, 1))])
+def test_rest_state_is_fixed_point(d, shape, walls):
+    s = make(d, shape, walls=walls)
+    s.init()
+    st0 = s.get_state()
+    s.step(7)
+    st = s.get_state()
+    # the oracle stores h unshifted, so sum_i w_i = 1 holds only to rounding
+    # and A - I is O(1e-16): the rest state is fixed to that rounding level
+    assert not st0["f"].any()
+    assert np.abs(st["f"]).max() < 1e-17
+    # h at rest is w_i delta_ab
+    w = weights(d)
+    nc = 3 if d == 2 else 6
+    diag = [1, 0, 1] if d == 2 else [1, 1, 1, 0, 0, 0]
+    for c in range(nc):
+        assert np.allclose(st["h"][:, c, :], diag[c] * w, rtol=0, atol=2e-15)
+        assert np.allclose(st0["h"][:, c, :], diag[c] * w, rtol=0, atol=3e-16)
+
+
+@pytest.mark.parametrize("d,shape,walls,force", [
+    (2, (8, 8), (0, 0, 0), O.FORCE_FOUR_ROLL),
+    (2, (8, 6), (0, 1, 0), O.FORCE_CONST),
+    (3, (4, 5, 6), (0, 0, 1), O.FORCE_CONST)])
+def test_mass_recurrence(d, shape, walls, force):
+    # M = sum over nodes and directions of f obeys M' = (1 - 1/tau_f) M
+    # because f^eq, f^B and F_i all have zero sum (Sec. 2.2) and streaming
+    # (periodic or bounce-back) permutes populations.
+    s = make(d, shape, walls=walls)
+    s.set_force(force, (1e-5, -2e-5, 3e-6))
+    u, tau, p = smooth_fields(d, shape, 1)
+    s.init(u, tau, p)
+    st = s.get_state()
+    f = st["f"].copy()
+    f[:, 0] += 1e-3          # give the state a mass
+    s.set_state(f=f)
+    M = f.sum()
+    for _ in range(5):
+        s.step(1)
+        M2 = s.get_state()["f"].sum()
+        assert M2 == pytest.approx((1 - 1 / s.tau_f) * M, rel=1e-11)
+        M = M2
+
+
+@pytest.mark.parametrize("d,shape,force", [(2, (8, 8), O.FORCE_FOUR_ROLL),
+                                           (2, (6, 10), O.FORCE_CONST),
+                                           (3, (4, 4, 6), O.FORCE_CONST)])
+def test_momentum_budget_periodic(d, shape, force):
+    # P = sum c_i f_i over the lattice obeys P' = P + sum_x F(x, t) on a
+    # periodic lattice: f^B has zero first moment and the Guo term adds
+    # (1 - 1/2tau_f) F on top of the F/2 carried by u.
+    c = C2 if d == 2 else C3
+    s = make(d, shape)
+    s.set_force(force, (2e-5, -1e-5, 5e-6))
+    u, tau, p = smooth_fields(d, shape, 2)
+    s.init(u, tau, p)
+    for _ in range(5):
+        P = s.get_state()["f"] @ c
+        F = s.force_field().sum(0)
+        s.step(1)
+        P2 = s.get_state()["f"] @ c
+        assert np.allclose(P2.sum(0), P.sum(0) + F, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("d,shape", [(2, (8, 8)), (3, (4, 4, 4))])
+def test_conformation_budget_periodic(d, shape):
+    # sum_i h*_i = A + chi + (chi - chi_prev)/2 (Sec. 2.3), and streaming
+    # conserves it; chi(t) is what the oracle stores as chi_prev after a step.
+    s = make(d, shape)
+    u, tau, p = smooth_fields(d, shape, 3, amp_tau=1e-2)
+    s.init(u, tau, p)
+    Atot = s.moments()["A"].sum(0)
+    chi_old = None
+    for n in range(5):
+        s.step(1)
+        chi = s.get_state()["chi_prev"].sum(0)
+        dchi = 0.0 if chi_old is None else chi - chi_old
+        A2 = s.moments()["A"].sum(0)
+        assert np.allclose(A2, Atot + chi + 0.5 * dchi, rtol=1e-12, atol=1e-13)
+        Atot, chi_old = A2, chi
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_uniform_stress_recurrence(d):
+    # Uniform polymer stress, fluid at rest, no force: u stays 0 up to the
+    # rounding of the first-moment sum (f^B is even under c -> -c), and
+    # e = A - I follows the discrete
+    # recurrence e1 = e0 (1 - 1/lam), e_{n+1} = e_n - e_n/lam - (e_n - e_{n-1})/(2 lam).
+    shape = (5, 4) if d == 2 else (3, 4, 5)
+    lam, eta_p = 7.0, 0.3
+    s = make(d, shape, lam=lam, eta_p=eta_p)
+    nc = 3 if d == 2 else 6
+    N = int(np.prod(shape))
+    tau0 = np.tile(np.linspace(0.01, 0.06, nc), (N, 1))
+    s.init(None, tau0, None)
+    e_prev, e = None, lam * tau0[0] / eta_p
+    diag = np.array([1, 0, 1] if d == 2 else [1, 1, 1, 0, 0, 0], float)
+    for n in range(20):
+        s.step(1)
+        m = s.moments()
+        assert np.abs(m["u"]).max() < 1e-17
+        e_next = e * (1 - 1 / lam) if e_prev is None else e - e / lam - (e - e_prev) / (2 * lam)
+        assert np.allclose(m["A"] - diag, e_next, rtol=1e-12, atol=1e-15)
+        e_prev, e = e, e_next
+
+
+def rot90_2d(u, tau, ny, nx):
+    """Rotate 2D fields by +90 degrees about the grid centre on a square
+    periodic grid: (x, y) -> (-y, x), vectors and tensors rotate too."""
+    U = u.reshape(ny, nx, 2)
+    T = tau.reshape(ny, nx, 3)
+    # new[y', x'] = old at (x, y) with x' = -y, y' = x  ->  old[y = -x', x = y']
+    idx_y = (-np.arange(nx)) % nx
+    Un = np.empty_like(U)
+    Tn = np.empty_like(T)
+    for yp in range(ny):
+        for xp in range(nx):
+            ou = U[(-xp) % ny, yp]
+            ot = T[(-xp) % ny, yp]
+            Un[yp, xp] = [-ou[1], ou[0]]
+            # R A R^T with R = [[0,-1],[1,0]]: xx' = yy, xy' = -xy, yy' = xx
+            Tn[yp, xp] = [ot[2], -ot[1], ot[0]]
+    return Un.reshape(-1, 2), Tn.reshape(-1, 3)
+
+
+def test_rotation_equivariance_2d():
+    n = 8
+    u, tau, p = smooth_fields(2, (n, n), 4, amp_tau=1e-2)
+    a = make(2, (n, n))
+    a.init(u, tau, p)
+    ur, tr = rot90_2d(u, tau, n, n)
+    pr = p.reshape(n, n)[[(-xp) % n for xp in range(n)], :].T.copy().reshape(-1)
+    # pressure is a scalar: p'[y', x'] = p[y=-x', x=y']
+    P = p.reshape(n, n)
+    pr = np.array([[P[(-xp) % n, yp] for xp in range(n)] for yp in range(n)]).reshape(-1)
+    b = make(2, (n, n))
+    b.init(ur, tr, pr)
+    a.step(6)
+    b.step(6)
+    ma, mb = a.moments(), b.moments()
+    ur2, tr2 = rot90_2d(ma["u"], ma["tau"], n, n)
+    assert np.allclose(mb["u"], ur2, atol=1e-15)
+    assert np.allclose(mb["tau"], tr2, atol=1e-16)
+
+
+def test_mirror_equivariance_channel():
+    # walls in y: mirroring y -> L - y flips u_y, tau_xy
+    nx, ny = 6, 8
+    u, tau, p = smooth_fields(2, (ny, nx), 5, amp_tau=1e-2)
+    a = make(2, (ny, nx), walls=(0, 1, 0))
+    a.set_force(O.FORCE_CONST, (1e-5, 0.0, 0.0))
+    a.init(u, tau, p)
+
+    def mirror(u, tau, p):
+        U = u.reshape(ny, nx, 2)[::-1].copy()
+        U[..., 1] *= -1
+        T = tau.reshape(ny, nx, 3)[::-1].copy()
+        T[..., 1] *= -1
+        return U.reshape(-1, 2), T.reshape(-1, 3), p.reshape(ny, nx)[::-1].reshape(-1)
+
+    b = make(2, (ny, nx), walls=(0, 1, 0))
+    b.set_force(O.FORCE_CONST, (1e-5, 0.0, 0.0))
+    b.init(*mirror(u, tau, p))
+    a.step(9)
+    b.step(9)
+    ma, mb = a.moments(), b.moments()
+    um, tm, pm = mirror(ma["u"], ma["tau"], ma["p"])
+    assert np.allclose(mb["u"], um, atol=1e-16)
+    assert np.allclose(mb["tau"], tm, atol=1e-17)
+    assert np.allclose(mb["p"], pm, atol=1e-16)
+
+
+def test_translation_equivariance_3d():
+    shape = (4, 5, 6)
+    u, tau, p = smooth_fields(3, shape, 6, amp_tau=1e-2)
+    a = make(3, shape)
+    a.init(u, tau, p)
+
+    def shift(x, k):
+        X = x.reshape(shape + x.shape[1:])
+        return np.roll(X, 1, axis=k).reshape(x.shape)
+
+    b = make(3, shape)
+    b.init(shift(u, 0), shift(tau, 0), shift(p, 0))
+    a.step(3)
+    b.step(3)
+    ma, mb = a.moments(), b.moments()
+    assert np.allclose(mb["u"], shift(ma["u"], 0), atol=1e-16)
+    assert np.allclose(mb["tau"], shift(ma["tau"], 0), atol=1e-17)
+
+
+# ------------------------------------------------------ brute force (route 2)
+def brute_step(d, shape, walls, st, prm, F, t):
+    """One step written as tensor contractions over the velocity set, with
+    f^B from a library pseudo-inverse and streaming by array rolls.
+    Arrays: f[N,q], h[N,nc,q]."""
+    c = C2 if d == 2 else C3
+    w = weights(d)
+    q = len(c)
+    comps = [(0, 0), (0, 1), (1, 1)] if d == 2 else \
+        [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    nc = len(comps)
+    N = int(np.prod(shape))
+    tf, th, lam, eta = prm
+    f, h = st["f"], st["h"]
+    I = np.eye(d)
+    A = h.sum(-1)
+    Afull = np.zeros((N, d, d))
+    for k, (a, b) in enumerate(comps):
+        Afull[:, a, b] = Afull[:, b, a] = A[:, k]
+    T = eta / lam * (Afull - I)
+    # f^B = pinv(C) b
+    C = constraint_matrix(d)
+    pairs = [(1, 0), (0, 0), (0, 1), (1, 1)] if d == 2 else \
+        [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1)]
+    bvec = np.concatenate([np.stack([-T[:, a, b] / tf for a, b in pairs], -1),
+                           np.zeros((N, 1 + d))], -1)
+    fB = bvec @ np.linalg.pinv(C).T
+    u = np.einsum("ni,ia->na", f, c) + 0.5 * F
+    cc = np.einsum("ia,ib->iab", c, c) - CS2 * I
+    Fi = w * (1 - 0.5 / tf) * (np.einsum("ia,na->ni", c, F) / CS2 +
+                               np.einsum("nab,iab->ni", np.einsum("na,nb->nab", F, u)
+                                         + np.einsum("na,nb->nab", u, F), cc) / (2 * CS2 ** 2))
+    lam_i = w / CS2
+    lam_i[0] = (w[0] - 1) / CS2
+    s0 = w[0] * (-1.5 * (u * u).sum(-1))
+    p = CS2 / (1 - w[0]) * (f[:, 1:].sum(-1) + s0 + tf * Fi[:, 0] + tf * fB[:, 0])
+    feq = lam_i * p[:, None] + w * (np.einsum("ia,na->ni", c, u) / CS2 +
+                                    np.einsum("nab,iab->ni", np.einsum("na,nb->nab", u, u), cc)
+                                    / (2 * CS2 ** 2))
+    fp = f - (f - feq) / tf + fB + Fi
+    # gradient G[n,a,b] = d_a u_b
+    U = u.reshape(shape + (d,))
+    G = np.zeros(shape + (d, d))
+    for a in range(d):
+        ax = (d - 1) - a          # array axis of spatial axis a (x fastest)
+        up = np.roll(U, -1, axis=ax)
+        um = np.roll(U, 1, axis=ax)
+        g = 0.5 * (up - um)
+        if walls[a]:
+            sl0 = [slice(None)] * d
+            sl1 = [slice(None)] * d
+            sl0[ax], sl1[ax] = 0, 1
+            g[tuple(sl0)] = U[tuple(sl0)] + U[tuple(sl1)] / 3
+            sl0[ax], sl1[ax] = -1, -2
+            g[tuple(sl0)] = -(U[tuple(sl0)] + U[tuple(sl1)] / 3)
+        G[..., a, :] = g
+    G = G.reshape(N, d, d)
+    chi_full = -(Afull - I) / lam + Afull @ G + np.transpose(G, (0, 2, 1)) @ Afull
+    chi = np.stack([chi_full[:, a, b] for a, b in comps], -1)
+    cu = np.einsum("ia,na->ni", c, u)
+    cup = np.einsum("ia,na->ni", c, st["u_prev"])
+    k = 1 - 0.5 / th
+    chii = w * chi[:, :, None] * (1 + k * cu[:, None, :] / CS2)
+    chip = w * st["chi_prev"][:, :, None] * (1 + k * cup[:, None, :] / CS2)
+    heq = w * A[:, :, None] * (1 + cu[:, None, :] / CS2)
+    dchi = 0.0 if t == 0 else chii - chip
+    hp = h - (h - heq) / th + chii + 0.5 * dchi
+    # streaming
+    opp = [int(np.where((c == -c[i]).all(1))[0][0]) for i in range(q)]
+    fq = fp.reshape(shape + (q,))
+    hq = hp.reshape(shape + (nc, q))
+    fn = np.zeros_like(fq)
+    hn = np.zeros_like(hq)
+    coords = np.stack(np.meshgrid(*[np.arange(n) for n in shape], indexing="ij"), -1)
+    for i in range(q):
+        fn[..., i] = fq[..., i]
+        hn[..., :, i] = hq[..., :, i]
+        rolled_f = fq[..., i]
+        rolled_h = hq[..., :, i]
+        for a in range(d):
+            ax = (d - 1) - a
+            rolled_f = np.roll(rolled_f, int(c[i, a]), axis=ax)
+            rolled_h = np.roll(rolled_h, int(c[i, a]), axis=ax)
+        # the arriving population at x came from x - c_i; it crossed a wall
+        # if x - c_i lies outside on a wall axis -> take own opposite
+        bounce = np.zeros(shape, bool)
+        for a in range(d):
+            if walls[a]:
+                ax = (d - 1) - a
+                src = coords[..., ax] - int(c[i, a])
+                bounce |= (src < 0) | (src >= shape[ax])
+        fn[..., i] = np.where(bounce, fq[..., opp[i]], rolled_f)
+        hn[..., :, i] = np.where(bounce[..., None], hq[..., :, opp[i]], rolled_h)
+    return dict(f=fn.reshape(N, q), h=hn.reshape(N, nc, q), chi_prev=chi, u_prev=u)
+
+
+@pytest.mark.parametrize("d,shape,walls,force", [
+    (2, (8, 8), (0, 0, 0), O.FORCE_FOUR_ROLL),
+    (2, (8, 8), (0, 1, 0), O.FORCE_CONST),
+    (2, (7, 5), (1, 1, 0), O.FORCE_CONST),
+    (3, (4, 5, 6), (0, 0, 0), O.FORCE_NONE),
+    (3, (4, 5, 6), (1, 0, 1), O.FORCE_CONST)])
+def test_brute_force_steps(d, shape, walls, force):
+    prm = (0.73, 0.501, 40.0, 0.07)
+    s = make(d, shape, *prm, walls=walls)
+    s.set_force(force, (3e-5, -2e-5, 1e-5))
+    u, tau, p = smooth_fields(d, shape, 7, amp_tau=2e-2)
+    s.init(u, tau, p)
+    st = s.get_state()
+    for t in range(3):
+        F = s.force_field(t)
+        st = brute_step(d, shape, walls, st, prm, F, t)
+        s.step(1)
+        so = s.get_state()
+        # agreement to rounding (the inputs reach O(10), the entries O(1e-2))
+        for key in ("f", "h", "chi_prev"):
+            scale = max(1e-3, np.abs(st[key]).max())
+            assert np.abs(so[key] - st[key]).max() <= 2e-14 * scale, (t, key)
