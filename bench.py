@@ -1,0 +1,160 @@
+"""Throughput of the fused fluctuating-LB step on one MI355X.
+
+Workload: planar Poiseuille channel, D2Q9, 8192 x 1024 nodes, periodic in x,
+halfway bounce-back walls in y, constant body force g = 8 nu U0 / L^2,
+Re = 30.72 (U0 = 0.01, L = 1024, tau_f = 1 at beta = 0.5), Wi = 1,
+FP32 arithmetic with FP32 population storage; the fluid starts at rest
+(synthetic input, no dataset).  One step is one fused stream-and-collide
+launch over the whole lattice; the FP64 residual/conservation reduction runs
+every 100 steps inside the timed region as in a production run.
+
+Prints one JSON line: MLUPS (whole job), the roofline of the step kernel
+(algorithmic bytes per lattice update / measured kernel time, against the
+8 TB/s HBM peak) and the CPU oracle timed on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NX, NY = 8192, 1024
+RE, WI, BETA, U0, L = 30.72, 1.0, 0.5, 0.01, 1024.0
+REDUCE_EVERY = 100
+
+
+def bytes_per_lup(d, storage):
+    """Algorithmic HBM bytes per lattice update: every f and h population
+    read once and written once, plus chi(t-1) and u(t-1) read and written."""
+    q, nc = (9, 3) if d == 2 else (19, 6)
+    sb = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[storage]
+    ab = 8 if storage == "f64" else 4
+    return 2 * q * (1 + nc) * sb + 2 * (nc + d) * ab
+
+
+def run_gpu(steps, warmup, storage="f32"):
+    import torch
+    from paper_2506_13072_amd import vflb
+    g = vflb.Sim(2, NX, NY, 1, storage)
+    g.set_params(RE, WI, BETA, U0, L)
+    g.set_boundaries((vflb.PERIODIC, vflb.WALLS))
+    lp = g.lattice_params()
+    nu = lp["nu_s"] + lp["nu_p"]
+    g.set_force(vflb.FORCE_CONST, (8 * nu * U0 / L ** 2, 0.0, 0.0))
+    g.init_fields()
+    g.step(1)
+    done = 1
+    while done < warmup:
+        n = min(REDUCE_EVERY, warmup - done)
+        g.step(n)
+        done += n
+    g.reduce()
+    g.synchronize()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(g.stream)
+    red_ms = 0.0
+    left = steps
+    while left > 0:
+        n = min(REDUCE_EVERY, left)
+        g.step(n)
+        left -= n
+        if left > 0 or n == REDUCE_EVERY:
+            r0 = torch.cuda.Event(enable_timing=True)
+            r1 = torch.cuda.Event(enable_timing=True)
+            r0.record(g.stream)
+            r = g.reduce()
+            r1.record(g.stream)
+            r1.synchronize()
+            red_ms += r0.elapsed_time(r1)
+    e1.record(g.stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = e0.elapsed_time(e1)
+    step_ms = (total_ms - red_ms) / steps
+    return dict(total_ms=total_ms, step_ms=step_ms, red_ms=red_ms, wall=wall,
+                R=r["R"], nonfinite=r["nonfinite"])
+
+
+def run_cpu_baseline(budget_s=15.0):
+    """The FP64 oracle, single-threaded, on a 256 x 128 copy of the channel
+    (the size of the paper's own timing table) with the same lattice-unit
+    parameters except the width; steps until about budget_s of work."""
+    from oracle import oracle as O
+    nx, ny = 256, 128
+    p = O.lattice_params(RE, WI, BETA, U0, L)
+    o = O.OracleSim(2, nx, ny)
+    o.set_params(p["tau_f"], 0.501, p["lam"], p["eta_p"])
+    o.set_walls((0, 1, 0))
+    nu = p["nu_s"] + p["nu_p"]
+    o.set_force(O.FORCE_CONST, (8 * nu * U0 / L ** 2, 0.0, 0.0))
+    o.init()
+    o.step(5)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        o.step(10)
+        n += 10
+    dt = time.perf_counter() - t0
+    return dict(value=nx * ny * n / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"D2Q9 {nx}x{ny} channel, same lattice parameters, {n} steps, "
+                       f"FP64, single thread, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "bf16s", "f64"])
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is not built)", file=sys.stderr)
+        sys.exit(2)
+    res = run_gpu(args.steps, args.warmup, args.storage)
+    nodes = NX * NY
+    mlups = nodes * args.steps / (res["total_ms"] / 1e3) / 1e6
+    bpl = bytes_per_lup(2, args.storage)
+    achieved = bpl * nodes / (res["step_ms"] / 1e3) / 1e9
+    out = {
+        "metric": "MLUPS (fused stream-collide, D2Q9 Oldroyd-B fluctuating LB)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["total_ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage != "f64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "Poiseuille channel D2Q9 8192x1024, walls in y, "
+                               "const force, Re=30.72 Wi=1 beta=0.5",
+                   "storage": args.storage, "nodes": nodes,
+                   "reduce_every": REDUCE_EVERY},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_lup": bpl,
+                     "kernel_ms": round(res["step_ms"], 5)},
+        "residual": res["R"],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = run_cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * vflb.h -- C ABI of libvflb, the MI355X (gfx950) implementation of the
+ * fluctuating lattice Boltzmann method for Oldroyd-B viscoelastic flows
+ * (Wang, Liu, Wang, Yu, Ji, arXiv 2506.13072).
+ *
+ * One time step of the method on a D2Q9 or D3Q19 lattice, fused into a
+ * single pass over the populations:
+ *   - pull streaming of the velocity populations f_i and the conformation
+ *     populations h_abi (left-hand sides of the evolution equations of
+ *     Sec. 2.2 and Sec. 2.3), periodic or halfway bounce-back;
+ *   - moments: A = sum_i h_abi (Sec. 2.3), tau_p = (mu_p/lambda)(A - I)
+ *     (Sec. 2.1), u = sum c_i f_i + F/2 and the pressure (Sec. 2.2, App. B);
+ *   - the polymer-stress fluctuation term f^B from the pseudo-inverse
+ *     closed forms (Sec. 2.2 for D2Q9, App. A for D3Q19);
+ *   - the BGK collision with f^eq, the Guo forcing term and f^B (Sec. 2.2);
+ *   - the Oldroyd-B source chi = -(A - I)/lambda + A.grad u + grad u^T.A
+ *     from the velocity gradient at the same time level, its distribution
+ *     chi_abi and the collision of h with tau_h (Sec. 2.3).
+ *
+ * Conventions.
+ *   - C linkage only; every call returns a vflb_status.  A failing call
+ *     leaves the simulation unchanged and records a message readable with
+ *     vflb_last_error().
+ *   - Device memory is owned by the caller.  vflb_query_buffers() reports
+ *     the sizes of the VFLB_NBUF device buffers a simulation needs; the
+ *     caller allocates them (any allocator, 256-byte aligned) and hands
+ *     them over with vflb_bind_buffers().  The library never frees them.
+ *     Handles and small host-side metadata are owned by the library.
+ *   - Work is enqueued on the HIP stream given at creation, in call order.
+ *     vflb_reduce(), vflb_set_force(), vflb_save() and vflb_load()
+ *     synchronise that stream; every other call only enqueues.
+ *   - Fields are node-major with x fastest: node n = (z*ny + y)*nx + x.
+ *     Symmetric tensors use the component order (xx, xy, yy) in 2D and
+ *     (xx, yy, zz, xy, xz, yz) in 3D.
+ *   - Lattice units: dx = dt = 1, c_s^2 = 1/3, rho0 = 1.
+ */
+#ifndef VFLB_H
+#define VFLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vflb_sim vflb_sim;
+
+typedef enum {
+  VFLB_OK = 0,
+  VFLB_EINVAL = 1,    /* bad argument; nothing was changed            */
+  VFLB_ENOMEM = 2,    /* a buffer is missing or too small             */
+  VFLB_EDEVICE = 3,   /* a HIP call failed                            */
+  VFLB_EUNSTABLE = 4, /* non-finite values found by vflb_reduce       */
+  VFLB_ESTATE = 5     /* call out of order (e.g. step before init)    */
+} vflb_status;
+
+typedef enum { VFLB_D2Q9 = 2, VFLB_D3Q19 = 3 } vflb_lattice;
+
+/* Storage of the populations.  Arithmetic is FP64 for VFLB_F64 and FP32
+ * otherwise.  The conformation populations are stored shifted by their rest
+ * value w_i delta_ab (so A - I is their plain sum); the velocity populations
+ * have rest value 0 in this incompressible model.  VFLB_F16S stores the
+ * shifted values times a power of two (vflb_set_storage_scale), VFLB_BF16S
+ * stores them unscaled; both round to nearest even. */
+typedef enum {
+  VFLB_F64 = 0,
+  VFLB_F32 = 1,
+  VFLB_F16S = 2,
+  VFLB_BF16S = 3
+} vflb_storage;
+
+/* Body force kinds (lattice units):
+ *   NONE       F = 0
+ *   CONST      F = amp
+ *   FOUR_ROLL  F = (amp[0] sin(kx x) cos(ky y), amp[1] cos(kx x) sin(ky y), 0),
+ *              kx = 2 pi/nx, ky = 2 pi/ny, x, y the node indices
+ *              (simplified four-roll mill, Sec. 3.1)
+ *   COS_T      F = amp cos(omega t), t the step index (Womersley, Sec. 3.3)
+ * The force of step t is evaluated at time level t, in the velocity moment
+ * and in the forcing term alike. */
+enum {
+  VFLB_FORCE_NONE = 0,
+  VFLB_FORCE_CONST = 1,
+  VFLB_FORCE_FOUR_ROLL = 2,
+  VFLB_FORCE_COS_T = 3
+};
+
+/* Boundary kind per axis: periodic, or halfway bounce-back walls half a
+ * lattice spacing outside the first and the last node of that axis (for f
+ * and for h alike).  Next to a wall the normal derivative of u uses the
+ * parabola through the wall value 0 and the first two nodes. */
+enum { VFLB_PERIODIC = 0, VFLB_WALLS = 1 };
+
+/* Device buffers of one simulation (sizes from vflb_query_buffers). */
+enum {
+  VFLB_BUF_F0 = 0,  /* f populations, ping              Q*N storage words  */
+  VFLB_BUF_F1 = 1,  /* f populations, pong                                  */
+  VFLB_BUF_H0 = 2,  /* shifted h populations, ping      NC*Q*N words        */
+  VFLB_BUF_H1 = 3,  /* shifted h populations, pong                          */
+  VFLB_BUF_AUX = 4, /* chi(t-1) [NC][N] then u(t-1) [D][N], arithmetic type */
+  VFLB_BUF_SNAP = 5,/* residual snapshot u [D][N], tau [NC][N], arith. type */
+  VFLB_BUF_WORK = 6,/* force tables, reduction partials, step counter       */
+  VFLB_NBUF = 7
+};
+
+/* Read-back fields (vflb_read).  FIELD_U .. FIELD_H are moments of the
+ * pre-collision state at the current time level t, with the force F(t);
+ * CHI_PREV and U_PREV are the auxiliary state kept for the backward
+ * difference of the source term (chi and u of time level t-1). */
+enum {
+  VFLB_FIELD_U = 0,   /* [D][N]  velocity                                  */
+  VFLB_FIELD_P = 1,   /* [N]     pressure (App. B)                         */
+  VFLB_FIELD_RHO = 2, /* [N]     rho0 + p / c_s^2 (the model has no density) */
+  VFLB_FIELD_A = 3,   /* [NC][N] conformation tensor                       */
+  VFLB_FIELD_TAU = 4, /* [NC][N] polymer stress                            */
+  VFLB_FIELD_F = 5,   /* [Q][N]  pre-collision f populations               */
+  VFLB_FIELD_H = 6,   /* [NC][Q][N] pre-collision h populations, unshifted */
+  VFLB_FIELD_CHI_PREV = 7, /* [NC][N] stored source tensor of the last step */
+  VFLB_FIELD_U_PREV = 8    /* [D][N]  stored velocity of the last step      */
+};
+
+/* Dimensionless parameters (Sec. 3): beta = nu_s/(nu_s + nu_p),
+ * Wi = lambda U/L, Re = U L/(nu_s + nu_p).  Mapped to lattice units as
+ * nu = U0 L / Re, nu_s = beta nu, nu_p = (1 - beta) nu,
+ * tau_f = nu_s/c_s^2 + 1/2 (Sec. 2.2), lambda = Wi L / U0 unless
+ * lambda > 0 is given, eta_p = nu_p.  tau_h <= 0 selects the paper's 0.501.
+ * Valid: Re > 0, U0 > 0, L > 0, 0 < beta <= 1, tau_f > 1/2, tau_h > 1/2,
+ * lambda > 0.  beta = 1 is the Newtonian limit (eta_p = 0, f^B = 0). */
+typedef struct {
+  double Re, Wi, beta, U0, L;
+  double lambda; /* > 0 overrides Wi L / U0 */
+  double tau_h;  /* <= 0: 0.501             */
+} vflb_params;
+
+/* Derived lattice-unit parameters (vflb_get_lattice_params). */
+typedef struct {
+  double nu_s, nu_p, tau_f, tau_h, lambda, eta_p;
+} vflb_lattice_params;
+
+/* Create a simulation of nx*ny*nz nodes (nz = 1 for D2Q9) whose work is
+ * enqueued on hip_stream (a hipStream_t; NULL is the null stream).
+ * *out receives a library-owned handle.  EINVAL for a bad lattice, storage
+ * or size. */
+vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
+                        void *hip_stream, vflb_sim **out);
+
+/* Sizes in bytes of the VFLB_NBUF device buffers. */
+vflb_status vflb_query_buffers(const vflb_sim *sim, size_t bytes[VFLB_NBUF]);
+
+/* Hand over the caller-owned device buffers (one pointer per buffer, each at
+ * least the queried size).  EINVAL on a NULL pointer. */
+vflb_status vflb_bind_buffers(vflb_sim *sim, void *const dev_ptrs[VFLB_NBUF]);
+
+/* Set the physical parameters (see vflb_params).  EINVAL when the derived
+ * lattice parameters are out of range. */
+vflb_status vflb_set_params(vflb_sim *sim, const vflb_params *p);
+
+/* Lattice-unit parameters derived by vflb_set_params. */
+vflb_status vflb_get_lattice_params(const vflb_sim *sim,
+                                    vflb_lattice_params *out);
+
+/* Set the body force (kind and lattice-unit amplitude amp[3]; omega for
+ * COS_T).  Needs bound buffers (the four-roll tables live in the work
+ * buffer).  EINVAL for an unknown kind.  FOUR_ROLL on D3Q19 is the same
+ * z-independent field. */
+vflb_status vflb_set_force(vflb_sim *sim, int kind, const double amp[3],
+                           double omega);
+
+/* Boundary kind per axis (VFLB_PERIODIC or VFLB_WALLS); a wall axis needs
+ * at least 2 nodes. */
+vflb_status vflb_set_boundaries(vflb_sim *sim, const int kind_per_axis[3]);
+
+/* Power-of-two scales of the VFLB_F16S storage: f is stored as
+ * f * 2^log2_f, the shifted h as (h - w delta) * 2^log2_h.  Defaults are
+ * chosen from U0 by vflb_set_params.  Ignored for other storages. */
+vflb_status vflb_set_storage_scale(vflb_sim *sim, int log2_f, int log2_h);
+
+/* Equilibrium-only initial state from FP64 device fields u [D][N],
+ * tau [NC][N] (polymer stress) and p [N]; NULL means zero.  Sets
+ * f = f^eq(p, u), h = h^eq(A, u) with A = I + lambda tau / eta_p, and the
+ * time level t = 0.  Needs bound buffers and parameters. */
+vflb_status vflb_init_fields(vflb_sim *sim, const double *u_dev,
+                             const double *tau_dev, const double *p_dev);
+
+/* Advance nsteps >= 0 time steps (nsteps fused stream-collide launches,
+ * replayed from a captured HIP graph when nsteps is large). */
+vflb_status vflb_step(vflb_sim *sim, int64_t nsteps);
+
+/* Current time level (host copy; no synchronisation). */
+int64_t vflb_time(const vflb_sim *sim);
+
+/* FP64 reductions over the pre-collision state at time t (synchronises):
+ *   out[0]  R: max over q in {u, tau} of ||q - q_snap||_2 / ||q||_2, where
+ *           q_snap is the state at the previous vflb_reduce call (+inf on
+ *           the first call); the snapshot is then replaced
+ *   out[1]  M  = sum of all f (stays 0 from an equilibrium start)
+ *   out[2..4] P = sum of c_i f_i (x, y, z)
+ *   out[5]  KE = (1/N) sum |u|^2 / 2,  out[6] PE = (1/N) sum tr(tau)/2
+ *           (Sec. 3.4)
+ *   out[7]  number of nodes with a non-finite moment
+ *   out[8..13] sum over nodes of the NC components of A
+ * Returns VFLB_EUNSTABLE when out[7] > 0 (out is still filled). */
+vflb_status vflb_reduce(vflb_sim *sim, double out[14]);
+
+/* Write a read-back field (VFLB_FIELD_*) as FP64 into the caller's device
+ * array of n doubles (n must equal the field size). */
+vflb_status vflb_read(vflb_sim *sim, int field, double *dev_dst, size_t n);
+
+/* Checkpoint: vflb_state_size() bytes describe the full state (populations,
+ * auxiliary fields, time level).  vflb_save copies it into a caller device
+ * blob, vflb_load restores it (same lattice, size and storage). */
+vflb_status vflb_state_size(const vflb_sim *sim, size_t *bytes);
+vflb_status vflb_save(vflb_sim *sim, void *dev_blob, size_t n);
+vflb_status vflb_load(vflb_sim *sim, const void *dev_blob, size_t n);
+
+/* Block height of the D2Q9 step kernel (tile 64 x tile_y, tile_y in
+ * {1, 2, 4, 8}); 0 restores the built-in choice.  Results do not
+ * depend on it. */
+vflb_status vflb_set_tile(vflb_sim *sim, int tile_y);
+
+/* Release the handle (not the caller's buffers). */
+void vflb_destroy(vflb_sim *sim);
+
+/* Message of the last failed call on sim (or of the last failed
+ * vflb_create when sim is NULL); never NULL. */
+const char *vflb_last_error(const vflb_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VFLB_H */

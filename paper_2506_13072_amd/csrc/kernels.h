@@ -1,0 +1,515 @@
+// kernels.h -- HIP kernels of the fused fluctuating-LB step for gfx950.
+//
+// Data layout in HBM (structure of arrays, x fastest, N nodes):
+//   f  [Q][N]            velocity populations, post-collision of the last
+//                        step (pull scheme: streaming happens on the read)
+//   h  [NC][Q][N]        conformation populations minus w_i delta_ab
+//   aux[NC][N] + [D][N]  chi(t-1) and u(t-1) for the backward difference of
+//                        the source term; read and written in place by the
+//                        owning node only
+// The step kernel pulls f and h, forms the moments, collides f (Sec. 2.2),
+// builds u on a tile plus a one-node halo in LDS for the same-time
+// velocity gradient, then forms the Oldroyd-B source and collides h
+// (Sec. 2.3).  f and h are written to the other buffer of a ping-pong pair.
+#pragma once
+
+#include "lattice.h"
+
+namespace vflb {
+
+enum { FORCE_NONE = 0, FORCE_CONST = 1, FORCE_FOUR_ROLL = 2, FORCE_COS_T = 3 };
+
+struct Geo {
+  int nx, ny, nz;
+  int walls;  // bit a: halfway bounce-back walls on axis a
+  size_t N;
+};
+
+template <class R> struct ForceArgs {
+  int kind;
+  R F0[3];        // uniform force (CONST, COS_T at this time level)
+  R amp[2];       // FOUR_ROLL amplitudes
+  const R* tab;   // FOUR_ROLL tables: sin(kx x)[nx], cos(kx x)[nx], sin(ky y)[ny], cos(ky y)[ny]
+};
+
+template <class S> struct StepArgs {
+  using R = typename StoreT<S>::R;
+  const S* fin;
+  S* fout;
+  const S* hin;
+  S* hout;
+  R* aux;
+  Geo g;
+  Phys<R> P;
+  ForceArgs<R> F;
+  R sf, inv_sf, sh, inv_sh;  // storage scales (1 unless FP16)
+  int first;                 // t == 0: no previous source term
+};
+
+__device__ inline size_t node_of(int x, int y, int z, const Geo& g) {
+  return ((size_t)z * g.ny + y) * g.nx + x;
+}
+
+// Index of the post-collision value that streams into direction i of node
+// (x, y, z): population i at x - c_i (periodic wrap), or population
+// opp(i) at the node itself when x - c_i lies beyond a wall (halfway
+// bounce-back).  The returned index includes the plane offset.
+template <int D>
+__device__ inline size_t pull_index(int i, int x, int y, int z, const Geo& g) {
+  int s[3] = {x - cdir<D>(i, 0), y - cdir<D>(i, 1), z - cdir<D>(i, 2)};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  bool bounce = false;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (cdir<D>(i, a) != 0 && (s[a] < 0 || s[a] >= n[a])) {
+      if (g.walls & (1 << a))
+        bounce = true;
+      else
+        s[a] = s[a] < 0 ? n[a] - 1 : 0;
+    }
+  }
+  if (bounce) return (size_t)Lat<D>::opp(i) * g.N + node_of(x, y, z, g);
+  return (size_t)i * g.N + node_of(s[0], s[1], s[2], g);
+}
+
+template <class R>
+__device__ inline void force_at(const ForceArgs<R>& fa, int x, int y, int nx,
+                                int ny, R* F) {
+  F[0] = F[1] = F[2] = 0;
+  if (fa.kind == FORCE_CONST || fa.kind == FORCE_COS_T) {
+    F[0] = fa.F0[0];
+    F[1] = fa.F0[1];
+    F[2] = fa.F0[2];
+  } else if (fa.kind == FORCE_FOUR_ROLL) {
+    const R* sx = fa.tab;
+    const R* cx = fa.tab + nx;
+    const R* sy = fa.tab + 2 * nx;
+    const R* cy = fa.tab + 2 * nx + ny;
+    F[0] = fa.amp[0] * sx[x] * cy[y];
+    F[1] = fa.amp[1] * cx[x] * sy[y];
+  }
+}
+
+// Wrap a coordinate that may lie outside [0, n) by at most one tile: for a
+// wall axis the point is outside the fluid (returns false).
+__device__ inline bool wrap_coord(int& c, int n, bool wall) {
+  if (c >= 0 && c < n) return true;
+  if (wall) return false;
+  c = ((c % n) + n) % n;
+  return true;
+}
+
+// --------------------------------------------------------------- step
+template <int D, class S, int MAXT>
+__global__ void __launch_bounds__(MAXT) step_kernel(StepArgs<S> a) {
+  using St = StoreT<S>;
+  using R = typename St::R;
+  using L = Lat<D>;
+  constexpr int Q = L::Q, NC = L::NC;
+  extern __shared__ unsigned char smem_raw[];
+  R* su = reinterpret_cast<R*>(smem_raw);
+
+  const Geo& g = a.g;
+  const int TX = blockDim.x, TY = blockDim.y, TZ = blockDim.z;
+  const int SX = TX + 2, SY = TY + 2, SZ = (D == 3) ? TZ + 2 : 1;
+  const int nslot = SX * SY * SZ;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
+  const int tid = (tz * TY + ty) * TX + tx;
+  const int nthr = TX * TY * TZ;
+  const int x = x0 + tx, y = y0 + ty, z = (D == 3) ? z0 + tz : 0;
+  const bool active = x < g.nx && y < g.ny && z < g.nz;
+  const int slot = (((D == 3) ? tz + 1 : 0) * SY + ty + 1) * SX + tx + 1;
+
+  // node whose velocity this thread places in its own slot (ragged tails
+  // wrap periodically so that the last nodes see their true neighbours)
+  int wx = x, wy = y, wz = z;
+  bool valid = wrap_coord(wx, g.nx, g.walls & 1) && wrap_coord(wy, g.ny, g.walls & 2);
+  if (D == 3) valid = valid && wrap_coord(wz, g.nz, g.walls & 4);
+
+  R f[Q];
+  R h[NC][Q];
+  R chip[NC], up[3] = {0, 0, 0};
+  size_t idx[Q];
+  const size_t n = active ? node_of(x, y, z, g) : 0;
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      idx[i] = pull_index<D>(i, wx, wy, wz, g);
+      f[i] = St::ld(a.fin, idx[i], a.inv_sf);
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        h[c][i] = St::ld(a.hin, (size_t)c * Q * g.N + idx[i], a.inv_sh);
+    if (!a.first) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) chip[c] = a.aux[(size_t)c * g.N + n];
+#pragma unroll
+      for (int b = 0; b < D; ++b) up[b] = a.aux[(size_t)(NC + b) * g.N + n];
+    }
+  }
+
+  R u[3] = {0, 0, 0}, F[3];
+  R e[NC];
+  if (valid) {
+    force_at<R>(a.F, wx, wy, g.nx, g.ny, F);
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      R s = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (cdir<D>(i, b) != 0) s += (R)cdir<D>(i, b) * f[i];
+      u[b] = s + (R)0.5 * F[b];
+      su[b * nslot + slot] = u[b];
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      R s = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s += h[c][i];
+      e[c] = s;
+    }
+    collide_f<D, R>(f, e, u, F, a.P);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) St::st(a.fout, (size_t)i * g.N + n, f[i], a.sf);
+  }
+
+  // velocity on the halo slots of the tile
+  for (int s = tid; s < nslot; s += nthr) {
+    const int hx = s % SX, hy = (s / SX) % SY, hz = s / (SX * SY);
+    const bool inner = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY &&
+                       (D == 2 || (hz >= 1 && hz <= TZ));
+    if (inner) continue;
+    int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = (D == 3) ? z0 + hz - 1 : 0;
+    bool ok = wrap_coord(gx, g.nx, g.walls & 1) && wrap_coord(gy, g.ny, g.walls & 2);
+    if (D == 3) ok = ok && wrap_coord(gz, g.nz, g.walls & 4);
+    if (!ok) continue;
+    R Fh[3];
+    force_at<R>(a.F, gx, gy, g.nx, g.ny, Fh);
+    R fh[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) fh[i] = St::ld(a.fin, pull_index<D>(i, gx, gy, gz, g), a.inv_sf);
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      R sm = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (cdir<D>(i, b) != 0) sm += (R)cdir<D>(i, b) * fh[i];
+      su[b * nslot + s] = sm + (R)0.5 * Fh[b];
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+
+  // same-time velocity gradient G[a][b] = d_a u_b
+  R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  const int coord[3] = {x, y, z};
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  const int stride[3] = {1, SX, SX * SY};
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    const bool wall = g.walls & (1 << ax);
+    const bool lo = wall && coord[ax] == 0;
+    const bool hi = wall && coord[ax] == nn[ax] - 1;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      const R* ub = su + b * nslot + slot;
+      R d;
+      if (lo)
+        d = u[b] + ub[stride[ax]] * (R)(1.0 / 3.0);
+      else if (hi)
+        d = -(u[b] + ub[-stride[ax]] * (R)(1.0 / 3.0));
+      else
+        d = (R)0.5 * (ub[stride[ax]] - ub[-stride[ax]]);
+      G[ax][b] = d;
+    }
+  }
+  R chi[NC];
+  source_tensor<D, R>(e, G, a.P.inv_lam, chi);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const R Ac = e[c] + ((L::ca(c) == L::cb(c)) ? (R)1 : (R)0);
+    collide_h<D, R>(h[c], e[c], Ac, chi[c], chip[c], u, up, a.first != 0, a.P);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      St::st(a.hout, ((size_t)c * Q + i) * g.N + n, h[c][i], a.sh);
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) a.aux[(size_t)c * g.N + n] = chi[c];
+#pragma unroll
+  for (int b = 0; b < D; ++b) a.aux[(size_t)(NC + b) * g.N + n] = u[b];
+}
+
+// --------------------------------------------------- shared node moments
+// Pre-collision moments of one node: pulls f and h, returns u, e = A - I,
+// tau, p and the pulled populations.
+template <int D, class S>
+struct NodeMoments {
+  using R = typename StoreT<S>::R;
+  R f[Lat<D>::Q];
+  R h[Lat<D>::NC][Lat<D>::Q];
+  R u[3], e[Lat<D>::NC], tau[Lat<D>::NC], p;
+};
+
+template <int D, class S>
+__device__ inline void node_moments(const S* fin, const S* hin, int x, int y,
+                                    int z, const Geo& g,
+                                    const Phys<typename StoreT<S>::R>& P,
+                                    const ForceArgs<typename StoreT<S>::R>& fa,
+                                    typename StoreT<S>::R inv_sf,
+                                    typename StoreT<S>::R inv_sh,
+                                    NodeMoments<D, S>& m) {
+  using St = StoreT<S>;
+  using R = typename St::R;
+  using L = Lat<D>;
+  constexpr int Q = L::Q, NC = L::NC;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const size_t id = pull_index<D>(i, x, y, z, g);
+    m.f[i] = St::ld(fin, id, inv_sf);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) m.h[c][i] = St::ld(hin, (size_t)c * Q * g.N + id, inv_sh);
+  }
+  R F[3];
+  force_at<R>(fa, x, y, g.nx, g.ny, F);
+  m.u[2] = 0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    R s = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      if (cdir<D>(i, b) != 0) s += (R)cdir<D>(i, b) * m.f[i];
+    m.u[b] = s + (R)0.5 * F[b];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    R s = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s += m.h[c][i];
+    m.e[c] = s;
+    m.tau[c] = P.eta_over_lam * s;
+  }
+  R fB[Q];
+  fluct_term<R>(m.tau, P.inv_tau_f, fB, (L*)nullptr);
+  R uu = 0, Fu = 0, sum = 0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    uu += m.u[b] * m.u[b];
+    Fu += F[b] * m.u[b];
+  }
+#pragma unroll
+  for (int i = 1; i < Q; ++i) sum += m.f[i];
+  constexpr R w0 = (R)L::w(0);
+  const R F0 = -3 * w0 * P.k_f * Fu;
+  constexpr R pref = (R)((1.0 / 3.0) / (1.0 - L::w(0)));
+  m.p = pref * (sum - (R)1.5 * w0 * uu + P.tau_f * F0 + P.tau_f * fB[0]);
+}
+
+template <int D>
+__device__ inline void node_xyz(size_t n, const Geo& g, int& x, int& y, int& z) {
+  x = (int)(n % g.nx);
+  y = (int)((n / g.nx) % g.ny);
+  z = (int)(n / ((size_t)g.nx * g.ny));
+}
+
+// ------------------------------------------------------------- read-back
+enum { FIELD_U = 0, FIELD_P = 1, FIELD_RHO = 2, FIELD_A = 3, FIELD_TAU = 4,
+       FIELD_F = 5, FIELD_H = 6, FIELD_CHI_PREV = 7, FIELD_U_PREV = 8 };
+
+// copy of the auxiliary state (arithmetic type) to FP64
+template <class R>
+__global__ void __launch_bounds__(256) aux_read_kernel(const R* aux, size_t count,
+                                                       double* out) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (size_t)gridDim.x * blockDim.x)
+    out[k] = (double)aux[k];
+}
+
+template <int D, class S>
+__global__ void __launch_bounds__(256) moments_kernel(
+    const S* fin, const S* hin, Geo g, Phys<typename StoreT<S>::R> P,
+    ForceArgs<typename StoreT<S>::R> fa, typename StoreT<S>::R inv_sf,
+    typename StoreT<S>::R inv_sh, int field, double* out) {
+  using L = Lat<D>;
+  constexpr int Q = L::Q, NC = L::NC;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    node_xyz<D>(n, g, x, y, z);
+    NodeMoments<D, S> m;
+    node_moments<D, S>(fin, hin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
+    switch (field) {
+      case FIELD_U:
+        for (int b = 0; b < D; ++b) out[(size_t)b * g.N + n] = (double)m.u[b];
+        break;
+      case FIELD_P:
+        out[n] = (double)m.p;
+        break;
+      case FIELD_RHO:
+        out[n] = 1.0 + 3.0 * (double)m.p;
+        break;
+      case FIELD_A:
+        for (int c = 0; c < NC; ++c)
+          out[(size_t)c * g.N + n] =
+              (double)m.e[c] + ((L::ca(c) == L::cb(c)) ? 1.0 : 0.0);
+        break;
+      case FIELD_TAU:
+        for (int c = 0; c < NC; ++c) out[(size_t)c * g.N + n] = (double)m.tau[c];
+        break;
+      case FIELD_F:
+        for (int i = 0; i < Q; ++i) out[(size_t)i * g.N + n] = (double)m.f[i];
+        break;
+      case FIELD_H:
+        for (int c = 0; c < NC; ++c)
+          for (int i = 0; i < Q; ++i)
+            out[((size_t)c * Q + i) * g.N + n] =
+                (double)m.h[c][i] + ((L::ca(c) == L::cb(c)) ? L::w(i) : 0.0);
+        break;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ init
+// Equilibrium-only state: f = f^eq(p, u), h = h^eq(A, u) (shifted), with
+// A = I + lambda tau / eta_p; each value is written where the pull of the
+// first step reads it, so that the first step sees exactly this state.
+template <int D, class S>
+__global__ void __launch_bounds__(256) init_kernel(
+    S* fbuf, S* hbuf, typename StoreT<S>::R* aux, Geo g,
+    const double* u_in, const double* tau_in, const double* p_in,
+    double lam_over_eta, typename StoreT<S>::R sf, typename StoreT<S>::R sh) {
+  using St = StoreT<S>;
+  using R = typename St::R;
+  using L = Lat<D>;
+  constexpr int Q = L::Q, NC = L::NC;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    node_xyz<D>(n, g, x, y, z);
+    R u[3] = {0, 0, 0};
+    if (u_in)
+      for (int b = 0; b < D; ++b) u[b] = (R)u_in[(size_t)b * g.N + n];
+    const R p = p_in ? (R)p_in[n] : (R)0;
+    R e[NC];
+    for (int c = 0; c < NC; ++c)
+      e[c] = tau_in ? (R)(lam_over_eta * tau_in[(size_t)c * g.N + n]) : (R)0;
+    R uu = 0;
+    for (int b = 0; b < D; ++b) uu += u[b] * u[b];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R wi = (R)L::w(i);
+      const R lam_i = (R)(i == 0 ? 3.0 * (L::w(0) - 1.0) : 3.0 * L::w(i));
+      const R cu = cdot<D, R>(i, u);
+      const R feq = lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
+      const size_t id = pull_index<D>(i, x, y, z, g);
+      St::st(fbuf, id, feq, sf);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const R Ac = e[c] + ((L::ca(c) == L::cb(c)) ? (R)1 : (R)0);
+        St::st(hbuf, (size_t)c * Q * g.N + id, wi * e[c] + 3 * wi * Ac * cu, sh);
+      }
+    }
+    for (int c = 0; c < NC; ++c) aux[(size_t)c * g.N + n] = 0;
+    for (int b = 0; b < D; ++b) aux[(size_t)(NC + b) * g.N + n] = u[b];
+  }
+}
+
+// ------------------------------------------------------------ reductions
+constexpr int NRED = 17;  // du2 u2 dt2 t2 | M | Px Py Pz | KE PE | nan | A x6
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <int D, class S>
+__global__ void __launch_bounds__(256) reduce_kernel(
+    const S* fin, const S* hin, typename StoreT<S>::R* snap, int snap_valid,
+    Geo g, Phys<typename StoreT<S>::R> P, ForceArgs<typename StoreT<S>::R> fa,
+    typename StoreT<S>::R inv_sf, typename StoreT<S>::R inv_sh,
+    double* partials) {
+  using R = typename StoreT<S>::R;
+  using L = Lat<D>;
+  constexpr int Q = L::Q, NC = L::NC;
+  double acc[NRED];
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    node_xyz<D>(n, g, x, y, z);
+    NodeMoments<D, S> m;
+    node_moments<D, S>(fin, hin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
+    bool finite = true;
+    for (int b = 0; b < D; ++b) {
+      const double ub = (double)m.u[b];
+      finite = finite && isfinite(ub);
+      if (snap_valid) {
+        const double d = ub - (double)snap[(size_t)b * g.N + n];
+        acc[0] += d * d;
+      }
+      acc[1] += ub * ub;
+      snap[(size_t)b * g.N + n] = m.u[b];
+    }
+    double tr = 0.0;
+    for (int c = 0; c < NC; ++c) {
+      const double tc = (double)m.tau[c];
+      finite = finite && isfinite(tc);
+      const double wgt = (L::ca(c) == L::cb(c)) ? 1.0 : 2.0;  // tensor norm
+      if (snap_valid) {
+        const double d = tc - (double)snap[(size_t)(D + c) * g.N + n];
+        acc[2] += wgt * d * d;
+      }
+      acc[3] += wgt * tc * tc;
+      if (L::ca(c) == L::cb(c)) tr += tc;
+      acc[11 + c] += (double)m.e[c] + ((L::ca(c) == L::cb(c)) ? 1.0 : 0.0);
+      snap[(size_t)(D + c) * g.N + n] = m.tau[c];
+    }
+    double M = 0.0, Pm[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+      const double fi = (double)m.f[i];
+      M += fi;
+      for (int b = 0; b < D; ++b) Pm[b] += cdir<D>(i, b) * fi;
+    }
+    finite = finite && isfinite(M) && isfinite((double)m.p);
+    acc[4] += M;
+    acc[5] += Pm[0];
+    acc[6] += Pm[1];
+    acc[7] += Pm[2];
+    acc[8] += 0.5 * ((double)m.u[0] * m.u[0] + (double)m.u[1] * m.u[1] +
+                     (double)m.u[2] * m.u[2]);
+    acc[9] += 0.5 * tr;
+    acc[10] += finite ? 0.0 : 1.0;
+  }
+  __shared__ double red[256 / 64][NRED];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) red[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NRED) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
+    partials[(size_t)blockIdx.x * NRED + threadIdx.x] = s;
+  }
+}
+
+__global__ void reduce_finish_kernel(const double* partials, int nblocks,
+                                     double* out) {
+  const int k = threadIdx.x;
+  if (k >= NRED) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * NRED + k];
+  out[k] = s;
+}
+
+}  // namespace vflb

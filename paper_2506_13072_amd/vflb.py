@@ -1,0 +1,250 @@
+"""Python binding of libvflb (include/vflb.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of ``libvflb.so``; PyTorch
+supplies device memory (the buffers the library asks for) and the HIP
+stream.  Loading fails loudly when the library has not been built: there is
+no fallback.
+
+Field arrays returned to Python are node-major, ``[N, ncomp]`` with
+x fastest, the same layout as the CPU oracle uses; the library itself works
+on component-major ``[ncomp][N]`` arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvflb.so")
+
+D2Q9, D3Q19 = 2, 3
+F64, F32, F16S, BF16S = 0, 1, 2, 3
+STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S}
+FORCE_NONE, FORCE_CONST, FORCE_FOUR_ROLL, FORCE_COS_T = 0, 1, 2, 3
+PERIODIC, WALLS = 0, 1
+(FIELD_U, FIELD_P, FIELD_RHO, FIELD_A, FIELD_TAU, FIELD_F, FIELD_H,
+ FIELD_CHI_PREV, FIELD_U_PREV) = range(9)
+NBUF = 7
+OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = range(6)
+
+
+class VflbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vflb error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("Re", ctypes.c_double), ("Wi", ctypes.c_double),
+                ("beta", ctypes.c_double), ("U0", ctypes.c_double),
+                ("L", ctypes.c_double), ("lam", ctypes.c_double),
+                ("tau_h", ctypes.c_double)]
+
+
+class LatticeParams(ctypes.Structure):
+    _fields_ = [("nu_s", ctypes.c_double), ("nu_p", ctypes.c_double),
+                ("tau_f", ctypes.c_double), ("tau_h", ctypes.c_double),
+                ("lam", ctypes.c_double), ("eta_p", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libvflb.so`` (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_2506_13072_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        I64, SZ = ctypes.c_int64, ctypes.c_size_t
+        L.vflb_create.argtypes = [I, I, I, I, I, P, ctypes.POINTER(P)]
+        L.vflb_query_buffers.argtypes = [P, ctypes.POINTER(SZ)]
+        L.vflb_bind_buffers.argtypes = [P, ctypes.POINTER(P)]
+        L.vflb_set_params.argtypes = [P, ctypes.POINTER(Params)]
+        L.vflb_get_lattice_params.argtypes = [P, ctypes.POINTER(LatticeParams)]
+        L.vflb_set_force.argtypes = [P, I, ctypes.POINTER(D), D]
+        L.vflb_set_boundaries.argtypes = [P, ctypes.POINTER(I)]
+        L.vflb_set_storage_scale.argtypes = [P, I, I]
+        L.vflb_init_fields.argtypes = [P, P, P, P]
+        L.vflb_step.argtypes = [P, I64]
+        L.vflb_time.argtypes = [P]
+        L.vflb_time.restype = I64
+        L.vflb_reduce.argtypes = [P, ctypes.POINTER(D)]
+        L.vflb_read.argtypes = [P, I, P, SZ]
+        L.vflb_state_size.argtypes = [P, ctypes.POINTER(SZ)]
+        L.vflb_save.argtypes = [P, P, SZ]
+        L.vflb_load.argtypes = [P, P, SZ]
+        L.vflb_set_tile.argtypes = [P, I]
+        L.vflb_destroy.argtypes = [P]
+        L.vflb_destroy.restype = None
+        L.vflb_last_error.argtypes = [P]
+        L.vflb_last_error.restype = ctypes.c_char_p
+        for name in ("vflb_create", "vflb_query_buffers", "vflb_bind_buffers",
+                     "vflb_set_params", "vflb_get_lattice_params", "vflb_set_force",
+                     "vflb_set_boundaries", "vflb_set_storage_scale", "vflb_init_fields",
+                     "vflb_step", "vflb_reduce", "vflb_read", "vflb_state_size",
+                     "vflb_save", "vflb_load", "vflb_set_tile"):
+            getattr(L, name).restype = I
+        _lib = L
+    return _lib
+
+
+def _check(handle, code):
+    if code != OK:
+        msg = lib().vflb_last_error(handle)
+        raise VflbError(code, msg.decode() if msg else "")
+
+
+class Sim:
+    """One lattice: ``Sim(lattice, nx, ny, nz, storage)``.
+
+    ``stream`` is a ``torch.cuda.Stream`` (a default-priority side stream is
+    created when omitted); the library enqueues every kernel on it.
+    """
+
+    def __init__(self, lattice, nx, ny, nz=1, storage="f32", device="cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.D = 2 if lattice in (2, "d2q9", "D2Q9") else 3
+        self.nx, self.ny = int(nx), int(ny)
+        self.nz = int(nz) if self.D == 3 else 1
+        self.N = self.nx * self.ny * self.nz
+        self.Q = 9 if self.D == 2 else 19
+        self.NC = 3 if self.D == 2 else 6
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        h = ctypes.c_void_p()
+        _check(None, lib().vflb_create(self.D, self.nx, self.ny, self.nz, self.storage,
+                                       ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(h)))
+        self._h = h
+        sizes = (ctypes.c_size_t * NBUF)()
+        _check(self._h, lib().vflb_query_buffers(self._h, sizes))
+        self.buffers = [torch.empty(int(b), dtype=torch.uint8, device=self.device)
+                        for b in sizes]
+        ptrs = (ctypes.c_void_p * NBUF)(*[b.data_ptr() for b in self.buffers])
+        _check(self._h, lib().vflb_bind_buffers(self._h, ptrs))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().vflb_destroy(h)
+            self._h = None
+
+    # ---------------------------------------------------------- set-up
+    def set_params(self, Re, Wi, beta, U0, L, lam=0.0, tau_h=0.0):
+        p = Params(Re, Wi, beta, U0, L, lam, tau_h)
+        _check(self._h, lib().vflb_set_params(self._h, ctypes.byref(p)))
+
+    def lattice_params(self):
+        lp = LatticeParams()
+        _check(self._h, lib().vflb_get_lattice_params(self._h, ctypes.byref(lp)))
+        return dict(nu_s=lp.nu_s, nu_p=lp.nu_p, tau_f=lp.tau_f, tau_h=lp.tau_h,
+                    lam=lp.lam, eta_p=lp.eta_p)
+
+    def set_force(self, kind, amp=(0.0, 0.0, 0.0), omega=0.0):
+        a = (ctypes.c_double * 3)(*(list(amp) + [0.0] * (3 - len(amp))))
+        _check(self._h, lib().vflb_set_force(self._h, int(kind), a, float(omega)))
+
+    def set_boundaries(self, walls):
+        w = list(walls) + [0] * (3 - len(walls))
+        k = (ctypes.c_int * 3)(*[int(x) for x in w])
+        _check(self._h, lib().vflb_set_boundaries(self._h, k))
+
+    def set_storage_scale(self, log2_f, log2_h):
+        _check(self._h, lib().vflb_set_storage_scale(self._h, int(log2_f), int(log2_h)))
+
+    def set_tile(self, tile_y):
+        _check(self._h, lib().vflb_set_tile(self._h, int(tile_y)))
+
+    def _dev_field(self, a, ncomp):
+        """Node-major [N, ncomp] host/torch array -> component-major FP64
+        device tensor (or None)."""
+        if a is None:
+            return None
+        t = self.torch.as_tensor(np.asarray(a, dtype=np.float64) if not
+                                 isinstance(a, self.torch.Tensor) else a,
+                                 dtype=self.torch.float64)
+        t = t.reshape(self.N, ncomp).t().contiguous().to(self.device)
+        return t
+
+    def init_fields(self, u=None, tau=None, p=None):
+        tu = self._dev_field(u, self.D)
+        tt = self._dev_field(tau, self.NC)
+        tp = self._dev_field(p, 1)
+        self.torch.cuda.current_stream(self.device).synchronize()
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        with self.torch.cuda.stream(self.stream):
+            _check(self._h, lib().vflb_init_fields(self._h, ptr(tu), ptr(tt), ptr(tp)))
+        self.stream.synchronize()
+        self._keep = (tu, tt, tp)
+
+    # ------------------------------------------------------------ run
+    def step(self, n=1):
+        _check(self._h, lib().vflb_step(self._h, int(n)))
+
+    @property
+    def t(self):
+        return lib().vflb_time(self._h)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def reduce(self, allow_unstable=False):
+        out = (ctypes.c_double * 14)()
+        rc = lib().vflb_reduce(self._h, out)
+        if rc != OK and not (allow_unstable and rc == EUNSTABLE):
+            _check(self._h, rc)
+        o = list(out)
+        return dict(R=o[0], M=o[1], P=o[2:2 + self.D], KE=o[5], PE=o[6],
+                    nonfinite=o[7], A_sum=o[8:8 + self.NC], status=rc)
+
+    def read_device(self, field):
+        """Field as a component-major FP64 device tensor [ncomp, N]."""
+        ncomp = {FIELD_U: self.D, FIELD_P: 1, FIELD_RHO: 1, FIELD_A: self.NC,
+                 FIELD_TAU: self.NC, FIELD_F: self.Q, FIELD_H: self.NC * self.Q,
+                 FIELD_CHI_PREV: self.NC, FIELD_U_PREV: self.D}[field]
+        out = self.torch.empty(ncomp * self.N, dtype=self.torch.float64,
+                               device=self.device)
+        _check(self._h, lib().vflb_read(self._h, int(field),
+                                        ctypes.c_void_p(out.data_ptr()), out.numel()))
+        return out.view(ncomp, self.N)
+
+    def read(self, field):
+        """Field as a node-major numpy array [N, ncomp] (FP64)."""
+        t = self.read_device(field)
+        self.stream.synchronize()
+        a = t.cpu().numpy().T.copy()
+        if field == FIELD_H:
+            a = a.reshape(self.N, self.NC, self.Q)
+        return a
+
+    def moments(self):
+        return dict(u=self.read(FIELD_U), p=self.read(FIELD_P)[:, 0],
+                    A=self.read(FIELD_A), tau=self.read(FIELD_TAU))
+
+    def state(self):
+        """Pre-collision populations and the auxiliary state, node-major."""
+        return dict(f=self.read(FIELD_F), h=self.read(FIELD_H),
+                    chi_prev=self.read(FIELD_CHI_PREV), u_prev=self.read(FIELD_U_PREV),
+                    t=self.t)
+
+    # ----------------------------------------------------- checkpoint
+    def save(self):
+        n = ctypes.c_size_t()
+        _check(self._h, lib().vflb_state_size(self._h, ctypes.byref(n)))
+        blob = self.torch.empty(n.value, dtype=self.torch.uint8, device=self.device)
+        _check(self._h, lib().vflb_save(self._h, ctypes.c_void_p(blob.data_ptr()), n.value))
+        return blob
+
+    def load(self, blob):
+        _check(self._h, lib().vflb_load(self._h, ctypes.c_void_p(blob.data_ptr()),
+                                        blob.numel()))

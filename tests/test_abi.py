@@ -1,0 +1,60 @@
+"""The C-ABI library loads, exports every entry point its header declares,
+and validates arguments on the host (no GPU needed for these calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vflb.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vflb_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2506_13072_amd import vflb
+    return vflb.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("vflb_create", "vflb_bind_buffers", "vflb_set_params", "vflb_set_force",
+              "vflb_set_boundaries", "vflb_init_fields", "vflb_step", "vflb_reduce",
+              "vflb_read", "vflb_save", "vflb_load", "vflb_destroy", "vflb_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    path = os.path.join(ROOT, "paper_2506_13072_amd", "libvflb.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\s[TW]\s+(vflb_\w+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        getattr(lib, n)
+
+
+def test_create_validates_arguments_on_host(lib):
+    h = ctypes.c_void_p()
+    assert lib.vflb_create(7, 8, 8, 1, 1, None, ctypes.byref(h)) == 1   # lattice
+    assert b"lattice" in lib.vflb_last_error(None)
+    assert lib.vflb_create(2, 8, 8, 1, 9, None, ctypes.byref(h)) == 1   # storage
+    assert lib.vflb_create(2, 0, 8, 1, 1, None, ctypes.byref(h)) == 1   # size
+    assert lib.vflb_create(3, 8, 8, 0, 1, None, ctypes.byref(h)) == 1
+    assert not h.value
+
+
+def test_python_binding_refuses_missing_library(monkeypatch, tmp_path):
+    from paper_2506_13072_amd import vflb
+    monkeypatch.setattr(vflb, "_lib", None)
+    monkeypatch.setattr(vflb, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        vflb.lib()

@@ -7,35 +7,8 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_2506_13072_amd.workloads import smooth_fields
 from tests.test_oracle_pins import C2, C3, CS2, constraint_matrix, weights
-
-
-def smooth_fields(d, shape, seed, amp_u=0.02, amp_tau=1e-3, amp_p=1e-3):
-    """Seeded, smooth periodic fields (a few low Fourier modes)."""
-    rng = np.random.default_rng(seed)
-    grids = np.meshgrid(*[2 * np.pi * np.arange(n) / n for n in shape[::-1]],
-                        indexing="xy" if d == 2 else "ij")
-    if d == 3:
-        grids = np.meshgrid(*[2 * np.pi * np.arange(n) / n for n in shape],
-                            indexing="ij")[::-1]
-    N = int(np.prod(shape))
-    nc = 3 if d == 2 else 6
-
-    def field(scale):
-        out = np.zeros(shape)
-        for _ in range(3):
-            k = rng.integers(0, 2, size=d)
-            ph = rng.uniform(0, 2 * np.pi, size=d)
-            term = np.ones(shape)
-            for a in range(d):
-                term = term * np.cos(k[a] * grids[a] + ph[a])
-            out += rng.normal() * term
-        return scale * out.reshape(N)
-
-    u = np.stack([field(amp_u) for _ in range(d)], -1)
-    tau = np.stack([field(amp_tau) for _ in range(nc)], -1)
-    p = field(amp_p)
-    return u, tau, p
 
 
 def make(d, shape, tau_f=0.8, tau_h=0.501, lam=50.0, eta_p=0.05, walls=(0, 0, 0)):
