@@ -39,12 +39,14 @@ def bytes_per_lup(d, storage):
     return 2 * q * (1 + nc) * sb + 2 * (nc + d) * ab
 
 
-def run_gpu(steps, warmup, storage="f32"):
+def run_gpu(steps, warmup, storage="f32", tile=0):
     import torch
     from paper_2506_13072_amd import vflb
     g = vflb.Sim(2, NX, NY, 1, storage)
     g.set_params(RE, WI, BETA, U0, L)
     g.set_boundaries((vflb.PERIODIC, vflb.WALLS))
+    if tile:
+        g.set_tile(tile)
     lp = g.lattice_params()
     nu = lp["nu_s"] + lp["nu_p"]
     g.set_force(vflb.FORCE_CONST, (8 * nu * U0 / L ** 2, 0.0, 0.0))
@@ -64,11 +66,12 @@ def run_gpu(steps, warmup, storage="f32"):
     e0.record(g.stream)
     red_ms = 0.0
     left = steps
+    r = None
     while left > 0:
         n = min(REDUCE_EVERY, left)
         g.step(n)
         left -= n
-        if left > 0 or n == REDUCE_EVERY:
+        if left > 0 or n == REDUCE_EVERY or r is None:
             r0 = torch.cuda.Event(enable_timing=True)
             r1 = torch.cuda.Event(enable_timing=True)
             r0.record(g.stream)
@@ -84,6 +87,54 @@ def run_gpu(steps, warmup, storage="f32"):
     step_ms = (total_ms - red_ms) / steps
     return dict(total_ms=total_ms, step_ms=step_ms, red_ms=red_ms, wall=wall,
                 R=r["R"], nonfinite=r["nonfinite"])
+
+
+def run_gpu_tgv(n, steps, warmup, storage="f32"):
+    """3D Taylor-Green vortex, D3Q19, periodic n^3, theta = 0 start,
+    U0 = 0.02, Re = 100, Wi = 0.5, beta = 0.9, L = n/(2 pi)."""
+    import math
+    import torch
+    from paper_2506_13072_amd import vflb
+    from paper_2506_13072_amd.workloads import taylor_green_3d_device
+    g = vflb.Sim(3, n, n, n, storage)
+    g.set_params(100.0, 0.5, 0.9, 0.02, n / (2 * math.pi))
+    u, p = taylor_green_3d_device(n, 0.02)
+    g.init_fields_device(u, None, p)
+    del u, p
+    g.step(warmup)
+    g.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    g.step(steps)
+    e1.record(g.stream)
+    e1.synchronize()
+    r = g.reduce()
+    ms = e0.elapsed_time(e1) / steps
+    return dict(step_ms=ms, GLUPS=n ** 3 / ms / 1e6, KE=r["KE"], nonfinite=r["nonfinite"])
+
+
+def copy_ceiling(nbytes=4 << 30, reps=10):
+    """Rate of the library's plain streaming-copy kernel (read + write bytes
+    per second), the achievable-bandwidth reference next to the 8 TB/s
+    peak."""
+    import torch
+    from paper_2506_13072_amd import vflb
+    st = torch.cuda.Stream()
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    vflb.stream_copy(src, dst, st)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        vflb.stream_copy(src, dst, st)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return 2 * nbytes / (ms / 1e3) / 1e9
 
 
 def run_cpu_baseline(budget_s=15.0):
@@ -118,12 +169,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "bf16s", "f64"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="D2Q9 tile height (4, 8, 16)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the streaming-copy kernel (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        print(json.dumps({"copy_GBps": round(copy_ceiling(), 1)}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is not built)", file=sys.stderr)
         sys.exit(2)
-    res = run_gpu(args.steps, args.warmup, args.storage)
+    res = run_gpu(args.steps, args.warmup, args.storage, args.tile)
+    ceiling = copy_ceiling()
     nodes = NX * NY
     mlups = nodes * args.steps / (res["total_ms"] / 1e3) / 1e6
     bpl = bytes_per_lup(2, args.storage)
@@ -148,7 +206,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_lup": bpl,
-                     "kernel_ms": round(res["step_ms"], 5)},
+                     "kernel_ms": round(res["step_ms"], 5),
+                     "copy_ceiling_GBps": round(ceiling, 1),
+                     "frac_of_copy": round(achieved / ceiling, 4)},
         "residual": res["R"],
     }
     if not args.no_cpu:

@@ -92,16 +92,17 @@ enum {
  * parabola through the wall value 0 and the first two nodes. */
 enum { VFLB_PERIODIC = 0, VFLB_WALLS = 1 };
 
-/* Device buffers of one simulation (sizes from vflb_query_buffers). */
+/* Device buffers of one simulation (sizes from vflb_query_buffers).  Their
+ * internal layout is private to the library (it differs between lattices
+ * and storages); read fields through vflb_read and move whole states through
+ * vflb_save / vflb_load. */
 enum {
-  VFLB_BUF_F0 = 0,  /* f populations, ping              Q*N storage words  */
-  VFLB_BUF_F1 = 1,  /* f populations, pong                                  */
-  VFLB_BUF_H0 = 2,  /* shifted h populations, ping      NC*Q*N words        */
-  VFLB_BUF_H1 = 3,  /* shifted h populations, pong                          */
-  VFLB_BUF_AUX = 4, /* chi(t-1) [NC][N] then u(t-1) [D][N], arithmetic type */
-  VFLB_BUF_SNAP = 5,/* residual snapshot u [D][N], tau [NC][N], arith. type */
-  VFLB_BUF_WORK = 6,/* force tables, reduction partials, step counter       */
-  VFLB_NBUF = 7
+  VFLB_BUF_POP0 = 0, /* all populations, ping                              */
+  VFLB_BUF_POP1 = 1, /* all populations, pong                              */
+  VFLB_BUF_AUX = 2,  /* chi(t-1) and u(t-1), arithmetic type               */
+  VFLB_BUF_SNAP = 3, /* residual snapshot of u and tau, arithmetic type    */
+  VFLB_BUF_WORK = 4, /* force tables, reduction partials                   */
+  VFLB_NBUF = 5
 };
 
 /* Read-back fields (vflb_read).  FIELD_U .. FIELD_H are moments of the
@@ -215,9 +216,17 @@ vflb_status vflb_save(vflb_sim *sim, void *dev_blob, size_t n);
 vflb_status vflb_load(vflb_sim *sim, const void *dev_blob, size_t n);
 
 /* Block height of the D2Q9 step kernel (tile 64 x tile_y, tile_y in
- * {1, 2, 4, 8}); 0 restores the built-in choice.  Results do not
- * depend on it. */
+ * {4, 8, 16}); 0 restores the built-in choice.  Results do not depend on
+ * it. */
 vflb_status vflb_set_tile(vflb_sim *sim, int tile_y);
+
+/* Bandwidth probe: copies nbytes (a multiple of 16) from src to dst, both
+ * device pointers 16-byte aligned, with a plain streaming kernel on
+ * hip_stream.  Not part of the method: it measures the achievable HBM copy
+ * rate and calibrates hardware byte counters against a transfer of known
+ * size.  EINVAL on bad sizes or alignment. */
+vflb_status vflb_stream_copy(const void *src, void *dst, size_t nbytes,
+                             void *hip_stream);
 
 /* Release the handle (not the caller's buffers). */
 void vflb_destroy(vflb_sim *sim);

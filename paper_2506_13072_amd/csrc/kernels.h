@@ -1,19 +1,17 @@
 // kernels.h -- HIP kernels of the fused fluctuating-LB step for gfx950.
 //
-// Data layout in HBM (structure of arrays, x fastest, N nodes):
-//   f  [Q][N]            velocity populations, post-collision of the last
-//                        step (pull scheme: streaming happens on the read)
-//   h  [NC][Q][N]        conformation populations minus w_i delta_ab
-//   aux[NC][N] + [D][N]  chi(t-1) and u(t-1) for the backward difference of
-//                        the source term; read and written in place by the
-//                        owning node only
+// Populations are post-collision values of the last step (pull scheme:
+// streaming happens on the read), h stored minus w_i delta_ab; layout.h
+// gives their placement in HBM.  chi(t-1) and u(t-1) for the backward
+// difference of the source term are read and written in place by the
+// owning node only.
 // The step kernel pulls f and h, forms the moments, collides f (Sec. 2.2),
 // builds u on a tile plus a one-node halo in LDS for the same-time
 // velocity gradient, then forms the Oldroyd-B source and collides h
 // (Sec. 2.3).  f and h are written to the other buffer of a ping-pong pair.
 #pragma once
 
-#include "lattice.h"
+#include "layout.h"
 
 namespace vflb {
 
@@ -34,10 +32,8 @@ template <class R> struct ForceArgs {
 
 template <class S> struct StepArgs {
   using R = typename StoreT<S>::R;
-  const S* fin;
-  S* fout;
-  const S* hin;
-  S* hout;
+  const S* pin;   // populations read (pull)
+  S* pout;        // populations written
   R* aux;
   Geo g;
   Phys<R> P;
@@ -127,30 +123,24 @@ __global__ void __launch_bounds__(MAXT) step_kernel(StepArgs<S> a) {
   bool valid = wrap_coord(wx, g.nx, g.walls & 1) && wrap_coord(wy, g.ny, g.walls & 2);
   if (D == 3) valid = valid && wrap_coord(wz, g.nz, g.walls & 4);
 
+  using P = Pops<D, S>;
   R f[Q];
   R h[NC][Q];
   R chip[NC], up[3] = {0, 0, 0};
-  size_t idx[Q];
   const size_t n = active ? node_of(x, y, z, g) : 0;
-  if (valid) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      idx[i] = pull_index<D>(i, wx, wy, wz, g);
-      f[i] = St::ld(a.fin, idx[i], a.inv_sf);
-    }
-  }
   if (active) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int i = 0; i < Q; ++i) {
+      R hv[NC];
+      P::load(a.pin, pull_index<D>(i, wx, wy, wz, g), g.N, a.inv_sf, a.inv_sh, f[i], hv);
 #pragma unroll
-      for (int i = 0; i < Q; ++i)
-        h[c][i] = St::ld(a.hin, (size_t)c * Q * g.N + idx[i], a.inv_sh);
-    if (!a.first) {
-#pragma unroll
-      for (int c = 0; c < NC; ++c) chip[c] = a.aux[(size_t)c * g.N + n];
-#pragma unroll
-      for (int b = 0; b < D; ++b) up[b] = a.aux[(size_t)(NC + b) * g.N + n];
+      for (int c = 0; c < NC; ++c) h[c][i] = hv[c];
     }
+    if (!a.first) Aux<D, R>::load(a.aux, n, g.N, chip, up);
+  } else if (valid) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      f[i] = P::load_f(a.pin, pull_index<D>(i, wx, wy, wz, g), g.N, a.inv_sf);
   }
 
   R u[3] = {0, 0, 0}, F[3];
@@ -176,8 +166,6 @@ __global__ void __launch_bounds__(MAXT) step_kernel(StepArgs<S> a) {
       e[c] = s;
     }
     collide_f<D, R>(f, e, u, F, a.P);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) St::st(a.fout, (size_t)i * g.N + n, f[i], a.sf);
   }
 
   // velocity on the halo slots of the tile
@@ -194,7 +182,8 @@ __global__ void __launch_bounds__(MAXT) step_kernel(StepArgs<S> a) {
     force_at<R>(a.F, gx, gy, g.nx, g.ny, Fh);
     R fh[Q];
 #pragma unroll
-    for (int i = 1; i < Q; ++i) fh[i] = St::ld(a.fin, pull_index<D>(i, gx, gy, gz, g), a.inv_sf);
+    for (int i = 1; i < Q; ++i)
+      fh[i] = Pops<D, S>::load_f(a.pin, pull_index<D>(i, gx, gy, gz, g), g.N, a.inv_sf);
 #pragma unroll
     for (int b = 0; b < D; ++b) {
       R sm = 0;
@@ -236,14 +225,15 @@ __global__ void __launch_bounds__(MAXT) step_kernel(StepArgs<S> a) {
   for (int c = 0; c < NC; ++c) {
     const R Ac = e[c] + ((L::ca(c) == L::cb(c)) ? (R)1 : (R)0);
     collide_h<D, R>(h[c], e[c], Ac, chi[c], chip[c], u, up, a.first != 0, a.P);
-#pragma unroll
-    for (int i = 0; i < Q; ++i)
-      St::st(a.hout, ((size_t)c * Q + i) * g.N + n, h[c][i], a.sh);
   }
 #pragma unroll
-  for (int c = 0; c < NC; ++c) a.aux[(size_t)c * g.N + n] = chi[c];
+  for (int i = 0; i < Q; ++i) {
+    R hv[NC];
 #pragma unroll
-  for (int b = 0; b < D; ++b) a.aux[(size_t)(NC + b) * g.N + n] = u[b];
+    for (int c = 0; c < NC; ++c) hv[c] = h[c][i];
+    Pops<D, S>::store(a.pout, (size_t)i * g.N + n, g.N, a.sf, a.sh, f[i], hv);
+  }
+  Aux<D, R>::store(a.aux, n, g.N, chi, u);
 }
 
 // --------------------------------------------------- shared node moments
@@ -258,8 +248,7 @@ struct NodeMoments {
 };
 
 template <int D, class S>
-__device__ inline void node_moments(const S* fin, const S* hin, int x, int y,
-                                    int z, const Geo& g,
+__device__ inline void node_moments(const S* pin, int x, int y, int z, const Geo& g,
                                     const Phys<typename StoreT<S>::R>& P,
                                     const ForceArgs<typename StoreT<S>::R>& fa,
                                     typename StoreT<S>::R inv_sf,
@@ -271,10 +260,10 @@ __device__ inline void node_moments(const S* fin, const S* hin, int x, int y,
   constexpr int Q = L::Q, NC = L::NC;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const size_t id = pull_index<D>(i, x, y, z, g);
-    m.f[i] = St::ld(fin, id, inv_sf);
+    R hv[NC];
+    Pops<D, S>::load(pin, pull_index<D>(i, x, y, z, g), g.N, inv_sf, inv_sh, m.f[i], hv);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) m.h[c][i] = St::ld(hin, (size_t)c * Q * g.N + id, inv_sh);
+    for (int c = 0; c < NC; ++c) m.h[c][i] = hv[c];
   }
   R F[3];
   force_at<R>(fa, x, y, g.nx, g.ny, F);
@@ -322,18 +311,25 @@ __device__ inline void node_xyz(size_t n, const Geo& g, int& x, int& y, int& z) 
 enum { FIELD_U = 0, FIELD_P = 1, FIELD_RHO = 2, FIELD_A = 3, FIELD_TAU = 4,
        FIELD_F = 5, FIELD_H = 6, FIELD_CHI_PREV = 7, FIELD_U_PREV = 8 };
 
-// copy of the auxiliary state (arithmetic type) to FP64
-template <class R>
-__global__ void __launch_bounds__(256) aux_read_kernel(const R* aux, size_t count,
+// auxiliary state chi(t-1) (field 7) or u(t-1) (field 8), component-major FP64
+template <int D, class R>
+__global__ void __launch_bounds__(256) aux_read_kernel(const R* aux, Geo g, int field,
                                                        double* out) {
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
-       k += (size_t)gridDim.x * blockDim.x)
-    out[k] = (double)aux[k];
+  constexpr int NC = Lat<D>::NC;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    R chi[NC], u[3] = {0, 0, 0};
+    Aux<D, R>::load(aux, n, g.N, chi, u);
+    if (field == FIELD_CHI_PREV)
+      for (int c = 0; c < NC; ++c) out[(size_t)c * g.N + n] = (double)chi[c];
+    else
+      for (int b = 0; b < D; ++b) out[(size_t)b * g.N + n] = (double)u[b];
+  }
 }
 
 template <int D, class S>
 __global__ void __launch_bounds__(256) moments_kernel(
-    const S* fin, const S* hin, Geo g, Phys<typename StoreT<S>::R> P,
+    const S* pin, Geo g, Phys<typename StoreT<S>::R> P,
     ForceArgs<typename StoreT<S>::R> fa, typename StoreT<S>::R inv_sf,
     typename StoreT<S>::R inv_sh, int field, double* out) {
   using L = Lat<D>;
@@ -343,7 +339,7 @@ __global__ void __launch_bounds__(256) moments_kernel(
     int x, y, z;
     node_xyz<D>(n, g, x, y, z);
     NodeMoments<D, S> m;
-    node_moments<D, S>(fin, hin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
+    node_moments<D, S>(pin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
     switch (field) {
       case FIELD_U:
         for (int b = 0; b < D; ++b) out[(size_t)b * g.N + n] = (double)m.u[b];
@@ -381,7 +377,7 @@ __global__ void __launch_bounds__(256) moments_kernel(
 // first step reads it, so that the first step sees exactly this state.
 template <int D, class S>
 __global__ void __launch_bounds__(256) init_kernel(
-    S* fbuf, S* hbuf, typename StoreT<S>::R* aux, Geo g,
+    S* pbuf, typename StoreT<S>::R* aux, Geo g,
     const double* u_in, const double* tau_in, const double* p_in,
     double lam_over_eta, typename StoreT<S>::R sf, typename StoreT<S>::R sh) {
   using St = StoreT<S>;
@@ -407,16 +403,17 @@ __global__ void __launch_bounds__(256) init_kernel(
       const R lam_i = (R)(i == 0 ? 3.0 * (L::w(0) - 1.0) : 3.0 * L::w(i));
       const R cu = cdot<D, R>(i, u);
       const R feq = lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
-      const size_t id = pull_index<D>(i, x, y, z, g);
-      St::st(fbuf, id, feq, sf);
+      R hv[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const R Ac = e[c] + ((L::ca(c) == L::cb(c)) ? (R)1 : (R)0);
-        St::st(hbuf, (size_t)c * Q * g.N + id, wi * e[c] + 3 * wi * Ac * cu, sh);
+        hv[c] = wi * e[c] + 3 * wi * Ac * cu;
       }
+      Pops<D, S>::store(pbuf, pull_index<D>(i, x, y, z, g), g.N, sf, sh, feq, hv);
     }
-    for (int c = 0; c < NC; ++c) aux[(size_t)c * g.N + n] = 0;
-    for (int b = 0; b < D; ++b) aux[(size_t)(NC + b) * g.N + n] = u[b];
+    R zero[NC];
+    for (int c = 0; c < NC; ++c) zero[c] = 0;
+    Aux<D, R>::store(aux, n, g.N, zero, u);
   }
 }
 
@@ -431,7 +428,7 @@ __device__ inline double wave_sum(double v) {
 
 template <int D, class S>
 __global__ void __launch_bounds__(256) reduce_kernel(
-    const S* fin, const S* hin, typename StoreT<S>::R* snap, int snap_valid,
+    const S* pin, typename StoreT<S>::R* snap, int snap_valid,
     Geo g, Phys<typename StoreT<S>::R> P, ForceArgs<typename StoreT<S>::R> fa,
     typename StoreT<S>::R inv_sf, typename StoreT<S>::R inv_sh,
     double* partials) {
@@ -446,7 +443,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(
     int x, y, z;
     node_xyz<D>(n, g, x, y, z);
     NodeMoments<D, S> m;
-    node_moments<D, S>(fin, hin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
+    node_moments<D, S>(pin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
     bool finite = true;
     for (int b = 0; b < D; ++b) {
       const double ub = (double)m.u[b];
@@ -510,6 +507,15 @@ __global__ void reduce_finish_kernel(const double* partials, int nblocks,
   double s = 0.0;
   for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * NRED + k];
   out[k] = s;
+}
+
+// plain streaming copy: one 16-byte vector per lane, non-temporal
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) stream_copy_kernel(const v4u32* __restrict__ src,
+                                                          v4u32* __restrict__ dst,
+                                                          size_t n) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
 }
 
 }  // namespace vflb

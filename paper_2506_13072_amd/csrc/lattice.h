@@ -85,16 +85,23 @@ struct bf16_t {
   uint16_t bits;
 };
 
+// Stores of step outputs are non-temporal: the values are read again only
+// by the next step, after the whole lattice has streamed through the caches.
+template <class T>
+__device__ inline void stream_store(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 template <class S> struct StoreT;
 template <> struct StoreT<double> {
   using R = double;
   __device__ static R ld(const double* p, size_t i, R) { return p[i]; }
-  __device__ static void st(double* p, size_t i, R v, R) { p[i] = v; }
+  __device__ static void st(double* p, size_t i, R v, R) { stream_store(p + i, v); }
 };
 template <> struct StoreT<float> {
   using R = float;
   __device__ static R ld(const float* p, size_t i, R) { return p[i]; }
-  __device__ static void st(float* p, size_t i, R v, R) { p[i] = v; }
+  __device__ static void st(float* p, size_t i, R v, R) { stream_store(p + i, v); }
 };
 template <> struct StoreT<_Float16> {
   using R = float;
@@ -103,7 +110,7 @@ template <> struct StoreT<_Float16> {
     return (float)p[i] * inv_scale;
   }
   __device__ static void st(_Float16* p, size_t i, R v, R scale) {
-    p[i] = (_Float16)(v * scale);
+    stream_store(p + i, (_Float16)(v * scale));
   }
 };
 template <> struct StoreT<bf16_t> {
@@ -121,9 +128,7 @@ template <> struct StoreT<bf16_t> {
       b += 0x7fffu + ((b >> 16) & 1u);          // round to nearest even
       out = (uint16_t)(b >> 16);
     }
-    bf16_t r;
-    r.bits = out;
-    p[i] = r;
+    stream_store(reinterpret_cast<uint16_t*>(p) + i, out);
   }
 };
 

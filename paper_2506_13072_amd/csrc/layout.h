@@ -1,0 +1,251 @@
+// layout.h -- where populations and auxiliary fields live in HBM.
+//
+// One buffer per ping/pong side holds all populations of the lattice.  A
+// "tuple index" t = i*N + n names direction i at node n.
+//
+//  D2Q9:  tuples [Q][N] of (f_i, h_xx,i, h_xy,i, h_yy,i).  f and the three
+//         conformation populations of one direction stream from the same
+//         source node, so a pull is one aligned vector load (16 bytes in
+//         FP32, 8 in 16-bit storage) and a store one vector store.
+//  D3Q19: FP32/FP64 tuples (f, h_xx, h_yy, h_zz) [Q][N] followed by tuples
+//         (h_xy, h_xz, h_yz) [Q][N]; 16-bit storage one 8-wide tuple
+//         (f, h_xx, h_yy, h_zz, h_xy, h_xz, h_yz, unused) [Q][N].
+//
+// Auxiliary state chi(t-1), u(t-1):
+//  D2Q9:  chi [N][3] then u [N][2] (one 12-byte and one 8-byte access).
+//  D3Q19: chi [NC][N] then u [D][N].
+#pragma once
+
+#include "lattice.h"
+
+namespace vflb {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+// 4-wide tuple access in the arithmetic type: component 0 scaled by the f
+// scale, components 1..3 by the h scale (scales are 1 except for FP16).
+template <class S> struct Tuple4;
+template <> struct Tuple4<float> {
+  __device__ static void ld(const float* p, size_t t, float, float, float* v) {
+    const f32x4 q = reinterpret_cast<const f32x4*>(p)[t];
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  __device__ static void st(float* p, size_t t, float, float, const float* v) {
+    f32x4 q = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(q, reinterpret_cast<f32x4*>(p) + t);
+  }
+};
+template <> struct Tuple4<double> {
+  __device__ static void ld(const double* p, size_t t, double, double, double* v) {
+    const f64x4 q = reinterpret_cast<const f64x4*>(p)[t];
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  }
+  __device__ static void st(double* p, size_t t, double, double, const double* v) {
+    f64x4 q = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(q, reinterpret_cast<f64x4*>(p) + t);
+  }
+};
+template <> struct Tuple4<_Float16> {
+  __device__ static void ld(const _Float16* p, size_t t, float isf, float ish, float* v) {
+    const f16x4 q = reinterpret_cast<const f16x4*>(p)[t];
+    v[0] = (float)q.x * isf; v[1] = (float)q.y * ish;
+    v[2] = (float)q.z * ish; v[3] = (float)q.w * ish;
+  }
+  __device__ static void st(_Float16* p, size_t t, float sf, float sh, const float* v) {
+    f16x4 q = {(_Float16)(v[0] * sf), (_Float16)(v[1] * sh), (_Float16)(v[2] * sh),
+               (_Float16)(v[3] * sh)};
+    __builtin_nontemporal_store(q, reinterpret_cast<f16x4*>(p) + t);
+  }
+};
+__device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ inline uint16_t f32_to_bf16(float v) {
+  uint32_t b = __float_as_uint(v);
+  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu))
+    return (uint16_t)((b >> 16) | 0x0040u);  // keep NaN a NaN
+  b += 0x7fffu + ((b >> 16) & 1u);          // round to nearest even
+  return (uint16_t)(b >> 16);
+}
+template <> struct Tuple4<bf16_t> {
+  __device__ static void ld(const bf16_t* p, size_t t, float, float, float* v) {
+    const u16x4 q = reinterpret_cast<const u16x4*>(p)[t];
+    v[0] = bf16_to_f32(q.x); v[1] = bf16_to_f32(q.y);
+    v[2] = bf16_to_f32(q.z); v[3] = bf16_to_f32(q.w);
+  }
+  __device__ static void st(bf16_t* p, size_t t, float, float, const float* v) {
+    u16x4 q = {f32_to_bf16(v[0]), f32_to_bf16(v[1]), f32_to_bf16(v[2]), f32_to_bf16(v[3])};
+    __builtin_nontemporal_store(q, reinterpret_cast<u16x4*>(p) + t);
+  }
+};
+
+template <int D, class S> struct Pops;
+
+template <class S> struct Pops<2, S> {
+  using St = StoreT<S>;
+  using R = typename St::R;
+  static constexpr int Q = 9, NC = 3;
+  __host__ __device__ static size_t words(size_t N) { return (size_t)4 * Q * N; }
+  __device__ static void load(const S* p, size_t t, size_t, R isf, R ish, R& f, R* h) {
+    R v[4];
+    Tuple4<S>::ld(p, t, isf, ish, v);
+    f = v[0]; h[0] = v[1]; h[1] = v[2]; h[2] = v[3];
+  }
+  __device__ static R load_f(const S* p, size_t t, size_t, R isf) {
+    return St::ld(p, 4 * t, isf);
+  }
+  __device__ static void store(S* p, size_t t, size_t, R sf, R sh, R f, const R* h) {
+    const R v[4] = {f, h[0], h[1], h[2]};
+    Tuple4<S>::st(p, t, sf, sh, v);
+  }
+};
+
+// D3Q19, FP32/FP64: A tuples [Q][N] of (f, h_xx, h_yy, h_zz) followed by
+// B tuples [Q][N] of (h_xy, h_xz, h_yz): one 4-wide and one 3-wide access
+// per pulled direction, no padding.
+template <class S> struct Pops3Wide {
+  using R = S;
+  static constexpr int Q = 19, NC = 6;
+  typedef S s4 __attribute__((ext_vector_type(4)));
+  struct s3 { S a, b, c; };
+  __host__ __device__ static size_t words(size_t N) { return (size_t)7 * Q * N; }
+  __device__ static void load(const S* p, size_t t, size_t N, R, R, R& f, R* h) {
+    const s4 a = reinterpret_cast<const s4*>(p)[t];
+    const s3 b = reinterpret_cast<const s3*>(p + (size_t)4 * Q * N)[t];
+    f = a.x; h[0] = a.y; h[1] = a.z; h[2] = a.w;
+    h[3] = b.a; h[4] = b.b; h[5] = b.c;
+  }
+  __device__ static R load_f(const S* p, size_t t, size_t, R) { return p[4 * t]; }
+  __device__ static void store(S* p, size_t t, size_t N, R, R, R f, const R* h) {
+    const s4 a = {f, h[0], h[1], h[2]};
+    __builtin_nontemporal_store(a, reinterpret_cast<s4*>(p) + t);
+    S* b = p + (size_t)4 * Q * N + 3 * t;
+    stream_store(b, h[3]);
+    stream_store(b + 1, h[4]);
+    stream_store(b + 2, h[5]);
+  }
+};
+// Plane-based access used by the step kernel: the base of direction i's
+// plane is uniform across the wavefront and the node offset a 32-bit byte
+// offset, so loads use the scalar-base + 32-bit-offset addressing form
+// (no per-lane 64-bit address arithmetic).  Valid while one plane holds
+// less than 4 GiB.
+template <class S, int QQ> struct Plane3 {
+  typedef S s4 __attribute__((ext_vector_type(4)));
+  struct s3 { S a, b, c; };
+  __device__ static void load(const S* p, int i, uint32_t node, size_t N, S& f, S* h) {
+    const char* A = reinterpret_cast<const char*>(p) + (size_t)i * N * (4 * sizeof(S));
+    const char* B = reinterpret_cast<const char*>(p) + (size_t)QQ * N * (4 * sizeof(S)) +
+                    (size_t)i * N * (3 * sizeof(S));
+    const s4 a = *reinterpret_cast<const s4*>(A + node * (uint32_t)(4 * sizeof(S)));
+    const s3 b = *reinterpret_cast<const s3*>(B + node * (uint32_t)(3 * sizeof(S)));
+    f = a.x; h[0] = a.y; h[1] = a.z; h[2] = a.w;
+    h[3] = b.a; h[4] = b.b; h[5] = b.c;
+  }
+  __device__ static S load_f(const S* p, int i, uint32_t node, size_t N) {
+    const char* A = reinterpret_cast<const char*>(p) + (size_t)i * N * (4 * sizeof(S));
+    return *reinterpret_cast<const S*>(A + node * (uint32_t)(4 * sizeof(S)));
+  }
+  __device__ static void store(S* p, int i, uint32_t node, size_t N, S f, const S* h) {
+    char* A = reinterpret_cast<char*>(p) + (size_t)i * N * (4 * sizeof(S));
+    char* B = reinterpret_cast<char*>(p) + (size_t)QQ * N * (4 * sizeof(S)) +
+              (size_t)i * N * (3 * sizeof(S));
+    const s4 a = {f, h[0], h[1], h[2]};
+    __builtin_nontemporal_store(a, reinterpret_cast<s4*>(A + node * (uint32_t)(4 * sizeof(S))));
+    S* b = reinterpret_cast<S*>(B + node * (uint32_t)(3 * sizeof(S)));
+    stream_store(b, h[3]);
+    stream_store(b + 1, h[4]);
+    stream_store(b + 2, h[5]);
+  }
+};
+
+template <> struct Pops<3, float> : Pops3Wide<float> {};
+template <> struct Pops<3, double> : Pops3Wide<double> {};
+
+// D3Q19, 16-bit: one 16-byte tuple [Q][N] of (f, h_xx, h_yy, h_zz, h_xy,
+// h_xz, h_yz, unused) per direction and node: a pull is one aligned 16-byte
+// load (the unused eighth slot costs 2 of 16 bytes).
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+template <> struct Pops<3, _Float16> {
+  using R = float;
+  static constexpr int Q = 19, NC = 6;
+  __host__ __device__ static size_t words(size_t N) { return (size_t)8 * Q * N; }
+  __device__ static void load(const _Float16* p, size_t t, size_t, R isf, R ish, R& f, R* h) {
+    const f16x8 q = reinterpret_cast<const f16x8*>(p)[t];
+    f = (float)q[0] * isf;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) h[c] = (float)q[1 + c] * ish;
+  }
+  __device__ static R load_f(const _Float16* p, size_t t, size_t, R isf) {
+    return (float)p[8 * t] * isf;
+  }
+  __device__ static void store(_Float16* p, size_t t, size_t, R sf, R sh, R f, const R* h) {
+    f16x8 q;
+    q[0] = (_Float16)(f * sf);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q[1 + c] = (_Float16)(h[c] * sh);
+    q[7] = (_Float16)0.0f;
+    __builtin_nontemporal_store(q, reinterpret_cast<f16x8*>(p) + t);
+  }
+};
+template <> struct Pops<3, bf16_t> {
+  using R = float;
+  static constexpr int Q = 19, NC = 6;
+  __host__ __device__ static size_t words(size_t N) { return (size_t)8 * Q * N; }
+  __device__ static void load(const bf16_t* p, size_t t, size_t, R, R, R& f, R* h) {
+    const u16x8 q = reinterpret_cast<const u16x8*>(p)[t];
+    f = bf16_to_f32(q[0]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) h[c] = bf16_to_f32(q[1 + c]);
+  }
+  __device__ static R load_f(const bf16_t* p, size_t t, size_t, R) {
+    return bf16_to_f32(reinterpret_cast<const uint16_t*>(p)[8 * t]);
+  }
+  __device__ static void store(bf16_t* p, size_t t, size_t, R, R, R f, const R* h) {
+    u16x8 q;
+    q[0] = f32_to_bf16(f);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q[1 + c] = f32_to_bf16(h[c]);
+    q[7] = 0;
+    __builtin_nontemporal_store(q, reinterpret_cast<u16x8*>(p) + t);
+  }
+};
+
+// auxiliary state
+template <int D, class R> struct Aux;
+template <class R> struct Aux<2, R> {
+  static constexpr int NC = 3;
+  __host__ __device__ static size_t words(size_t N) { return (size_t)5 * N; }
+  __device__ static void load(const R* a, size_t n, size_t N, R* chi, R* u) {
+    const R* c = a + 3 * n;
+    chi[0] = c[0]; chi[1] = c[1]; chi[2] = c[2];
+    const R* w = a + 3 * N + 2 * n;
+    u[0] = w[0]; u[1] = w[1];
+  }
+  __device__ static void store(R* a, size_t n, size_t N, const R* chi, const R* u) {
+    R* c = a + 3 * n;
+    stream_store(c, chi[0]); stream_store(c + 1, chi[1]); stream_store(c + 2, chi[2]);
+    R* w = a + 3 * N + 2 * n;
+    stream_store(w, u[0]); stream_store(w + 1, u[1]);
+  }
+};
+template <class R> struct Aux<3, R> {
+  static constexpr int NC = 6;
+  __host__ __device__ static size_t words(size_t N) { return (size_t)9 * N; }
+  __device__ static void load(const R* a, size_t n, size_t N, R* chi, R* u) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) chi[c] = a[(size_t)c * N + n];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[b] = a[(size_t)(NC + b) * N + n];
+  }
+  __device__ static void store(R* a, size_t n, size_t N, const R* chi, const R* u) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) stream_store(a + (size_t)c * N + n, chi[c]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) stream_store(a + (size_t)(NC + b) * N + n, u[b]);
+  }
+};
+
+}  // namespace vflb

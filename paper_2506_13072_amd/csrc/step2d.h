@@ -1,0 +1,190 @@
+// step2d.h -- the fused D2Q9 step, specialised for gfx950.
+//
+// Workgroup = TY wavefronts of 64 lanes; each wavefront owns one 64-node
+// row segment of a 64 x TY tile.  The 2(64+2) + 2 TY halo nodes of the tile
+// are assigned to the first lanes before any load is issued, so the halo
+// pulls travel with the tile's own 36 population loads in one round trip.
+// Tiles are numbered row-major in launch order (measured faster on MI355X
+// than giving each XCD a contiguous band of tiles), and the outputs are
+// written with non-temporal stores: they are read back only in the next
+// step, long after they would have left the caches.
+#pragma once
+
+#include "kernels.h"
+
+namespace vflb {
+
+struct Pull2 {
+  // in-plane offsets of the three columns and rows a node pulls from
+  size_t col[3], row[3];  // index 0: from c = +1 (x-1), 1: c = 0, 2: c = -1 (x+1)
+  bool lo_x, hi_x, lo_y, hi_y;  // node next to a wall on that side
+  size_t self;
+};
+
+__device__ inline void make_pull2(int x, int y, const Geo& g, Pull2& p) {
+  const bool wx = g.walls & 1, wy = g.walls & 2;
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+  p.col[0] = (size_t)xm;
+  p.col[1] = (size_t)x;
+  p.col[2] = (size_t)xp;
+  p.row[0] = (size_t)ym * g.nx;
+  p.row[1] = (size_t)y * g.nx;
+  p.row[2] = (size_t)yp * g.nx;
+  p.lo_x = wx && x == 0;
+  p.hi_x = wx && x == g.nx - 1;
+  p.lo_y = wy && y == 0;
+  p.hi_y = wy && y == g.ny - 1;
+  p.self = p.row[1] + p.col[1];
+}
+
+// index (plane offset included) of the value that streams into direction i
+__device__ inline size_t pull2_index(int i, const Pull2& p, size_t N) {
+  const int cx = Lat<2>::cx(i), cy = Lat<2>::cy(i);
+  const bool bounce = (cx > 0 && p.lo_x) || (cx < 0 && p.hi_x) ||
+                      (cy > 0 && p.lo_y) || (cy < 0 && p.hi_y);
+  if (bounce) return (size_t)Lat<2>::opp(i) * N + p.self;
+  return (size_t)i * N + p.row[1 - cy] + p.col[1 - cx];
+}
+
+// u = sum c_i f_i + F/2 (Sec. 2.2).  Evaluated by the owner of a node and
+// by the lanes that fill the halo; no contraction into fused multiply-adds,
+// so both give the same bits and results do not depend on the tile shape.
+template <class R>
+__device__ inline void velocity2(const R* f, const R* F, R* u) {
+#pragma clang fp contract(off)
+  u[0] = (f[1] - f[3] + f[5] - f[6] - f[7] + f[8]) + (R)0.5 * F[0];
+  u[1] = (f[2] - f[4] + f[5] + f[6] - f[7] - f[8]) + (R)0.5 * F[1];
+}
+
+template <class S, int TY>
+__global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx, int nty) {
+  using R = typename StoreT<S>::R;
+  constexpr int Q = 9, NC = 3, TX = 64, SX = TX + 2, SY = TY + 2, NS = SX * SY;
+  constexpr int H = 2 * SX + 2 * TY;  // halo nodes of the tile
+  __shared__ R su[2][NS];
+
+  const Geo g = a.g;
+  const S* __restrict__ pin = a.pin;
+  S* __restrict__ pout = a.pout;
+  R* __restrict__ aux = a.aux;
+  const size_t N = g.N;
+  using P2 = Pops<2, S>;
+
+  const int tile = blockIdx.x;
+  const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+  (void)nty;
+
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * TX + tx;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool active = x < g.nx && y < g.ny;
+
+  // ---- halo node of this lane (if any): coordinates, slot, pull offsets
+  bool hvalid = false;
+  int hslot = 0, hx = 0, hy = 0;
+  if (tid < H) {
+    int sxl, syl;
+    if (tid < SX) { sxl = tid; syl = 0; }
+    else if (tid < 2 * SX) { sxl = tid - SX; syl = SY - 1; }
+    else if (tid < 2 * SX + TY) { sxl = 0; syl = 1 + tid - 2 * SX; }
+    else { sxl = SX - 1; syl = 1 + tid - 2 * SX - TY; }
+    hslot = syl * SX + sxl;
+    hx = x0 - 1 + sxl;
+    hy = y0 - 1 + syl;
+    hvalid = wrap_coord(hx, g.nx, g.walls & 1) && wrap_coord(hy, g.ny, g.walls & 2);
+  }
+  // own node, wrapped for lanes past a ragged edge (they supply the slot's
+  // velocity for the true last node's gradient)
+  int wx = x, wy = y;
+  const bool valid = wrap_coord(wx, g.nx, g.walls & 1) && wrap_coord(wy, g.ny, g.walls & 2);
+
+  // ---- issue every load of the step
+  R fh[Q];
+  if (hvalid) {
+    Pull2 ph;
+    make_pull2(hx, hy, g, ph);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) fh[i] = P2::load_f(pin, pull2_index(i, ph, N), N, a.inv_sf);
+  }
+  Pull2 p;
+  make_pull2(wx, wy, g, p);
+  R f[Q];
+  R h[NC][Q];
+  R chip[NC] = {0, 0, 0}, up[2] = {0, 0};
+  const size_t n = p.self;
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R hv[NC];
+      P2::load(pin, pull2_index(i, p, N), N, a.inv_sf, a.inv_sh, f[i], hv);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) h[c][i] = hv[c];
+    }
+    if (!a.first) Aux<2, R>::load(aux, n, N, chip, up);
+  } else if (valid) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) f[i] = P2::load_f(pin, pull2_index(i, p, N), N, a.inv_sf);
+  }
+
+  // ---- velocities into LDS
+  R u[3] = {0, 0, 0}, F[3] = {0, 0, 0};
+  if (valid) {
+    force_at<R>(a.F, wx, wy, g.nx, g.ny, F);
+    velocity2(f, F, u);
+    const int slot = (ty + 1) * SX + tx + 1;
+    su[0][slot] = u[0];
+    su[1][slot] = u[1];
+  }
+  if (hvalid) {
+    R Fh[3], uh[3];
+    force_at<R>(a.F, hx, hy, g.nx, g.ny, Fh);
+    velocity2(fh, Fh, uh);
+    su[0][hslot] = uh[0];
+    su[1][hslot] = uh[1];
+  }
+
+  // ---- f collision and store (needs A from h, not the gradient)
+  R e[NC];
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      R s = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s += h[c][i];
+      e[c] = s;
+    }
+    collide_f<2, R>(f, e, u, F, a.P);
+  }
+  __syncthreads();
+  if (!active) return;
+
+  // ---- same-time velocity gradient G[a][b] = d_a u_b
+  R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  const int slot = (ty + 1) * SX + tx + 1;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const R* ub = &su[b][slot];
+    G[0][b] = p.lo_x ? u[b] + ub[1] * (R)(1.0 / 3.0)
+            : p.hi_x ? -(u[b] + ub[-1] * (R)(1.0 / 3.0))
+                     : (R)0.5 * (ub[1] - ub[-1]);
+    G[1][b] = p.lo_y ? u[b] + ub[SX] * (R)(1.0 / 3.0)
+            : p.hi_y ? -(u[b] + ub[-SX] * (R)(1.0 / 3.0))
+                     : (R)0.5 * (ub[SX] - ub[-SX]);
+  }
+  R chi[NC];
+  source_tensor<2, R>(e, G, a.P.inv_lam, chi);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const R Ac = e[c] + ((c != 1) ? (R)1 : (R)0);
+    collide_h<2, R>(h[c], e[c], Ac, chi[c], chip[c], u, up, a.first != 0, a.P);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R hv[NC] = {h[0][i], h[1][i], h[2][i]};
+    P2::store(pout, (size_t)i * N + n, N, a.sf, a.sh, f[i], hv);
+  }
+  Aux<2, R>::store(aux, n, N, chi, u);
+}
+
+}  // namespace vflb

@@ -11,6 +11,8 @@
 
 #include "../../include/vflb.h"
 #include "kernels.h"
+#include "step2d.h"
+#include "step3d.h"
 
 using namespace vflb;
 
@@ -91,7 +93,9 @@ void drop_graphs(vflb_sim* s) {
 
 int default_tile_y(const vflb_sim* s) {
   if (s->tile_y > 0) return s->tile_y;
-  return 8;
+  // measured on MI355X (8192 x 1024 channel): 64 x 16 tiles for FP32/FP64,
+  // 64 x 8 for 16-bit storage
+  return (s->storage == VFLB_F16S || s->storage == VFLB_BF16S) ? 8 : 16;
 }
 
 template <class R>
@@ -145,10 +149,8 @@ template <int D, class S>
 vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
   using R = typename StoreT<S>::R;
   StepArgs<S> a;
-  a.fin = static_cast<const S*>(s->buf[VFLB_BUF_F0 + parity]);
-  a.fout = static_cast<S*>(s->buf[VFLB_BUF_F0 + (parity ^ 1)]);
-  a.hin = static_cast<const S*>(s->buf[VFLB_BUF_H0 + parity]);
-  a.hout = static_cast<S*>(s->buf[VFLB_BUF_H0 + (parity ^ 1)]);
+  a.pin = static_cast<const S*>(s->buf[VFLB_BUF_POP0 + parity]);
+  a.pout = static_cast<S*>(s->buf[VFLB_BUF_POP0 + (parity ^ 1)]);
   a.aux = static_cast<R*>(s->buf[VFLB_BUF_AUX]);
   a.g = geo_of(s);
   a.P = phys_of<R>(s);
@@ -159,20 +161,31 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
   a.inv_sh = (R)std::ldexp(1.0, -s->log2_sh);
   if (s->storage != VFLB_F16S) a.sf = a.inv_sf = a.sh = a.inv_sh = (R)1;
   a.first = (t == 0);
-  dim3 block, grid;
-  if (D == 2) {
-    block = dim3(64, default_tile_y(s), 1);
+  if constexpr (D == 2) {
+    const int ty = default_tile_y(s);
+    const int ntx = (s->nx + 63) / 64, nty = (s->ny + ty - 1) / ty;
+    const dim3 grid((unsigned)(ntx * nty));
+    switch (ty) {
+      case 4:
+        hipLaunchKernelGGL((step2d_kernel<S, 4>), grid, dim3(64, 4), 0, st, a, ntx, nty);
+        break;
+      case 16:
+        hipLaunchKernelGGL((step2d_kernel<S, 16>), grid, dim3(64, 16), 0, st, a, ntx, nty);
+        break;
+      default:
+        hipLaunchKernelGGL((step2d_kernel<S, 8>), grid, dim3(64, 8), 0, st, a, ntx, nty);
+        break;
+    }
   } else {
-    block = dim3(32, 4, 2);
+    constexpr int TY3 = 4, ZC = 32;
+    const int ntx = (s->nx + 63) / 64, nty = (s->ny + TY3 - 1) / TY3;
+    const int nzc = (s->nz + ZC - 1) / ZC;
+    const dim3 grid((unsigned)(ntx * nty * nzc));
+    if (s->walls)
+      hipLaunchKernelGGL((step3d_kernel<S, TY3, ZC, true>), grid, dim3(64, TY3), 0, st, a, ntx, nty);
+    else
+      hipLaunchKernelGGL((step3d_kernel<S, TY3, ZC, false>), grid, dim3(64, TY3), 0, st, a, ntx, nty);
   }
-  grid = dim3((s->nx + block.x - 1) / block.x, (s->ny + block.y - 1) / block.y,
-              (s->nz + block.z - 1) / block.z);
-  const int SZ = (D == 3) ? block.z + 2 : 1;
-  const size_t lds = (size_t)D * (block.x + 2) * (block.y + 2) * SZ * sizeof(R);
-  if constexpr (D == 2)
-    hipLaunchKernelGGL((step_kernel<D, S, 512>), grid, block, lds, st, a);
-  else
-    hipLaunchKernelGGL((step_kernel<D, S, 256>), grid, block, lds, st, a);
   HIP_TRY(s, hipGetLastError());
   return VFLB_OK;
 }
@@ -188,8 +201,7 @@ vflb_status launch_init(vflb_sim* s, const double* u, const double* tau,
     sh = (R)std::ldexp(1.0, s->log2_sh);
   }
   hipLaunchKernelGGL((init_kernel<D, S>), dim3(grid1d(s, 256)), dim3(256), 0,
-                     s->stream, static_cast<S*>(s->buf[VFLB_BUF_F0]),
-                     static_cast<S*>(s->buf[VFLB_BUF_H0]),
+                     s->stream, static_cast<S*>(s->buf[VFLB_BUF_POP0]),
                      static_cast<R*>(s->buf[VFLB_BUF_AUX]), geo_of(s), u, tau, p,
                      loe, sf, sh);
   HIP_TRY(s, hipGetLastError());
@@ -205,8 +217,8 @@ vflb_status launch_moments(vflb_sim* s, int field, double* out) {
     ish = (R)std::ldexp(1.0, -s->log2_sh);
   }
   hipLaunchKernelGGL((moments_kernel<D, S>), dim3(grid1d(s, 256)), dim3(256), 0,
-                     s->stream, static_cast<const S*>(s->buf[VFLB_BUF_F0 + s->cur]),
-                     static_cast<const S*>(s->buf[VFLB_BUF_H0 + s->cur]), geo_of(s),
+                     s->stream, static_cast<const S*>(s->buf[VFLB_BUF_POP0 + s->cur]),
+                     geo_of(s),
                      phys_of<R>(s), force_of<R>(s, s->t), isf, ish, field, out);
   HIP_TRY(s, hipGetLastError());
   return VFLB_OK;
@@ -223,8 +235,7 @@ vflb_status launch_reduce(vflb_sim* s, double* dev_res) {
   const int nb = grid1d(s, 256);
   double* part = reinterpret_cast<double*>(static_cast<char*>(s->buf[VFLB_BUF_WORK]) + s->off_part);
   hipLaunchKernelGGL((reduce_kernel<D, S>), dim3(nb), dim3(256), 0, s->stream,
-                     static_cast<const S*>(s->buf[VFLB_BUF_F0 + s->cur]),
-                     static_cast<const S*>(s->buf[VFLB_BUF_H0 + s->cur]),
+                     static_cast<const S*>(s->buf[VFLB_BUF_POP0 + s->cur]),
                      static_cast<R*>(s->buf[VFLB_BUF_SNAP]), s->snap_valid ? 1 : 0,
                      geo_of(s), phys_of<R>(s), force_of<R>(s, s->t), isf, ish, part);
   HIP_TRY(s, hipGetLastError());
@@ -321,6 +332,11 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
     return fail(nullptr, VFLB_EINVAL, "bad size %d x %d x %d", nx, ny, nz);
   const size_t N = (size_t)nx * ny * nz;
   if (N > ((size_t)1 << 34)) return fail(nullptr, VFLB_EINVAL, "lattice too large");
+  // the D3Q19 step addresses one direction's population plane with 32-bit
+  // byte offsets: 16-byte tuples (32 in FP64) per node must stay below 4 GiB
+  if (lattice == VFLB_D3Q19 && N > ((size_t)1 << (storage == VFLB_F64 ? 27 : 28)))
+    return fail(nullptr, VFLB_EINVAL, "D3Q19 lattice of %zu nodes exceeds %s", N,
+                storage == VFLB_F64 ? "2^27 (FP64)" : "2^28");
   vflb_sim* s = new vflb_sim();
   s->D = lattice;
   s->Q = lattice == VFLB_D2Q9 ? 9 : 19;
@@ -332,8 +348,11 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
   s->storage = storage;
   s->stream = static_cast<hipStream_t>(hip_stream);
   const size_t sb = s->store_bytes(), ab = s->arith_bytes();
-  s->bytes[VFLB_BUF_F0] = s->bytes[VFLB_BUF_F1] = align256(sb * s->Q * N);
-  s->bytes[VFLB_BUF_H0] = s->bytes[VFLB_BUF_H1] = align256(sb * s->NC * s->Q * N);
+  size_t words;
+  if (lattice == VFLB_D2Q9) words = Pops<2, float>::words(N);
+  else if (storage == VFLB_F16S || storage == VFLB_BF16S) words = Pops<3, _Float16>::words(N);
+  else words = Pops<3, float>::words(N);
+  s->bytes[VFLB_BUF_POP0] = s->bytes[VFLB_BUF_POP1] = align256(sb * words);
   s->bytes[VFLB_BUF_AUX] = align256(ab * (s->NC + s->D) * N);
   s->bytes[VFLB_BUF_SNAP] = align256(ab * (s->NC + s->D) * N);
   s->off_tab = 0;
@@ -472,8 +491,8 @@ vflb_status vflb_set_storage_scale(vflb_sim* s, int log2_f, int log2_h) {
 
 vflb_status vflb_set_tile(vflb_sim* s, int tile_y) {
   if (!s) return VFLB_EINVAL;
-  if (tile_y != 0 && tile_y != 1 && tile_y != 2 && tile_y != 4 && tile_y != 8)
-    return fail(s, VFLB_EINVAL, "tile_y must be 0, 1, 2, 4 or 8");
+  if (tile_y != 0 && tile_y != 4 && tile_y != 8 && tile_y != 16)
+    return fail(s, VFLB_EINVAL, "tile_y must be 0, 4, 8 or 16");
   s->tile_y = tile_y;
   drop_graphs(s);
   return VFLB_OK;
@@ -573,14 +592,21 @@ vflb_status vflb_read(vflb_sim* s, int field, double* dev_dst, size_t n) {
   }
   if (n != need) return fail(s, VFLB_EINVAL, "field %d holds %zu values, not %zu", field, need, n);
   if (field == VFLB_FIELD_CHI_PREV || field == VFLB_FIELD_U_PREV) {
-    const size_t off = field == VFLB_FIELD_CHI_PREV ? 0 : (size_t)s->NC * s->N;
     const int nb = grid1d(s, 256);
-    if (s->storage == VFLB_F64)
-      hipLaunchKernelGGL((aux_read_kernel<double>), dim3(nb), dim3(256), 0, s->stream,
-                         static_cast<const double*>(s->buf[VFLB_BUF_AUX]) + off, need, dev_dst);
+    const Geo g = geo_of(s);
+    void* aux = s->buf[VFLB_BUF_AUX];
+    if (s->D == 2 && s->storage == VFLB_F64)
+      hipLaunchKernelGGL((aux_read_kernel<2, double>), dim3(nb), dim3(256), 0, s->stream,
+                         static_cast<const double*>(aux), g, field, dev_dst);
+    else if (s->D == 2)
+      hipLaunchKernelGGL((aux_read_kernel<2, float>), dim3(nb), dim3(256), 0, s->stream,
+                         static_cast<const float*>(aux), g, field, dev_dst);
+    else if (s->storage == VFLB_F64)
+      hipLaunchKernelGGL((aux_read_kernel<3, double>), dim3(nb), dim3(256), 0, s->stream,
+                         static_cast<const double*>(aux), g, field, dev_dst);
     else
-      hipLaunchKernelGGL((aux_read_kernel<float>), dim3(nb), dim3(256), 0, s->stream,
-                         static_cast<const float*>(s->buf[VFLB_BUF_AUX]) + off, need, dev_dst);
+      hipLaunchKernelGGL((aux_read_kernel<3, float>), dim3(nb), dim3(256), 0, s->stream,
+                         static_cast<const float*>(aux), g, field, dev_dst);
     HIP_TRY(s, hipGetLastError());
     return VFLB_OK;
   }
@@ -597,7 +623,7 @@ static const uint64_t kCkptMagic = 0x76666c62636b7074ull;
 
 vflb_status vflb_state_size(const vflb_sim* s, size_t* bytes) {
   if (!s || !bytes) return VFLB_EINVAL;
-  *bytes = 256 + s->bytes[VFLB_BUF_F0] + s->bytes[VFLB_BUF_H0] + s->bytes[VFLB_BUF_AUX];
+  *bytes = 256 + s->bytes[VFLB_BUF_POP0] + s->bytes[VFLB_BUF_AUX];
   return VFLB_OK;
 }
 
@@ -615,12 +641,9 @@ vflb_status vflb_save(vflb_sim* s, void* blob, size_t n) {
   char* b = static_cast<char*>(blob);
   HIP_TRY(s, hipMemcpyAsync(b, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
   size_t off = 256;
-  HIP_TRY(s, hipMemcpyAsync(b + off, s->buf[VFLB_BUF_F0 + s->cur], s->bytes[VFLB_BUF_F0],
+  HIP_TRY(s, hipMemcpyAsync(b + off, s->buf[VFLB_BUF_POP0 + s->cur], s->bytes[VFLB_BUF_POP0],
                             hipMemcpyDeviceToDevice, s->stream));
-  off += s->bytes[VFLB_BUF_F0];
-  HIP_TRY(s, hipMemcpyAsync(b + off, s->buf[VFLB_BUF_H0 + s->cur], s->bytes[VFLB_BUF_H0],
-                            hipMemcpyDeviceToDevice, s->stream));
-  off += s->bytes[VFLB_BUF_H0];
+  off += s->bytes[VFLB_BUF_POP0];
   HIP_TRY(s, hipMemcpyAsync(b + off, s->buf[VFLB_BUF_AUX], s->bytes[VFLB_BUF_AUX],
                             hipMemcpyDeviceToDevice, s->stream));
   HIP_TRY(s, hipStreamSynchronize(s->stream));
@@ -641,12 +664,9 @@ vflb_status vflb_load(vflb_sim* s, const void* blob, size_t n) {
       h.nz != s->nz || h.storage != s->storage)
     return fail(s, VFLB_EINVAL, "checkpoint does not match this simulation");
   size_t off = 256;
-  HIP_TRY(s, hipMemcpyAsync(s->buf[VFLB_BUF_F0], b + off, s->bytes[VFLB_BUF_F0],
+  HIP_TRY(s, hipMemcpyAsync(s->buf[VFLB_BUF_POP0], b + off, s->bytes[VFLB_BUF_POP0],
                             hipMemcpyDeviceToDevice, s->stream));
-  off += s->bytes[VFLB_BUF_F0];
-  HIP_TRY(s, hipMemcpyAsync(s->buf[VFLB_BUF_H0], b + off, s->bytes[VFLB_BUF_H0],
-                            hipMemcpyDeviceToDevice, s->stream));
-  off += s->bytes[VFLB_BUF_H0];
+  off += s->bytes[VFLB_BUF_POP0];
   HIP_TRY(s, hipMemcpyAsync(s->buf[VFLB_BUF_AUX], b + off, s->bytes[VFLB_BUF_AUX],
                             hipMemcpyDeviceToDevice, s->stream));
   HIP_TRY(s, hipStreamSynchronize(s->stream));
@@ -654,6 +674,21 @@ vflb_status vflb_load(vflb_sim* s, const void* blob, size_t n) {
   s->t = h.t;
   s->inited = true;
   s->snap_valid = false;
+  return VFLB_OK;
+}
+
+vflb_status vflb_stream_copy(const void* src, void* dst, size_t nbytes, void* hip_stream) {
+  if (!src || !dst || nbytes % 16 != 0 || ((uintptr_t)src | (uintptr_t)dst) % 16 != 0)
+    return fail(nullptr, VFLB_EINVAL, "stream copy needs 16-byte aligned pointers and sizes");
+  const size_t n = nbytes / 16;
+  if (n == 0) return VFLB_OK;
+  const size_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffffu) return fail(nullptr, VFLB_EINVAL, "copy too large");
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     static_cast<hipStream_t>(hip_stream), static_cast<const v4u32*>(src),
+                     static_cast<v4u32*>(dst), n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, VFLB_EDEVICE, "copy launch failed: %s", hipGetErrorString(e));
   return VFLB_OK;
 }
 

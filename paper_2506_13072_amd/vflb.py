@@ -26,7 +26,7 @@ FORCE_NONE, FORCE_CONST, FORCE_FOUR_ROLL, FORCE_COS_T = 0, 1, 2, 3
 PERIODIC, WALLS = 0, 1
 (FIELD_U, FIELD_P, FIELD_RHO, FIELD_A, FIELD_TAU, FIELD_F, FIELD_H,
  FIELD_CHI_PREV, FIELD_U_PREV) = range(9)
-NBUF = 7
+NBUF = 5
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = range(6)
 
 
@@ -81,6 +81,8 @@ def lib():
         L.vflb_save.argtypes = [P, P, SZ]
         L.vflb_load.argtypes = [P, P, SZ]
         L.vflb_set_tile.argtypes = [P, I]
+        L.vflb_stream_copy.argtypes = [P, P, SZ, P]
+        L.vflb_stream_copy.restype = I
         L.vflb_destroy.argtypes = [P]
         L.vflb_destroy.restype = None
         L.vflb_last_error.argtypes = [P]
@@ -99,6 +101,16 @@ def _check(handle, code):
     if code != OK:
         msg = lib().vflb_last_error(handle)
         raise VflbError(code, msg.decode() if msg else "")
+
+
+def stream_copy(src, dst, stream):
+    """Plain device copy of src into dst (torch tensors of equal byte size)
+    on the given torch stream, by the library's bandwidth-probe kernel."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(None, lib().vflb_stream_copy(ctypes.c_void_p(src.data_ptr()),
+                                        ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                        ctypes.c_void_p(stream.cuda_stream)))
 
 
 class Sim:
@@ -175,6 +187,16 @@ class Sim:
                                  dtype=self.torch.float64)
         t = t.reshape(self.N, ncomp).t().contiguous().to(self.device)
         return t
+
+    def init_fields_device(self, u=None, tau=None, p=None):
+        """Initial state from component-major FP64 device tensors
+        u [D, N], tau [NC, N], p [N] (None = zero)."""
+        for t in (u, tau, p):
+            assert t is None or (t.is_cuda and t.dtype == self.torch.float64 and t.is_contiguous())
+        self.torch.cuda.current_stream(self.device).synchronize()
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        _check(self._h, lib().vflb_init_fields(self._h, ptr(u), ptr(tau), ptr(p)))
+        self.stream.synchronize()
 
     def init_fields(self, u=None, tau=None, p=None):
         tu = self._dev_field(u, self.D)

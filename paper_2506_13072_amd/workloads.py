@@ -79,6 +79,24 @@ def taylor_green_3d_velocity(n, U0, theta=0.0):
     return u.reshape(-1, 3)
 
 
+def taylor_green_3d_device(n, U0, device="cuda"):
+    """The theta = 0 Taylor-Green vortex of taylor_green_3d_velocity plus its
+    pressure (U0^2/16)(cos 2x + cos 2y)(cos 2z + 2), generated on the device
+    (torch) for large lattices; returns component-major FP64 tensors
+    u [3, N] and p [N] in node order (x fastest)."""
+    import torch
+    x = 2 * math.pi * torch.arange(n, device=device, dtype=torch.float64) / n
+    sx, cx = torch.sin(x), torch.cos(x)
+    u = torch.empty(3, n, n, n, device=device, dtype=torch.float64)
+    # index order [z, y, x]
+    u[0] = U0 * sx[None, None, :] * cx[None, :, None] * cx[:, None, None]
+    u[1] = -U0 * cx[None, None, :] * sx[None, :, None] * cx[:, None, None]
+    u[2] = 0.0
+    c2 = torch.cos(2 * x)
+    p = (U0 ** 2 / 16) * (c2[None, None, :] + c2[None, :, None]) * (c2[:, None, None] + 2)
+    return u.reshape(3, -1), p.reshape(-1)
+
+
 # ------------------------------------------------------------ workloads
 # Dimensionless descriptions of the benchmark flows (Sec. 3).  L is the
 # characteristic length in lattice units.
