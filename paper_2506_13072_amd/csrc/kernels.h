@@ -5,10 +5,12 @@
 // gives their placement in HBM.  chi(t-1) and u(t-1) for the backward
 // difference of the source term are read and written in place by the
 // owning node only.
-// The step kernel pulls f and h, forms the moments, collides f (Sec. 2.2),
-// builds u on a tile plus a one-node halo in LDS for the same-time
-// velocity gradient, then forms the Oldroyd-B source and collides h
-// (Sec. 2.3).  f and h are written to the other buffer of a ping-pong pair.
+// This file holds what the step kernels (step2d.h, step3d.h) share, and
+// the initialisation, moment, reduction and copy kernels.  A step pulls f
+// and h, forms the moments, collides f (Sec. 2.2), builds u on a tile plus
+// a one-node halo in LDS for the same-time velocity gradient, then forms
+// the Oldroyd-B source and collides h (Sec. 2.3); f and h are written to the
+// other buffer of a ping-pong pair.
 #pragma once
 
 #include "layout.h"
@@ -46,10 +48,22 @@ __device__ inline size_t node_of(int x, int y, int z, const Geo& g) {
   return ((size_t)z * g.ny + y) * g.nx + x;
 }
 
+// Tuple index of population i at node n.  D2Q9: plane i, i*N + n.  D3Q19:
+// the rest population has plane 0 (index n); the two members of an opposite
+// pair (2k-1, 2k) share one double-width plane starting at (2k-1) N, where
+// they sit side by side (2n + 0 and 2n + 1), so the lane pair that owns a
+// node reads and writes adjacent tuples.
+template <int D>
+__host__ __device__ inline size_t tuple_of(int i, size_t n, size_t N) {
+  if (D == 2 || i == 0) return (size_t)i * N + n;
+  const int s = (i + 1) & 1;  // 0 for the odd member, 1 for the even one
+  return (size_t)(i - s) * N + 2 * n + s;
+}
+
 // Index of the post-collision value that streams into direction i of node
 // (x, y, z): population i at x - c_i (periodic wrap), or population
 // opp(i) at the node itself when x - c_i lies beyond a wall (halfway
-// bounce-back).  The returned index includes the plane offset.
+// bounce-back).  The returned value is a tuple index (tuple_of).
 template <int D>
 __device__ inline size_t pull_index(int i, int x, int y, int z, const Geo& g) {
   int s[3] = {x - cdir<D>(i, 0), y - cdir<D>(i, 1), z - cdir<D>(i, 2)};
@@ -64,8 +78,8 @@ __device__ inline size_t pull_index(int i, int x, int y, int z, const Geo& g) {
         s[a] = s[a] < 0 ? n[a] - 1 : 0;
     }
   }
-  if (bounce) return (size_t)Lat<D>::opp(i) * g.N + node_of(x, y, z, g);
-  return (size_t)i * g.N + node_of(s[0], s[1], s[2], g);
+  if (bounce) return tuple_of<D>(Lat<D>::opp(i), node_of(x, y, z, g), g.N);
+  return tuple_of<D>(i, node_of(s[0], s[1], s[2], g), g.N);
 }
 
 template <class R>
@@ -96,149 +110,6 @@ __device__ inline bool wrap_coord(int& c, int n, bool wall) {
 }
 
 // --------------------------------------------------------------- step
-template <int D, class S, int MAXT>
-__global__ void __launch_bounds__(MAXT) step_kernel(StepArgs<S> a) {
-  using St = StoreT<S>;
-  using R = typename St::R;
-  using L = Lat<D>;
-  constexpr int Q = L::Q, NC = L::NC;
-  extern __shared__ unsigned char smem_raw[];
-  R* su = reinterpret_cast<R*>(smem_raw);
-
-  const Geo& g = a.g;
-  const int TX = blockDim.x, TY = blockDim.y, TZ = blockDim.z;
-  const int SX = TX + 2, SY = TY + 2, SZ = (D == 3) ? TZ + 2 : 1;
-  const int nslot = SX * SY * SZ;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
-  const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
-  const int tid = (tz * TY + ty) * TX + tx;
-  const int nthr = TX * TY * TZ;
-  const int x = x0 + tx, y = y0 + ty, z = (D == 3) ? z0 + tz : 0;
-  const bool active = x < g.nx && y < g.ny && z < g.nz;
-  const int slot = (((D == 3) ? tz + 1 : 0) * SY + ty + 1) * SX + tx + 1;
-
-  // node whose velocity this thread places in its own slot (ragged tails
-  // wrap periodically so that the last nodes see their true neighbours)
-  int wx = x, wy = y, wz = z;
-  bool valid = wrap_coord(wx, g.nx, g.walls & 1) && wrap_coord(wy, g.ny, g.walls & 2);
-  if (D == 3) valid = valid && wrap_coord(wz, g.nz, g.walls & 4);
-
-  using P = Pops<D, S>;
-  R f[Q];
-  R h[NC][Q];
-  R chip[NC], up[3] = {0, 0, 0};
-  const size_t n = active ? node_of(x, y, z, g) : 0;
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      R hv[NC];
-      P::load(a.pin, pull_index<D>(i, wx, wy, wz, g), g.N, a.inv_sf, a.inv_sh, f[i], hv);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) h[c][i] = hv[c];
-    }
-    if (!a.first) Aux<D, R>::load(a.aux, n, g.N, chip, up);
-  } else if (valid) {
-#pragma unroll
-    for (int i = 1; i < Q; ++i)
-      f[i] = P::load_f(a.pin, pull_index<D>(i, wx, wy, wz, g), g.N, a.inv_sf);
-  }
-
-  R u[3] = {0, 0, 0}, F[3];
-  R e[NC];
-  if (valid) {
-    force_at<R>(a.F, wx, wy, g.nx, g.ny, F);
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-      R s = 0;
-#pragma unroll
-      for (int i = 1; i < Q; ++i)
-        if (cdir<D>(i, b) != 0) s += (R)cdir<D>(i, b) * f[i];
-      u[b] = s + (R)0.5 * F[b];
-      su[b * nslot + slot] = u[b];
-    }
-  }
-  if (active) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      R s = 0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) s += h[c][i];
-      e[c] = s;
-    }
-    collide_f<D, R>(f, e, u, F, a.P);
-  }
-
-  // velocity on the halo slots of the tile
-  for (int s = tid; s < nslot; s += nthr) {
-    const int hx = s % SX, hy = (s / SX) % SY, hz = s / (SX * SY);
-    const bool inner = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY &&
-                       (D == 2 || (hz >= 1 && hz <= TZ));
-    if (inner) continue;
-    int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = (D == 3) ? z0 + hz - 1 : 0;
-    bool ok = wrap_coord(gx, g.nx, g.walls & 1) && wrap_coord(gy, g.ny, g.walls & 2);
-    if (D == 3) ok = ok && wrap_coord(gz, g.nz, g.walls & 4);
-    if (!ok) continue;
-    R Fh[3];
-    force_at<R>(a.F, gx, gy, g.nx, g.ny, Fh);
-    R fh[Q];
-#pragma unroll
-    for (int i = 1; i < Q; ++i)
-      fh[i] = Pops<D, S>::load_f(a.pin, pull_index<D>(i, gx, gy, gz, g), g.N, a.inv_sf);
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-      R sm = 0;
-#pragma unroll
-      for (int i = 1; i < Q; ++i)
-        if (cdir<D>(i, b) != 0) sm += (R)cdir<D>(i, b) * fh[i];
-      su[b * nslot + s] = sm + (R)0.5 * Fh[b];
-    }
-  }
-  __syncthreads();
-  if (!active) return;
-
-  // same-time velocity gradient G[a][b] = d_a u_b
-  R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  const int coord[3] = {x, y, z};
-  const int nn[3] = {g.nx, g.ny, g.nz};
-  const int stride[3] = {1, SX, SX * SY};
-#pragma unroll
-  for (int ax = 0; ax < D; ++ax) {
-    const bool wall = g.walls & (1 << ax);
-    const bool lo = wall && coord[ax] == 0;
-    const bool hi = wall && coord[ax] == nn[ax] - 1;
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-      const R* ub = su + b * nslot + slot;
-      R d;
-      if (lo)
-        d = u[b] + ub[stride[ax]] * (R)(1.0 / 3.0);
-      else if (hi)
-        d = -(u[b] + ub[-stride[ax]] * (R)(1.0 / 3.0));
-      else
-        d = (R)0.5 * (ub[stride[ax]] - ub[-stride[ax]]);
-      G[ax][b] = d;
-    }
-  }
-  R chi[NC];
-  source_tensor<D, R>(e, G, a.P.inv_lam, chi);
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const R Ac = e[c] + ((L::ca(c) == L::cb(c)) ? (R)1 : (R)0);
-    collide_h<D, R>(h[c], e[c], Ac, chi[c], chip[c], u, up, a.first != 0, a.P);
-  }
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    R hv[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) hv[c] = h[c][i];
-    Pops<D, S>::store(a.pout, (size_t)i * g.N + n, g.N, a.sf, a.sh, f[i], hv);
-  }
-  Aux<D, R>::store(a.aux, n, g.N, chi, u);
-}
-
-// --------------------------------------------------- shared node moments
-// Pre-collision moments of one node: pulls f and h, returns u, e = A - I,
-// tau, p and the pulled populations.
 template <int D, class S>
 struct NodeMoments {
   using R = typename StoreT<S>::R;

@@ -1,15 +1,17 @@
 // layout.h -- where populations and auxiliary fields live in HBM.
 //
 // One buffer per ping/pong side holds all populations of the lattice.  A
-// "tuple index" t = i*N + n names direction i at node n.
+// tuple index t names direction i at node n: t = i*N + n for D2Q9; for
+// D3Q19 the members of an opposite pair interleave node by node
+// (tuple_of in kernels.h).
 //
 //  D2Q9:  tuples [Q][N] of (f_i, h_xx,i, h_xy,i, h_yy,i).  f and the three
 //         conformation populations of one direction stream from the same
 //         source node, so a pull is one aligned vector load (16 bytes in
 //         FP32, 8 in 16-bit storage) and a store one vector store.
-//  D3Q19: FP32/FP64 tuples (f, h_xx, h_yy, h_zz) [Q][N] followed by tuples
-//         (h_xy, h_xz, h_yz) [Q][N]; 16-bit storage one 8-wide tuple
-//         (f, h_xx, h_yy, h_zz, h_xy, h_xz, h_yz, unused) [Q][N].
+//  D3Q19: f [Q N], then (h_xx, h_yy, h_zz, h_xy) tuples [Q N], then
+//         (h_xz, h_yz) tuples [Q N], all three indexed by the same tuple
+//         index.
 //
 // Auxiliary state chi(t-1), u(t-1):
 //  D2Q9:  chi [N][3] then u [N][2] (one 12-byte and one 8-byte access).
@@ -101,117 +103,38 @@ template <class S> struct Pops<2, S> {
   }
 };
 
-// D3Q19, FP32/FP64: A tuples [Q][N] of (f, h_xx, h_yy, h_zz) followed by
-// B tuples [Q][N] of (h_xy, h_xz, h_yz): one 4-wide and one 3-wide access
-// per pulled direction, no padding.
-template <class S> struct Pops3Wide {
-  using R = S;
+// D3Q19: f [Q N], then tuples (h_xx, h_yy, h_zz, h_xy) [Q N], then tuples
+// (h_xz, h_yz) [Q N].  f sits alone so that forming u ahead of a plane
+// touches only f cache lines; per pulled direction the step issues one
+// 4-byte, one 16-byte and one 8-byte access (FP32; twice that in FP64, half
+// in 16-bit storage).
+template <class S> struct Pops3Split {
+  using St = StoreT<S>;
+  using R = typename St::R;
   static constexpr int Q = 19, NC = 6;
-  typedef S s4 __attribute__((ext_vector_type(4)));
-  struct s3 { S a, b, c; };
   __host__ __device__ static size_t words(size_t N) { return (size_t)7 * Q * N; }
-  __device__ static void load(const S* p, size_t t, size_t N, R, R, R& f, R* h) {
-    const s4 a = reinterpret_cast<const s4*>(p)[t];
-    const s3 b = reinterpret_cast<const s3*>(p + (size_t)4 * Q * N)[t];
-    f = a.x; h[0] = a.y; h[1] = a.z; h[2] = a.w;
-    h[3] = b.a; h[4] = b.b; h[5] = b.c;
+  __device__ static size_t h4(size_t N) { return (size_t)Q * N; }
+  __device__ static size_t h2(size_t N) { return (size_t)5 * Q * N; }
+  __device__ static void load(const S* p, size_t t, size_t N, R isf, R ish, R& f, R* h) {
+    f = St::ld(p, t, isf);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) h[c] = St::ld(p, h4(N) + 4 * t + c, ish);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) h[4 + c] = St::ld(p, h2(N) + 2 * t + c, ish);
   }
-  __device__ static R load_f(const S* p, size_t t, size_t, R) { return p[4 * t]; }
-  __device__ static void store(S* p, size_t t, size_t N, R, R, R f, const R* h) {
-    const s4 a = {f, h[0], h[1], h[2]};
-    __builtin_nontemporal_store(a, reinterpret_cast<s4*>(p) + t);
-    S* b = p + (size_t)4 * Q * N + 3 * t;
-    stream_store(b, h[3]);
-    stream_store(b + 1, h[4]);
-    stream_store(b + 2, h[5]);
+  __device__ static R load_f(const S* p, size_t t, size_t, R isf) { return St::ld(p, t, isf); }
+  __device__ static void store(S* p, size_t t, size_t N, R sf, R sh, R f, const R* h) {
+    St::st(p, t, f, sf);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) St::st(p, h4(N) + 4 * t + c, h[c], sh);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) St::st(p, h2(N) + 2 * t + c, h[4 + c], sh);
   }
 };
-// Plane-based access used by the step kernel: the base of direction i's
-// plane is uniform across the wavefront and the node offset a 32-bit byte
-// offset, so loads use the scalar-base + 32-bit-offset addressing form
-// (no per-lane 64-bit address arithmetic).  Valid while one plane holds
-// less than 4 GiB.
-template <class S, int QQ> struct Plane3 {
-  typedef S s4 __attribute__((ext_vector_type(4)));
-  struct s3 { S a, b, c; };
-  __device__ static void load(const S* p, int i, uint32_t node, size_t N, S& f, S* h) {
-    const char* A = reinterpret_cast<const char*>(p) + (size_t)i * N * (4 * sizeof(S));
-    const char* B = reinterpret_cast<const char*>(p) + (size_t)QQ * N * (4 * sizeof(S)) +
-                    (size_t)i * N * (3 * sizeof(S));
-    const s4 a = *reinterpret_cast<const s4*>(A + node * (uint32_t)(4 * sizeof(S)));
-    const s3 b = *reinterpret_cast<const s3*>(B + node * (uint32_t)(3 * sizeof(S)));
-    f = a.x; h[0] = a.y; h[1] = a.z; h[2] = a.w;
-    h[3] = b.a; h[4] = b.b; h[5] = b.c;
-  }
-  __device__ static S load_f(const S* p, int i, uint32_t node, size_t N) {
-    const char* A = reinterpret_cast<const char*>(p) + (size_t)i * N * (4 * sizeof(S));
-    return *reinterpret_cast<const S*>(A + node * (uint32_t)(4 * sizeof(S)));
-  }
-  __device__ static void store(S* p, int i, uint32_t node, size_t N, S f, const S* h) {
-    char* A = reinterpret_cast<char*>(p) + (size_t)i * N * (4 * sizeof(S));
-    char* B = reinterpret_cast<char*>(p) + (size_t)QQ * N * (4 * sizeof(S)) +
-              (size_t)i * N * (3 * sizeof(S));
-    const s4 a = {f, h[0], h[1], h[2]};
-    __builtin_nontemporal_store(a, reinterpret_cast<s4*>(A + node * (uint32_t)(4 * sizeof(S))));
-    S* b = reinterpret_cast<S*>(B + node * (uint32_t)(3 * sizeof(S)));
-    stream_store(b, h[3]);
-    stream_store(b + 1, h[4]);
-    stream_store(b + 2, h[5]);
-  }
-};
-
-template <> struct Pops<3, float> : Pops3Wide<float> {};
-template <> struct Pops<3, double> : Pops3Wide<double> {};
-
-// D3Q19, 16-bit: one 16-byte tuple [Q][N] of (f, h_xx, h_yy, h_zz, h_xy,
-// h_xz, h_yz, unused) per direction and node: a pull is one aligned 16-byte
-// load (the unused eighth slot costs 2 of 16 bytes).
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-template <> struct Pops<3, _Float16> {
-  using R = float;
-  static constexpr int Q = 19, NC = 6;
-  __host__ __device__ static size_t words(size_t N) { return (size_t)8 * Q * N; }
-  __device__ static void load(const _Float16* p, size_t t, size_t, R isf, R ish, R& f, R* h) {
-    const f16x8 q = reinterpret_cast<const f16x8*>(p)[t];
-    f = (float)q[0] * isf;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) h[c] = (float)q[1 + c] * ish;
-  }
-  __device__ static R load_f(const _Float16* p, size_t t, size_t, R isf) {
-    return (float)p[8 * t] * isf;
-  }
-  __device__ static void store(_Float16* p, size_t t, size_t, R sf, R sh, R f, const R* h) {
-    f16x8 q;
-    q[0] = (_Float16)(f * sf);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) q[1 + c] = (_Float16)(h[c] * sh);
-    q[7] = (_Float16)0.0f;
-    __builtin_nontemporal_store(q, reinterpret_cast<f16x8*>(p) + t);
-  }
-};
-template <> struct Pops<3, bf16_t> {
-  using R = float;
-  static constexpr int Q = 19, NC = 6;
-  __host__ __device__ static size_t words(size_t N) { return (size_t)8 * Q * N; }
-  __device__ static void load(const bf16_t* p, size_t t, size_t, R, R, R& f, R* h) {
-    const u16x8 q = reinterpret_cast<const u16x8*>(p)[t];
-    f = bf16_to_f32(q[0]);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) h[c] = bf16_to_f32(q[1 + c]);
-  }
-  __device__ static R load_f(const bf16_t* p, size_t t, size_t, R) {
-    return bf16_to_f32(reinterpret_cast<const uint16_t*>(p)[8 * t]);
-  }
-  __device__ static void store(bf16_t* p, size_t t, size_t, R, R, R f, const R* h) {
-    u16x8 q;
-    q[0] = f32_to_bf16(f);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) q[1 + c] = f32_to_bf16(h[c]);
-    q[7] = 0;
-    __builtin_nontemporal_store(q, reinterpret_cast<u16x8*>(p) + t);
-  }
-};
+template <> struct Pops<3, float> : Pops3Split<float> {};
+template <> struct Pops<3, double> : Pops3Split<double> {};
+template <> struct Pops<3, _Float16> : Pops3Split<_Float16> {};
+template <> struct Pops<3, bf16_t> : Pops3Split<bf16_t> {};
 
 // auxiliary state
 template <int D, class R> struct Aux;

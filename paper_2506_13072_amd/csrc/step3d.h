@@ -1,114 +1,129 @@
 // step3d.h -- the fused D3Q19 step for gfx950, marching along z.
 //
-// A workgroup of TY wavefronts owns a 64 x TY column of the lattice and
-// walks a chunk of ZC planes in z.  The velocity of three consecutive planes
-// (z-1, z, z+1) plus a one-node ring in x and y lives in LDS, so the
-// same-time gradient needs no halo in z: per plane the workgroup pulls the
-// 18 moving f populations of plane z+1 (own nodes and the x/y ring) to
-// form u(z+1), then collides plane z.  Only the first plane of a chunk
-// costs an extra u plane.
+// Two lanes own one node.  The even lane holds the rest population and the
+// odd member (2k-1) of each opposite pair, the odd lane the even member
+// (2k): lane s sees pair k with velocity (1 - 2s) c_{2k-1}.  The pair's
+// partial moments meet through one DPP lane swap each, so a lane keeps ten
+// populations of f and h (about 70 values) and two workgroups per CU stay
+// resident (two wavefronts per SIMD), one computing while the other waits
+// on HBM.  In HBM the two members of a pair sit side
+// by side (tuple_of), so a pair of lanes reads and writes adjacent tuples.
 //
-// Register budget: a node's 133 populations are not held at once.  Pass 1
-// pulls every direction and keeps the moments; pass 2 pulls each direction
-// again (a cache hit), collides and stores it.  Loads address a uniform
-// per-direction plane base with a 32-bit node offset.
+// A workgroup of TY wavefronts owns a 32 x TY column of nodes and walks a
+// chunk of ZC planes in z.  The velocity of three consecutive planes
+// (z-1, z, z+1) plus a one-node ring in x and y lives in LDS, so the
+// same-time gradient needs no halo in z.  Per plane the workgroup pulls the
+// moving f of plane z+1 (own nodes and the x/y ring) to form u(z+1); a lane
+// keeps the f it pulled for its own node and collides it one plane later,
+// so f crosses HBM once and h is pulled once, straight into registers.
+// Loads and stores address a uniform per-pair plane base with a 32-bit
+// offset.
 #pragma once
 
 #include "kernels.h"
 
 namespace vflb {
 
-// 16-bit storage: one 8-wide 16-byte tuple per direction and node
-template <class S> struct Plane3x8 {
-  using R = float;
-  __device__ static float unpack1(uint16_t b);
-  __device__ static void unpack8(uint4 q, R* v);
-  __device__ static uint4 pack8(const R* v);
-  __device__ static void load(const S* p, int i, uint32_t node, size_t N, R isf, R ish, R& f,
-                              R* h) {
-    const char* A = reinterpret_cast<const char*>(p) + (size_t)i * N * 16;
-    R v[8];
-    unpack8(*reinterpret_cast<const uint4*>(A + node * 16u), v);
-    f = v[0] * isf;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) h[c] = v[1 + c] * ish;
+// conversion between the storage type and the arithmetic type (scale: the
+// exact power of two of FP16 storage; unused otherwise)
+template <class S> struct Cvt;
+template <> struct Cvt<double> {
+  using V = double;
+  __device__ static double in(V v, double) { return v; }
+  __device__ static V out(double v, double) { return v; }
+};
+template <> struct Cvt<float> {
+  using V = float;
+  __device__ static float in(V v, float) { return v; }
+  __device__ static V out(float v, float) { return v; }
+};
+template <> struct Cvt<_Float16> {
+  using V = _Float16;
+  __device__ static float in(V v, float inv_scale) { return (float)v * inv_scale; }
+  __device__ static V out(float v, float scale) { return (_Float16)(v * scale); }
+};
+template <> struct Cvt<bf16_t> {
+  using V = uint16_t;
+  __device__ static float in(V v, float) { return bf16_to_f32(v); }
+  __device__ static V out(float v, float) { return f32_to_bf16(v); }
+};
+
+// Access to the D3Q19 population buffer by pair plane: k = 0 is the rest
+// plane (offset o = node), k = 1..9 the plane of directions (2k-1, 2k)
+// (offset o = 2 node + member).  f, the (xx, yy, zz, xy) 4-tuples and the
+// (xz, yz) 2-tuples follow one another, each Q N tuples long.
+template <class S> struct Pair3 {
+  using C = Cvt<S>;
+  using V = typename C::V;
+  using R = typename StoreT<S>::R;
+  typedef V v4 __attribute__((ext_vector_type(4)));
+  typedef V v2 __attribute__((ext_vector_type(2)));
+  static constexpr int Q = 19;
+  __device__ static size_t t0(int k, size_t N) { return k == 0 ? 0 : (size_t)(2 * k - 1) * N; }
+  __device__ static const char* fb(const S* p, int k, size_t N) {
+    return reinterpret_cast<const char*>(reinterpret_cast<const V*>(p) + t0(k, N));
   }
-  __device__ static R load_f(const S* p, int i, uint32_t node, size_t N, R isf) {
-    const char* A = reinterpret_cast<const char*>(p) + (size_t)i * N * 16;
-    return unpack1(*reinterpret_cast<const uint16_t*>(A + node * 16u)) * isf;
+  __device__ static const char* h4b(const S* p, int k, size_t N) {
+    return reinterpret_cast<const char*>(reinterpret_cast<const V*>(p) + (size_t)Q * N +
+                                         4 * t0(k, N));
   }
-  __device__ static void store(S* p, int i, uint32_t node, size_t N, R sf, R sh, R f,
-                               const R* h) {
-    char* A = reinterpret_cast<char*>(p) + (size_t)i * N * 16;
-    const R v[8] = {f * sf, h[0] * sh, h[1] * sh, h[2] * sh, h[3] * sh, h[4] * sh, h[5] * sh, 0};
-    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
-    const uint4 q = pack8(v);
-    const u4v qv = {q.x, q.y, q.z, q.w};
-    __builtin_nontemporal_store(qv, reinterpret_cast<u4v*>(A + node * 16u));
+  __device__ static const char* h2b(const S* p, int k, size_t N) {
+    return reinterpret_cast<const char*>(reinterpret_cast<const V*>(p) + (size_t)5 * Q * N +
+                                         2 * t0(k, N));
+  }
+  __device__ static R load_f(const S* p, int k, uint32_t o, size_t N, R isf) {
+    return C::in(*reinterpret_cast<const V*>(fb(p, k, N) + o * (uint32_t)sizeof(V)), isf);
+  }
+  __device__ static void load_h(const S* p, int k, uint32_t o, size_t N, R ish, R* h) {
+    const v4 a = *reinterpret_cast<const v4*>(h4b(p, k, N) + o * (uint32_t)sizeof(v4));
+    const v2 b = *reinterpret_cast<const v2*>(h2b(p, k, N) + o * (uint32_t)sizeof(v2));
+    h[0] = C::in(a.x, ish); h[1] = C::in(a.y, ish); h[2] = C::in(a.z, ish);
+    h[3] = C::in(a.w, ish); h[4] = C::in(b.x, ish); h[5] = C::in(b.y, ish);
+  }
+  __device__ static void store(S* p, int k, uint32_t o, size_t N, R sf, R sh, R f, const R* h) {
+    const v4 a = {C::out(h[0], sh), C::out(h[1], sh), C::out(h[2], sh), C::out(h[3], sh)};
+    const v2 b = {C::out(h[4], sh), C::out(h[5], sh)};
+    __builtin_nontemporal_store(
+        C::out(f, sf),
+        reinterpret_cast<V*>(const_cast<char*>(fb(p, k, N)) + o * (uint32_t)sizeof(V)));
+    __builtin_nontemporal_store(
+        a, reinterpret_cast<v4*>(const_cast<char*>(h4b(p, k, N)) + o * (uint32_t)sizeof(v4)));
+    __builtin_nontemporal_store(
+        b, reinterpret_cast<v2*>(const_cast<char*>(h2b(p, k, N)) + o * (uint32_t)sizeof(v2)));
   }
 };
-template <> __device__ inline float Plane3x8<_Float16>::unpack1(uint16_t b) {
-  return (float)__builtin_bit_cast(_Float16, b);
+
+// value of the partner lane (lanes 2j and 2j + 1): DPP quad permutation
+// [1, 0, 3, 2]; both lanes of a pair are always active together
+__device__ inline float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
-template <> __device__ inline float Plane3x8<bf16_t>::unpack1(uint16_t b) { return bf16_to_f32(b); }
-template <> __device__ inline void Plane3x8<_Float16>::unpack8(uint4 q, float* v) {
-  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[2 * k] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[k] & 0xffffu));
-    v[2 * k + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w[k] >> 16));
-  }
+__device__ inline double pair_swap(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0xB1, 0xF, 0xF,
+                                                            false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0xB1,
+                                                            0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-template <> __device__ inline void Plane3x8<bf16_t>::unpack8(uint4 q, float* v) {
-  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[2 * k] = __uint_as_float(w[k] << 16);
-    v[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
-  }
-}
-template <> __device__ inline uint4 Plane3x8<_Float16>::pack8(const float* v) {
-  uint32_t w[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    w[k] = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v[2 * k]) |
-           ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v[2 * k + 1]) << 16);
-  return make_uint4(w[0], w[1], w[2], w[3]);
-}
-template <> __device__ inline uint4 Plane3x8<bf16_t>::pack8(const float* v) {
-  uint32_t w[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    w[k] = (uint32_t)f32_to_bf16(v[2 * k]) | ((uint32_t)f32_to_bf16(v[2 * k + 1]) << 16);
-  return make_uint4(w[0], w[1], w[2], w[3]);
+// sum over the pair: the same bits in both lanes (addition commutes)
+template <class R>
+__device__ inline R pair_sum(R v) {
+  return v + pair_swap(v);
 }
 
-// FP32/FP64 plane access with the same signature as Plane3x8
-template <class S> struct Plane3W {
-  using R = S;
-  __device__ static void load(const S* p, int i, uint32_t node, size_t N, R, R, R& f, R* h) {
-    Plane3<S, 19>::load(p, i, node, N, f, h);
-  }
-  __device__ static R load_f(const S* p, int i, uint32_t node, size_t N, R) {
-    return Plane3<S, 19>::load_f(p, i, node, N);
-  }
-  __device__ static void store(S* p, int i, uint32_t node, size_t N, R, R, R f, const R* h) {
-    Plane3<S, 19>::store(p, i, node, N, f, h);
-  }
-};
-template <class S> struct PlaneSel { using T = Plane3W<S>; };
-template <> struct PlaneSel<_Float16> { using T = Plane3x8<_Float16>; };
-template <> struct PlaneSel<bf16_t> { using T = Plane3x8<bf16_t>; };
-
-// pull offsets of one node: per axis the 32-bit node delta to the source
-// for c = +1, 0, -1 (periodic wrap folded in) and the wall flags
-struct Pull3 {
-  int d[3][3];
-  bool lo[3], hi[3];
+// Pull geometry of one node as seen by the lane of member s.  A direction
+// of this lane with odd-member velocity component c_a = +1 streams from the
+// neighbour at node delta dm[a] (wm[a]: a wall lies there, bounce back),
+// c_a = -1 from dp[a] (wp[a]); periodic wrap is folded into the deltas.
+struct PairPull {
+  int dm[3], dp[3];
+  bool wm[3], wp[3];
+  bool lo[3], hi[3];  // node next to a wall at coordinate 0 / n - 1
   uint32_t self;
 };
 
-__device__ inline void make_pull3(int x, int y, int z, const Geo& g, Pull3& p) {
+__device__ inline void make_pair_pull(int x, int y, int z, int s, const Geo& g, PairPull& p) {
   const int c[3] = {x, y, z}, n[3] = {g.nx, g.ny, g.nz};
   const int stride[3] = {1, g.nx, g.nx * g.ny};
 #pragma unroll
@@ -116,91 +131,50 @@ __device__ inline void make_pull3(int x, int y, int z, const Geo& g, Pull3& p) {
     const bool wall = g.walls & (1 << a);
     p.lo[a] = wall && c[a] == 0;
     p.hi[a] = wall && c[a] == n[a] - 1;
-    p.d[a][0] = (c[a] == 0 ? n[a] - 1 : -1) * stride[a];  // source at x - 1
-    p.d[a][1] = 0;
-    p.d[a][2] = (c[a] == n[a] - 1 ? 1 - n[a] : 1) * stride[a];  // source at x + 1
+    const int from_minus = (c[a] == 0 ? n[a] - 1 : -1) * stride[a];     // source at x - 1
+    const int from_plus = (c[a] == n[a] - 1 ? 1 - n[a] : 1) * stride[a];  // source at x + 1
+    p.dm[a] = s ? from_plus : from_minus;
+    p.dp[a] = s ? from_minus : from_plus;
+    p.wm[a] = s ? p.hi[a] : p.lo[a];
+    p.wp[a] = s ? p.lo[a] : p.hi[a];
   }
   p.self = (uint32_t)(((size_t)z * g.ny + y) * g.nx + x);
 }
 
-template <bool WALLS>
-__device__ inline bool pull3_bounce(int i, const Pull3& p) {
-  if (!WALLS) return false;
-  const int cx = Lat<3>::cx(i), cy = Lat<3>::cy(i), cz = Lat<3>::cz(i);
-  return (cx > 0 && p.lo[0]) || (cx < 0 && p.hi[0]) || (cy > 0 && p.lo[1]) ||
-         (cy < 0 && p.hi[1]) || (cz > 0 && p.lo[2]) || (cz < 0 && p.hi[2]);
-}
-
-__device__ inline uint32_t pull3_node(int i, const Pull3& p) {
-  const int cx = Lat<3>::cx(i), cy = Lat<3>::cy(i), cz = Lat<3>::cz(i);
-  return (uint32_t)((int)p.self + p.d[0][1 - cx] + p.d[1][1 - cy] + p.d[2][1 - cz]);
-}
-
-// u = sum c_i f_i + F/2 for D3Q19, in one fixed evaluation order (shared by
-// the lanes that own a node and those that fill the ring)
-template <class R>
-__device__ inline void velocity3(const R* f, const R* F, R* u) {
-  u[0] = (((f[1] - f[2]) + (f[7] - f[8])) + ((f[9] - f[10]) + (f[11] - f[12]))) +
-         (f[13] - f[14]) + (R)0.5 * F[0];
-  u[1] = (((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16]))) +
-         (f[17] - f[18]) + (R)0.5 * F[1];
-  u[2] = (((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16]))) +
-         (f[18] - f[17]) + (R)0.5 * F[2];
-}
-
-// Direction tables for loops that walk the velocity set with a runtime
-// (wavefront-uniform) index: the loop bounds how many populations are in
-// flight, and uniform table reads cost scalar loads only.
-__constant__ int kC3[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
-                               {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
-                               {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
-                               {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
-// f^B_i = sum_c K[i][c] tau_c / tau_f with tau in (xx, yy, zz, xy, xz, yz):
-// the pseudo-inverse closed forms written as one row per direction
-#define K42(a, b, c) {(a) / 42.0, (b) / 42.0, (c) / 42.0, 0.0, 0.0, 0.0}
-__constant__ double kFB3[19][6] = {
-    {5.0 / 21, 5.0 / 21, 5.0 / 21, 0, 0, 0},
-    K42(-1, 6, 6), K42(-1, 6, 6), K42(6, -1, 6), K42(6, -1, 6), K42(6, 6, -1), K42(6, 6, -1),
-    {-10.0 / 84, -10.0 / 84, 4.0 / 84, -21.0 / 84, 0, 0},
-    {-10.0 / 84, -10.0 / 84, 4.0 / 84, -21.0 / 84, 0, 0},
-    {-10.0 / 84, -10.0 / 84, 4.0 / 84, 21.0 / 84, 0, 0},
-    {-10.0 / 84, -10.0 / 84, 4.0 / 84, 21.0 / 84, 0, 0},
-    {-10.0 / 84, 4.0 / 84, -10.0 / 84, 0, -21.0 / 84, 0},
-    {-10.0 / 84, 4.0 / 84, -10.0 / 84, 0, -21.0 / 84, 0},
-    {-10.0 / 84, 4.0 / 84, -10.0 / 84, 0, 21.0 / 84, 0},
-    {-10.0 / 84, 4.0 / 84, -10.0 / 84, 0, 21.0 / 84, 0},
-    {4.0 / 84, -10.0 / 84, -10.0 / 84, 0, 0, -21.0 / 84},
-    {4.0 / 84, -10.0 / 84, -10.0 / 84, 0, 0, -21.0 / 84},
-    {4.0 / 84, -10.0 / 84, -10.0 / 84, 0, 0, 21.0 / 84},
-    {4.0 / 84, -10.0 / 84, -10.0 / 84, 0, 0, 21.0 / 84}};
-#undef K42
-
-// runtime-direction versions of the pull helpers
-template <bool WALLS>
-__device__ inline bool pull3_bounce_rt(int i, const Pull3& p) {
-  if (!WALLS) return false;
-  const int cx = kC3[i][0], cy = kC3[i][1], cz = kC3[i][2];
-  return (cx > 0 && p.lo[0]) || (cx < 0 && p.hi[0]) || (cy > 0 && p.lo[1]) ||
-         (cy < 0 && p.hi[1]) || (cz > 0 && p.lo[2]) || (cz < 0 && p.hi[2]);
-}
-__device__ inline uint32_t pull3_node_rt(int i, const Pull3& p) {
-  int off = (int)p.self;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int c = kC3[i][a];
-    off += c > 0 ? p.d[a][0] : (c < 0 ? p.d[a][2] : 0);
+// offset in pair plane k of the value that streams into this lane's member
+// of pair k: the neighbour's member (2 src + s) or, beyond a wall, the
+// node's own opposite population, the partner's member (2 self + 1 - s)
+template <int K, bool WALLS>
+__device__ inline uint32_t pair_src(const PairPull& p, int s) {
+  constexpr int i = 2 * K - 1;
+  constexpr int cx = Lat<3>::cx(i), cy = Lat<3>::cy(i), cz = Lat<3>::cz(i);
+  const int off = (int)p.self + (cx > 0 ? p.dm[0] : (cx < 0 ? p.dp[0] : 0)) +
+                  (cy > 0 ? p.dm[1] : (cy < 0 ? p.dp[1] : 0)) +
+                  (cz > 0 ? p.dm[2] : (cz < 0 ? p.dp[2] : 0));
+  if (WALLS) {
+    const bool bounce = (cx > 0 && p.wm[0]) || (cx < 0 && p.wp[0]) || (cy > 0 && p.wm[1]) ||
+                        (cy < 0 && p.wp[1]) || (cz > 0 && p.wm[2]) || (cz < 0 && p.wp[2]);
+    if (bounce) return 2 * p.self + (uint32_t)(1 - s);
   }
-  return (uint32_t)off;
+  return 2 * (uint32_t)off + (uint32_t)s;
 }
-__device__ inline int opp3_rt(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+template <int K, class F>
+__device__ inline void for_pairs(F&& fn) {
+  if constexpr (K <= 9) {
+    fn(std::integral_constant<int, K>());
+    for_pairs<K + 1>(fn);
+  }
+}
 
 template <class S, int TY, int ZC, bool WALLS>
 __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int ntx, int nty) {
   using R = typename StoreT<S>::R;
-  using PA = typename PlaneSel<S>::T;
-  constexpr int Q = 19, NC = 6, TX = 64, SX = TX + 2, SY = TY + 2, NS = SX * SY;
-  constexpr int H = 2 * SX + 2 * TY;
-  constexpr int GROUP = 5;  // directions pulled together in pass 1 (loads in flight)
+  using PA = Pair3<S>;
+  using L = Lat<3>;
+  constexpr int NP = 10, NC = 6, TXN = 32, SX = TXN + 2, SY = TY + 2, NS = SX * SY;
+  constexpr int H = 2 * SX + 2 * TY;  // ring nodes
+  static_assert(2 * H <= 64 * TY, "ring needs more lanes than the workgroup has");
   __shared__ R ring[3][3][NS];
 
   const Geo g = a.g;
@@ -212,225 +186,250 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
   const int b = blockIdx.x;
   const int tx_tile = b % ntx, rest = b / ntx;
   const int ty_tile = rest % nty, zc = rest / nty;
-  const int x0 = tx_tile * TX, y0 = ty_tile * TY;
+  const int x0 = tx_tile * TXN, y0 = ty_tile * TY;
   const int zs = zc * ZC, ze = min(zs + ZC, g.nz);
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-  const int x = x0 + tx, y = y0 + ty;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  const int s = tx & 1;
+  const R sg = s ? (R)-1 : (R)1;
+  const int x = x0 + (tx >> 1), y = y0 + ty;
   const bool in_xy = x < g.nx && y < g.ny;
-  const int oslot = (ty + 1) * SX + tx + 1;
+  const int oslot = (ty + 1) * SX + (tx >> 1) + 1;
 
+  // own column (wrapped for lanes past a ragged edge: they supply the slot's
+  // velocity for the true last node's gradient) and, for the first 2H lanes,
+  // one node of the x/y ring
   int wx = x, wy = y;
   const bool vxy = wrap_coord(wx, g.nx, g.walls & 1) && wrap_coord(wy, g.ny, g.walls & 2);
   bool hxy = false;
   int hx = 0, hy = 0, hslot = 0;
-  if (tid < H) {
+  if (tid < 2 * H) {
+    const int r = tid >> 1;
     int sxl, syl;
-    if (tid < SX) { sxl = tid; syl = 0; }
-    else if (tid < 2 * SX) { sxl = tid - SX; syl = SY - 1; }
-    else if (tid < 2 * SX + TY) { sxl = 0; syl = 1 + tid - 2 * SX; }
-    else { sxl = SX - 1; syl = 1 + tid - 2 * SX - TY; }
+    if (r < SX) { sxl = r; syl = 0; }
+    else if (r < 2 * SX) { sxl = r - SX; syl = SY - 1; }
+    else if (r < 2 * SX + TY) { sxl = 0; syl = 1 + r - 2 * SX; }
+    else { sxl = SX - 1; syl = 1 + r - 2 * SX - TY; }
     hslot = syl * SX + sxl;
     hx = x0 - 1 + sxl;
     hy = y0 - 1 + syl;
     hxy = wrap_coord(hx, g.nx, g.walls & 1) && wrap_coord(hy, g.ny, g.walls & 2);
   }
+  R Fown[3];
+  force_at<R>(a.F, wx, wy, g.nx, g.ny, Fown);
 
-  // f of direction i streamed into the node described by pl
-  auto pull_f = [&](int i, const Pull3& pl) -> R {
-    if (pull3_bounce<WALLS>(i, pl)) return PA::load_f(pin, Lat<3>::opp(i), pl.self, N, a.inv_sf);
-    return PA::load_f(pin, i, pull3_node(i, pl), N, a.inv_sf);
+  // this lane's moving f streamed into the node of pp (slots 1..9)
+  auto pull_fs = [&](const PairPull& pp, R* f) {
+    for_pairs<1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      f[k] = PA::load_f(pin, k, pair_src<k, WALLS>(pp, s), N, a.inv_sf);
+    });
   };
-  auto pull_all = [&](int i, const Pull3& pl, R& f, R* h) {
-    if (pull3_bounce_rt<WALLS>(i, pl))
-      PA::load(pin, opp3_rt(i), pl.self, N, a.inv_sf, a.inv_sh, f, h);
-    else
-      PA::load(pin, i, pull3_node_rt(i, pl), N, a.inv_sf, a.inv_sh, f, h);
+  // u = sum c f + F/2: each lane sums its members, the pair adds the halves
+  auto pair_velocity = [&](const R* f, const R* F, R* u) {
+    R m[3] = {0, 0, 0};
+    for_pairs<1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int i = 2 * k - 1;
+      constexpr int c[3] = {L::cx(i), L::cy(i), L::cz(i)};
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb)
+        if (c[bb] != 0) m[bb] += (R)c[bb] * f[k];
+    });
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) u[bb] = pair_sum(sg * m[bb]) + (R)0.5 * F[bb];
   };
-
-  // velocity of plane zp (unwrapped index) into its ring slot: each lane
-  // handles its own column and, for the first H lanes, one ring node
-  auto plane_u = [&](int zp) {
+  // velocity of plane zp (unwrapped index) into its ring slots; the lane's
+  // own pulled f are returned in fo for the collision of that plane
+  auto plane_u = [&](int zp, R* fo) {
     int zw = zp;
     const bool vz = wrap_coord(zw, g.nz, g.walls & 4);
     const int rs = ((zp % 3) + 3) % 3;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const bool on = vz && (k == 0 ? vxy : hxy);
-      if (!on) continue;
-      const int px = k == 0 ? wx : hx, py = k == 0 ? wy : hy, ps = k == 0 ? oslot : hslot;
-      Pull3 pp;
-      make_pull3(px, py, zw, g, pp);
-      R f[Q], F[3], u[3];
-#pragma unroll
-      for (int i = 1; i < Q; ++i) f[i] = pull_f(i, pp);
-      force_at<R>(a.F, px, py, g.nx, g.ny, F);
-      velocity3(f, F, u);
-      ring[rs][0][ps] = u[0];
-      ring[rs][1][ps] = u[1];
-      ring[rs][2][ps] = u[2];
+    if (vz && vxy) {
+      PairPull pp;
+      make_pair_pull(wx, wy, zw, s, g, pp);
+      pull_fs(pp, fo);
+      R u[3];
+      pair_velocity(fo, Fown, u);
+      if (s == 0) {
+        ring[rs][0][oslot] = u[0];
+        ring[rs][1][oslot] = u[1];
+        ring[rs][2][oslot] = u[2];
+      }
+    }
+    if (vz && hxy) {
+      PairPull pp;
+      make_pair_pull(hx, hy, zw, s, g, pp);
+      R fr[NP], F[3], u[3];
+      pull_fs(pp, fr);
+      force_at<R>(a.F, hx, hy, g.nx, g.ny, F);
+      pair_velocity(fr, F, u);
+      if (s == 0) {
+        ring[rs][0][hslot] = u[0];
+        ring[rs][1][hslot] = u[1];
+        ring[rs][2][hslot] = u[2];
+      }
     }
   };
 
-  auto collide_node = [&](int xn, int yn, int zn) {
-    Pull3 pl;
-    make_pull3(xn, yn, zn, g, pl);
-    const uint32_t n = pl.self;
-    const int rc = ((zn % 3) + 3) % 3, rm = (((zn - 1) % 3) + 3) % 3, rp = ((zn + 1) % 3 + 3) % 3;
-    // ---- pass 1: moments of the pulled state
-    R e[NC] = {0, 0, 0, 0, 0, 0};
-    R sum_f = 0;
-#pragma unroll 1
-    for (int g0 = 0; g0 < Q; g0 += GROUP) {
-#pragma unroll
-      for (int k = 0; k < GROUP; ++k) {
-        const int i = g0 + k;
-        if (i < Q) {
-          R fi, hv[NC];
-          pull_all(i, pl, fi, hv);
-          if (i > 0) sum_f += fi;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) e[c] += hv[c];
-        }
-      }
-    }
-    R chip[NC] = {0, 0, 0, 0, 0, 0}, up[3] = {0, 0, 0};
-    if (!a.first) Aux<3, R>::load(aux, n, N, chip, up);
-    // u(z) of this node is in the ring (same pulled values, same formula)
-    const R u[3] = {ring[rc][0][oslot], ring[rc][1][oslot], ring[rc][2][oslot]};
-    R F[3];
-    force_at<R>(a.F, xn, yn, g.nx, g.ny, F);
-    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const R Fu = F[0] * u[0] + F[1] * u[1] + F[2] * u[2];
-    R tau[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) tau[c] = a.P.eta_over_lam * e[c];
-    auto fB_of = [&](int i) -> R {
-      R sm = 0;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) sm += (R)kFB3[i][c] * tau[c];
-      return sm * a.P.inv_tau_f;
-    };
-    constexpr R w0 = (R)(1.0 / 3.0);
-    const R F0 = -3 * w0 * a.P.k_f * Fu;
-    // pressure (App. B): cs2/(1 - w0) = 1/2 for D3Q19
-    const R p = (R)0.5 * (sum_f - (R)1.5 * w0 * uu + a.P.tau_f * F0 + a.P.tau_f * fB_of(0));
-    // ---- same-time gradient and source tensor
-    const bool lo[3] = {WALLS && (g.walls & 1) && xn == 0, WALLS && (g.walls & 2) && yn == 0,
-                        WALLS && (g.walls & 4) && zn == 0};
-    const bool hi[3] = {WALLS && (g.walls & 1) && xn == g.nx - 1,
-                        WALLS && (g.walls & 2) && yn == g.ny - 1,
-                        WALLS && (g.walls & 4) && zn == g.nz - 1};
-    R G[3][3];
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb) {
-      const R* uc = &ring[rc][bb][oslot];
-      const R nb[3][2] = {{uc[-1], uc[1]}, {uc[-SX], uc[SX]},
-                          {ring[rm][bb][oslot], ring[rp][bb][oslot]}};
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        G[ax][bb] = lo[ax] ? u[bb] + nb[ax][1] * (R)(1.0 / 3.0)
-                  : hi[ax] ? -(u[bb] + nb[ax][0] * (R)(1.0 / 3.0))
-                           : (R)0.5 * (nb[ax][1] - nb[ax][0]);
-      }
-    }
-    R chi[NC];
-    source_tensor<3, R>(e, G, a.P.inv_lam, chi);
-    const bool first = a.first != 0;
-    R A[NC], target[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      A[c] = e[c] + (c < 3 ? (R)1 : (R)0);
-      target[c] = e[c] + chi[c] + (first ? (R)0 : (R)0.5 * (chi[c] - chip[c]));
-    }
-    // one direction: BGK + Guo + f^B for f (Sec. 2.2), ADE collision for h (Sec. 2.3)
-    auto collide_dir = [&](int i, R& fi, R* hv) {
-      const int cx = kC3[i][0], cy = kC3[i][1], cz = kC3[i][2];
-      const int c2 = cx * cx + cy * cy + cz * cz;
-      const R wi = c2 == 0 ? (R)(1.0 / 3.0) : (c2 == 1 ? (R)(1.0 / 18.0) : (R)(1.0 / 36.0));
-      const R lam_i = c2 == 0 ? (R)(3.0 * (1.0 / 3.0 - 1.0)) : 3 * wi;
-      const R cu = (R)cx * u[0] + (R)cy * u[1] + (R)cz * u[2];
-      const R cF = (R)cx * F[0] + (R)cy * F[1] + (R)cz * F[2];
-      const R feq = lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
-      const R Fi = wi * a.P.k_f * (3 * cF + 9 * cF * cu - 3 * Fu);
-      fi = fi - (fi - feq) * a.P.inv_tau_f + fB_of(i) + Fi;
-      const R cup = (R)cx * up[0] + (R)cy * up[1] + (R)cz * up[2];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const R heq = wi * e[c] + 3 * wi * A[c] * cu;
-        const R chi_i = wi * chi[c] * (1 + a.P.k_h3 * cu);
-        R srcv = chi_i;
-        if (!first) srcv += (R)0.5 * (chi_i - wi * chip[c] * (1 + a.P.k_h3 * cup));
-        hv[c] = hv[c] - (hv[c] - heq) * a.P.inv_tau_h + srcv;
-      }
-    };
-    // ---- pass 2: moving non-axis directions are collided and stored at once
-    R mom[3] = {0, 0, 0}, hsum[NC] = {0, 0, 0, 0, 0, 0};
-#pragma unroll 1
-    for (int g0 = 7; g0 < Q; g0 += 4) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int i = g0 + k;
-        R fi, hv[NC];
-        pull_all(i, pl, fi, hv);
-        collide_dir(i, fi, hv);
-        mom[0] += (R)kC3[i][0] * fi;
-        mom[1] += (R)kC3[i][1] * fi;
-        mom[2] += (R)kC3[i][2] * fi;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) hsum[c] += hv[c];
-        PA::store(pout, i, n, N, a.sf, a.sh, fi, hv);
-      }
-    }
-    // The momentum identity sum c f* = u + F/2 is restored on the axis pairs:
-    // their f* is formed once from f alone to finish the momentum sum, then
-    // the full populations are collided with the correction applied.  The
-    // rest population of h closes sum_i h*_i = A - I + chi + dchi/2.
-#pragma unroll
-    for (int i = 1; i < 7; ++i) {
-      R fi;
-      if (pull3_bounce_rt<WALLS>(i, pl)) fi = PA::load_f(pin, opp3_rt(i), pl.self, N, a.inv_sf);
-      else fi = PA::load_f(pin, i, pull3_node_rt(i, pl), N, a.inv_sf);
-      R hdummy[NC] = {0, 0, 0, 0, 0, 0};
-      collide_dir(i, fi, hdummy);
-      mom[(i - 1) >> 1] += (i & 1) ? fi : -fi;
-    }
-    R half[3];
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb) half[bb] = (R)0.5 * ((u[bb] + (R)0.5 * F[bb]) - mom[bb]);
-#pragma unroll 1
-    for (int g0 = 1; g0 < 7; g0 += 3) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int i = g0 + k;
-        R fi, hv[NC];
-        pull_all(i, pl, fi, hv);
-        collide_dir(i, fi, hv);
-        const int ax = (i - 1) >> 1;
-        const R hb = ax == 0 ? half[0] : (ax == 1 ? half[1] : half[2]);
-        fi += (i & 1) ? hb : -hb;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) hsum[c] += hv[c];
-        PA::store(pout, i, n, N, a.sf, a.sh, fi, hv);
-      }
-    }
-    {
-      R f0, h0[NC];
-      pull_all(0, pl, f0, h0);
-      collide_dir(0, f0, h0);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) h0[c] = target[c] - hsum[c];
-      PA::store(pout, 0, n, N, a.sf, a.sh, f0, h0);
-    }
-    Aux<3, R>::store(aux, n, N, chi, u);
-  };
+  R fn[NP];  // pulled f of the own node of the next plane
+  {
+    R fd[NP];
+    plane_u(zs - 1, fd);
+  }
+  plane_u(zs, fn);
 
-  plane_u(zs - 1);
-  plane_u(zs);
 #pragma unroll 1
   for (int z = zs; z < ze; ++z) {
-    plane_u(z + 1);
+    // ---- pull this plane's populations (moving f carried from the look-ahead)
+    PairPull pl;
+    make_pair_pull(x, y, z, s, g, pl);
+    const uint32_t n = pl.self;
+    R f[NP], h[NC][NP];
+    R chip[NC] = {0, 0, 0, 0, 0, 0}, up[3] = {0, 0, 0};
+    if (in_xy) {
+      // rest population: both lanes read it (one address), the even lane keeps it
+      R f0, h0[NC];
+      f0 = PA::load_f(pin, 0, n, N, a.inv_sf);
+      PA::load_h(pin, 0, n, N, a.inv_sh, h0);
+      f[0] = s ? (R)0 : f0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) h[c][0] = s ? (R)0 : h0[c];
+#pragma unroll
+      for (int k = 1; k < NP; ++k) f[k] = fn[k];
+      for_pairs<1>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        R hv[NC];
+        PA::load_h(pin, k, pair_src<k, WALLS>(pl, s), N, a.inv_sh, hv);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) h[c][k] = hv[c];
+      });
+      if (!a.first) Aux<3, R>::load(aux, n, N, chip, up);
+    }
+    // ---- look ahead: u(z + 1)
+    plane_u(z + 1, fn);
     __syncthreads();
-    if (in_xy) collide_node(x, y, z);
+    if (in_xy) {
+      const int rc = ((z % 3) + 3) % 3, rm = (((z - 1) % 3) + 3) % 3, rp = ((z + 1) % 3 + 3) % 3;
+      const R u[3] = {ring[rc][0][oslot], ring[rc][1][oslot], ring[rc][2][oslot]};
+      const R* F = Fown;
+      // moments of the pulled state
+      R e[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        R sm = 0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) sm += h[c][k];
+        e[c] = pair_sum(sm);
+      }
+      R sum_f = 0;
+#pragma unroll
+      for (int k = 1; k < NP; ++k) sum_f += f[k];
+      sum_f = pair_sum(sum_f);
+      R tau[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) tau[c] = a.P.eta_over_lam * e[c];
+      R fB[L::Q];
+      fluct_term<R>(tau, a.P.inv_tau_f, fB, (L*)nullptr);
+      const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+      const R Fu = F[0] * u[0] + F[1] * u[1] + F[2] * u[2];
+      constexpr R w0 = (R)L::w(0);
+      const R F0 = -3 * w0 * a.P.k_f * Fu;
+      // pressure (App. B): cs2/(1 - w0) = 1/2 for D3Q19
+      const R p = (R)0.5 * (sum_f - (R)1.5 * w0 * uu + a.P.tau_f * F0 + a.P.tau_f * fB[0]);
+
+      // ---- f collision: BGK + Guo forcing + f^B (Sec. 2.2)
+      {
+        const R feq = (R)(3.0 * (L::w(0) - 1.0)) * p - w0 * (R)1.5 * uu;
+        f[0] = f[0] - (f[0] - feq) * a.P.inv_tau_f + fB[0] + F0;
+      }
+      R mp[3] = {0, 0, 0};
+      for_pairs<1>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int i = 2 * k - 1;
+        constexpr int c[3] = {L::cx(i), L::cy(i), L::cz(i)};
+        constexpr R wi = (R)L::w(i);
+        const R cu = sg * ((R)c[0] * u[0] + (R)c[1] * u[1] + (R)c[2] * u[2]);
+        const R cF = sg * ((R)c[0] * F[0] + (R)c[1] * F[1] + (R)c[2] * F[2]);
+        const R feq = 3 * wi * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
+        const R Fi = wi * a.P.k_f * (3 * cF + 9 * cF * cu - 3 * Fu);
+        f[k] = f[k] - (f[k] - feq) * a.P.inv_tau_f + fB[i] + Fi;
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+          if (c[bb] != 0) mp[bb] += (R)c[bb] * f[k];
+      });
+      // The update's momentum identity sum c f* = u + F/2 is restored on the
+      // axis pairs (k = 1, 2, 3): rounded weights would otherwise bias every
+      // step; mass and second moments are unchanged by it.
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) {
+        const R m = pair_sum(sg * mp[bb]);
+        const R half = (R)0.5 * ((u[bb] + (R)0.5 * F[bb]) - m);
+        f[1 + bb] += sg * half;
+      }
+
+      // ---- same-time gradient G[a][b] = d_a u_b (central; one-sided at walls)
+      R G[3][3];
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) {
+        const R* uc = &ring[rc][bb][oslot];
+        const R nb[3][2] = {{uc[-1], uc[1]}, {uc[-SX], uc[SX]},
+                            {ring[rm][bb][oslot], ring[rp][bb][oslot]}};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          G[ax][bb] = pl.lo[ax] ? u[bb] + nb[ax][1] * (R)(1.0 / 3.0)
+                    : pl.hi[ax] ? -(u[bb] + nb[ax][0] * (R)(1.0 / 3.0))
+                                : (R)0.5 * (nb[ax][1] - nb[ax][0]);
+        }
+      }
+      R chi[NC];
+      source_tensor<3, R>(e, G, a.P.inv_lam, chi);
+
+      // ---- h collision (Sec. 2.3); the rest population closes
+      // sum_i h*_i = A - I + chi + (chi - chi(t-1))/2
+      const bool first = a.first != 0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const R Ac = e[c] + (c < 3 ? (R)1 : (R)0);
+        const R target = e[c] + chi[c] + (first ? (R)0 : (R)0.5 * (chi[c] - chip[c]));
+        R hs = 0;
+        for_pairs<1>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          constexpr int i = 2 * k - 1;
+          constexpr int cv[3] = {L::cx(i), L::cy(i), L::cz(i)};
+          constexpr R wi = (R)L::w(i);
+          const R cu = sg * ((R)cv[0] * u[0] + (R)cv[1] * u[1] + (R)cv[2] * u[2]);
+          const R heq = wi * e[c] + 3 * wi * Ac * cu;
+          const R chi_i = wi * chi[c] * (1 + a.P.k_h3 * cu);
+          R src = chi_i;
+          if (!first) {
+            const R cup = sg * ((R)cv[0] * up[0] + (R)cv[1] * up[1] + (R)cv[2] * up[2]);
+            src += (R)0.5 * (chi_i - wi * chip[c] * (1 + a.P.k_h3 * cup));
+          }
+          h[c][k] = h[c][k] - (h[c][k] - heq) * a.P.inv_tau_h + src;
+          hs += h[c][k];
+        });
+        h[c][0] = target - pair_sum(hs);
+      }
+
+      // ---- stores
+      if (s == 0) {
+        const R hv[NC] = {h[0][0], h[1][0], h[2][0], h[3][0], h[4][0], h[5][0]};
+        PA::store(pout, 0, n, N, a.sf, a.sh, f[0], hv);
+      }
+#pragma unroll
+      for (int k = 1; k < NP; ++k) {
+        const R hv[NC] = {h[0][k], h[1][k], h[2][k], h[3][k], h[4][k], h[5][k]};
+        PA::store(pout, k, 2 * n + (uint32_t)s, N, a.sf, a.sh, f[k], hv);
+      }
+      // chi (6 planes) then u (3 planes): the pair splits the nine stores
+      const R item[9] = {chi[0], chi[1], chi[2], chi[3], chi[4], chi[5], u[0], u[1], u[2]};
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const int q = 2 * j + s;
+        const R v = s ? item[2 * j + 1 < 9 ? 2 * j + 1 : 8] : item[2 * j];
+        if (q < 9) stream_store(aux + (size_t)q * N + n, v);
+      }
+    }
     __syncthreads();
   }
 }

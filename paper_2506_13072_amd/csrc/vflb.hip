@@ -91,6 +91,9 @@ void drop_graphs(vflb_sim* s) {
   }
 }
 
+// D3Q19: 32 x tile_y node columns, tile_y 4 (two workgroups per CU) or 8
+int tile_y_3d(const vflb_sim* s) { return s->tile_y == 8 ? 8 : 4; }
+
 int default_tile_y(const vflb_sim* s) {
   if (s->tile_y > 0) return s->tile_y;
   // measured on MI355X (8192 x 1024 channel): 64 x 16 tiles for FP32/FP64,
@@ -177,14 +180,22 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
         break;
     }
   } else {
-    constexpr int TY3 = 4, ZC = 32;
-    const int ntx = (s->nx + 63) / 64, nty = (s->ny + TY3 - 1) / TY3;
+    constexpr int ZC = 32;
+    const int ty = tile_y_3d(s);
+    const int ntx = (s->nx + 31) / 32, nty = (s->ny + ty - 1) / ty;
     const int nzc = (s->nz + ZC - 1) / ZC;
     const dim3 grid((unsigned)(ntx * nty * nzc));
-    if (s->walls)
-      hipLaunchKernelGGL((step3d_kernel<S, TY3, ZC, true>), grid, dim3(64, TY3), 0, st, a, ntx, nty);
-    else
-      hipLaunchKernelGGL((step3d_kernel<S, TY3, ZC, false>), grid, dim3(64, TY3), 0, st, a, ntx, nty);
+    if (ty == 8) {
+      if (s->walls)
+        hipLaunchKernelGGL((step3d_kernel<S, 8, ZC, true>), grid, dim3(64, 8), 0, st, a, ntx, nty);
+      else
+        hipLaunchKernelGGL((step3d_kernel<S, 8, ZC, false>), grid, dim3(64, 8), 0, st, a, ntx, nty);
+    } else {
+      if (s->walls)
+        hipLaunchKernelGGL((step3d_kernel<S, 4, ZC, true>), grid, dim3(64, 4), 0, st, a, ntx, nty);
+      else
+        hipLaunchKernelGGL((step3d_kernel<S, 4, ZC, false>), grid, dim3(64, 4), 0, st, a, ntx, nty);
+    }
   }
   HIP_TRY(s, hipGetLastError());
   return VFLB_OK;
@@ -332,11 +343,12 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
     return fail(nullptr, VFLB_EINVAL, "bad size %d x %d x %d", nx, ny, nz);
   const size_t N = (size_t)nx * ny * nz;
   if (N > ((size_t)1 << 34)) return fail(nullptr, VFLB_EINVAL, "lattice too large");
-  // the D3Q19 step addresses one direction's population plane with 32-bit
-  // byte offsets: 16-byte tuples (32 in FP64) per node must stay below 4 GiB
-  if (lattice == VFLB_D3Q19 && N > ((size_t)1 << (storage == VFLB_F64 ? 27 : 28)))
-    return fail(nullptr, VFLB_EINVAL, "D3Q19 lattice of %zu nodes exceeds %s", N,
-                storage == VFLB_F64 ? "2^27 (FP64)" : "2^28");
+  // the D3Q19 step addresses a pair plane (2N four-component tuples) with
+  // 32-bit byte offsets, which must stay below 4 GiB
+  const int d3_log2_max = storage == VFLB_F64 ? 26 : (storage == VFLB_F32 ? 27 : 28);
+  if (lattice == VFLB_D3Q19 && N > ((size_t)1 << d3_log2_max))
+    return fail(nullptr, VFLB_EINVAL, "D3Q19 lattice of %zu nodes exceeds 2^%d for this storage",
+                N, d3_log2_max);
   vflb_sim* s = new vflb_sim();
   s->D = lattice;
   s->Q = lattice == VFLB_D2Q9 ? 9 : 19;
@@ -348,10 +360,8 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
   s->storage = storage;
   s->stream = static_cast<hipStream_t>(hip_stream);
   const size_t sb = s->store_bytes(), ab = s->arith_bytes();
-  size_t words;
-  if (lattice == VFLB_D2Q9) words = Pops<2, float>::words(N);
-  else if (storage == VFLB_F16S || storage == VFLB_BF16S) words = Pops<3, _Float16>::words(N);
-  else words = Pops<3, float>::words(N);
+  const size_t words =
+      lattice == VFLB_D2Q9 ? Pops<2, float>::words(N) : Pops<3, float>::words(N);
   s->bytes[VFLB_BUF_POP0] = s->bytes[VFLB_BUF_POP1] = align256(sb * words);
   s->bytes[VFLB_BUF_AUX] = align256(ab * (s->NC + s->D) * N);
   s->bytes[VFLB_BUF_SNAP] = align256(ab * (s->NC + s->D) * N);
@@ -491,8 +501,8 @@ vflb_status vflb_set_storage_scale(vflb_sim* s, int log2_f, int log2_h) {
 
 vflb_status vflb_set_tile(vflb_sim* s, int tile_y) {
   if (!s) return VFLB_EINVAL;
-  if (tile_y != 0 && tile_y != 4 && tile_y != 8 && tile_y != 16)
-    return fail(s, VFLB_EINVAL, "tile_y must be 0, 4, 8 or 16");
+  if (tile_y != 0 && tile_y != 4 && tile_y != 8 && (tile_y != 16 || s->D == 3))
+    return fail(s, VFLB_EINVAL, "tile_y must be 0, 4, 8 or 16 (D2Q9), 0, 4 or 8 (D3Q19)");
   s->tile_y = tile_y;
   drop_graphs(s);
   return VFLB_OK;
