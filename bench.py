@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
 NX, NY = 8192, 1024
 RE, WI, BETA, U0, L = 30.72, 1.0, 0.5, 0.01, 1024.0
 REDUCE_EVERY = 100
@@ -116,6 +117,29 @@ def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0):
     return dict(step_ms=ms, GLUPS=n ** 3 / ms / 1e6, KE=r["KE"], nonfinite=r["nonfinite"])
 
 
+def measured_traffic(record, kernel):
+    """HBM bytes per launch of the step kernel (FETCH_SIZE + WRITE_SIZE,
+    scaled against the streaming-copy kernel) from a committed rocprofv3
+    record under profiles/, or None when the record is missing or the kernel
+    sources have changed since it was taken."""
+    from paper_2506_13072_amd.build import kernel_sources_sha
+    try:
+        with open(os.path.join(PROFILES, record)) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        key, _, val = line.strip().partition(": ")
+        vals[key] = val
+    if vals.get("sources_sha256") != kernel_sources_sha(kernel):
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def copy_ceiling(nbytes=4 << 30, reps=10):
     """Rate of the library's plain streaming-copy kernel (read + write bytes
     per second), the achievable-bandwidth reference next to the 8 TB/s
@@ -189,14 +213,24 @@ def main():
     if args.workload == "tgv":
         r = run_gpu_tgv(args.tgv_n, args.steps, args.warmup, args.storage, args.tile)
         bpl = bytes_per_lup(3, args.storage)
-        ach = bpl * args.tgv_n ** 3 / (r["step_ms"] / 1e3) / 1e9
+        nodes = args.tgv_n ** 3
+        ach = bpl * nodes / (r["step_ms"] / 1e3) / 1e9
+        traffic = None
+        if args.storage == "f32" and args.tgv_n == 512 and not args.tile:
+            traffic = measured_traffic("step3d_f32_tgv_512.md", "step3d")
         print(json.dumps({"metric": "MLUPS (fused stream-collide, D3Q19)", "value": round(r["GLUPS"] * 1e3, 1),
                           "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-                          "ms_per_step": round(r["step_ms"], 4), "dtype": "f32",
-                          "config": {"workload": f"3D Taylor-Green vortex D3Q19 {args.tgv_n}^3",
-                                     "storage": args.storage},
+                          "ms_per_step": round(r["step_ms"], 4), "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
+                          "config": {"workload": f"3D Taylor-Green vortex D3Q19 {args.tgv_n}^3, "
+                                                 "periodic, Re=100 Wi=0.5 beta=0.9",
+                                     "storage": args.storage, "nodes": nodes},
                           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                       "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                                       "traffic_unit": "GB per launch",
+                                       "algorithmic_GB_per_launch": round(bpl * nodes / 1e9, 4),
                                        "bytes_per_lup": bpl}}), flush=True)
         return
     res = run_gpu(args.steps, args.warmup, args.storage, args.tile)
@@ -205,6 +239,9 @@ def main():
     mlups = nodes * args.steps / (res["total_ms"] / 1e3) / 1e6
     bpl = bytes_per_lup(2, args.storage)
     achieved = bpl * nodes / (res["step_ms"] / 1e3) / 1e9
+    traffic = None
+    if args.storage == "f32" and not args.tile:
+        traffic = measured_traffic("step2d_f32_channel_8192x1024.md", "step2d")
     out = {
         "metric": "MLUPS (fused stream-collide, D2Q9 Oldroyd-B fluctuating LB)",
         "value": round(mlups, 1),
@@ -224,7 +261,10 @@ def main():
                    "reduce_every": REDUCE_EVERY},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_lup": bpl,
+                     "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                     "traffic_unit": "GB per launch",
+                     "algorithmic_GB_per_launch": round(bpl * nodes / 1e9, 4),
+                     "bytes_per_lup": bpl,
                      "kernel_ms": round(res["step_ms"], 5),
                      "copy_ceiling_GBps": round(ceiling, 1),
                      "frac_of_copy": round(achieved / ceiling, 4)},

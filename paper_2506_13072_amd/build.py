@@ -4,11 +4,13 @@ from __future__ import annotations
 import os
 import subprocess
 
+import hashlib
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libvflb.so")
-SOURCES = [os.path.join(HERE, "csrc", "vflb.hip")]
-HEADERS = [os.path.join(HERE, "csrc", n) for n in ("lattice.h", "kernels.h")] + [
-    os.path.join(os.path.dirname(HERE), "include", "vflb.h")]
+CSRC = os.path.join(HERE, "csrc")
+SOURCES = [os.path.join(CSRC, "vflb.hip")]
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vflb.h")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -20,6 +22,28 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     "-Wall", "-Wno-unused-function",
 ]
+
+
+# device code each step kernel is compiled from
+KERNEL_FILES = {
+    "step2d": ("step2d.h", "kernels.h", "layout.h", "lattice.h"),
+    "step3d": ("step3d.h", "kernels.h", "layout.h", "lattice.h"),
+}
+
+
+def kernel_sources_sha(kernel: str) -> str:
+    """SHA-256 over what one step kernel is compiled from (its device
+    headers and the compiler flags).
+    Recorded next to measured hardware counters, so a consumer can tell
+    whether the counters still describe the kernel it runs."""
+    h = hashlib.sha256()
+    paths = [os.path.join(CSRC, n) for n in KERNEL_FILES[kernel]]
+    for path in paths:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    return h.hexdigest()
 
 
 def build(verbose: bool = False) -> str:

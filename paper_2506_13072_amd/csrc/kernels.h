@@ -48,16 +48,10 @@ __device__ inline size_t node_of(int x, int y, int z, const Geo& g) {
   return ((size_t)z * g.ny + y) * g.nx + x;
 }
 
-// Tuple index of population i at node n.  D2Q9: plane i, i*N + n.  D3Q19:
-// the rest population has plane 0 (index n); the two members of an opposite
-// pair (2k-1, 2k) share one double-width plane starting at (2k-1) N, where
-// they sit side by side (2n + 0 and 2n + 1), so the lane pair that owns a
-// node reads and writes adjacent tuples.
+// Tuple index of population i at node n: plane i, i*N + n.
 template <int D>
 __host__ __device__ inline size_t tuple_of(int i, size_t n, size_t N) {
-  if (D == 2 || i == 0) return (size_t)i * N + n;
-  const int s = (i + 1) & 1;  // 0 for the odd member, 1 for the even one
-  return (size_t)(i - s) * N + 2 * n + s;
+  return (size_t)i * N + n;
 }
 
 // Index of the post-collision value that streams into direction i of node

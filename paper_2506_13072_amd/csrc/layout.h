@@ -1,9 +1,7 @@
 // layout.h -- where populations and auxiliary fields live in HBM.
 //
 // One buffer per ping/pong side holds all populations of the lattice.  A
-// tuple index t names direction i at node n: t = i*N + n for D2Q9; for
-// D3Q19 the members of an opposite pair interleave node by node
-// (tuple_of in kernels.h).
+// tuple index t = i*N + n names direction i at node n.
 //
 //  D2Q9:  tuples [Q][N] of (f_i, h_xx,i, h_xy,i, h_yy,i).  f and the three
 //         conformation populations of one direction stream from the same

@@ -48,10 +48,11 @@ template <> struct Cvt<bf16_t> {
   __device__ static V out(float v, float) { return f32_to_bf16(v); }
 };
 
-// Access to the D3Q19 population buffer by pair plane: k = 0 is the rest
-// plane (offset o = node), k = 1..9 the plane of directions (2k-1, 2k)
-// (offset o = 2 node + member).  f, the (xx, yy, zz, xy) 4-tuples and the
-// (xz, yz) 2-tuples follow one another, each Q N tuples long.
+// Access to the D3Q19 population buffer by pair: k = 0 is the rest plane
+// (offset o = node), k = 1..9 the planes of directions 2k-1 and 2k, which
+// follow one another (offset o = member N + node).  f, the (xx, yy, zz, xy)
+// 4-tuples and the (xz, yz) 2-tuples follow one another, each Q N tuples
+// long.
 template <class S> struct Pair3 {
   using C = Cvt<S>;
   using V = typename C::V;
@@ -141,11 +142,11 @@ __device__ inline void make_pair_pull(int x, int y, int z, int s, const Geo& g, 
   p.self = (uint32_t)(((size_t)z * g.ny + y) * g.nx + x);
 }
 
-// offset in pair plane k of the value that streams into this lane's member
-// of pair k: the neighbour's member (2 src + s) or, beyond a wall, the
-// node's own opposite population, the partner's member (2 self + 1 - s)
+// offset from pair plane k of the value that streams into this lane's
+// member of pair k: the neighbour's member (s N + src) or, beyond a wall,
+// the node's own opposite population, the partner's member ((1 - s) N + self)
 template <int K, bool WALLS>
-__device__ inline uint32_t pair_src(const PairPull& p, int s) {
+__device__ inline uint32_t pair_src(const PairPull& p, int s, uint32_t N) {
   constexpr int i = 2 * K - 1;
   constexpr int cx = Lat<3>::cx(i), cy = Lat<3>::cy(i), cz = Lat<3>::cz(i);
   const int off = (int)p.self + (cx > 0 ? p.dm[0] : (cx < 0 ? p.dp[0] : 0)) +
@@ -154,9 +155,9 @@ __device__ inline uint32_t pair_src(const PairPull& p, int s) {
   if (WALLS) {
     const bool bounce = (cx > 0 && p.wm[0]) || (cx < 0 && p.wp[0]) || (cy > 0 && p.wm[1]) ||
                         (cy < 0 && p.wp[1]) || (cz > 0 && p.wm[2]) || (cz < 0 && p.wp[2]);
-    if (bounce) return 2 * p.self + (uint32_t)(1 - s);
+    if (bounce) return (s ? 0u : N) + p.self;
   }
-  return 2 * (uint32_t)off + (uint32_t)s;
+  return (s ? N : 0u) + (uint32_t)off;
 }
 
 template <int K, class F>
@@ -182,6 +183,7 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
   S* __restrict__ pout = a.pout;
   R* __restrict__ aux = a.aux;
   const size_t N = g.N;
+  const uint32_t N32 = (uint32_t)N;  // N <= 2^27 (2^26 in FP64), checked on the host
 
   const int b = blockIdx.x;
   const int tx_tile = b % ntx, rest = b / ntx;
@@ -221,7 +223,7 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
   auto pull_fs = [&](const PairPull& pp, R* f) {
     for_pairs<1>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      f[k] = PA::load_f(pin, k, pair_src<k, WALLS>(pp, s), N, a.inv_sf);
+      f[k] = PA::load_f(pin, k, pair_src<k, WALLS>(pp, s, N32), N, a.inv_sf);
     });
   };
   // u = sum c f + F/2: each lane sums its members, the pair adds the halves
@@ -299,7 +301,7 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
       for_pairs<1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         R hv[NC];
-        PA::load_h(pin, k, pair_src<k, WALLS>(pl, s), N, a.inv_sh, hv);
+        PA::load_h(pin, k, pair_src<k, WALLS>(pl, s, N32), N, a.inv_sh, hv);
 #pragma unroll
         for (int c = 0; c < NC; ++c) h[c][k] = hv[c];
       });
@@ -419,7 +421,7 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
 #pragma unroll
       for (int k = 1; k < NP; ++k) {
         const R hv[NC] = {h[0][k], h[1][k], h[2][k], h[3][k], h[4][k], h[5][k]};
-        PA::store(pout, k, 2 * n + (uint32_t)s, N, a.sf, a.sh, f[k], hv);
+        PA::store(pout, k, (s ? N32 : 0u) + n, N, a.sf, a.sh, f[k], hv);
       }
       // chi (6 planes) then u (3 planes): the pair splits the nine stores
       const R item[9] = {chi[0], chi[1], chi[2], chi[3], chi[4], chi[5], u[0], u[1], u[2]};

@@ -343,7 +343,7 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
     return fail(nullptr, VFLB_EINVAL, "bad size %d x %d x %d", nx, ny, nz);
   const size_t N = (size_t)nx * ny * nz;
   if (N > ((size_t)1 << 34)) return fail(nullptr, VFLB_EINVAL, "lattice too large");
-  // the D3Q19 step addresses a pair plane (2N four-component tuples) with
+  // the D3Q19 step addresses the two planes of an opposite pair (2N tuples) with
   // 32-bit byte offsets, which must stay below 4 GiB
   const int d3_log2_max = storage == VFLB_F64 ? 26 : (storage == VFLB_F32 ? 27 : 28);
   if (lattice == VFLB_D3Q19 && N > ((size_t)1 << d3_log2_max))

@@ -1,0 +1,121 @@
+"""Summarise rocprofv3 output of one kernel into a short markdown record.
+
+Reads the CSV files rocprofv3 writes with --output-format csv: the
+--kernel-trace --stats summary (average launch duration), one --pmc
+FETCH_SIZE and one --pmc WRITE_SIZE run of the workload, and the same two
+counters for the library's streaming-copy kernel (vflb_stream_copy of a
+known byte count), which turns the counters' units into bytes.  The record
+carries the SHA-256 of the kernel's sources (build.kernel_sources_sha) so
+that the figures are only used while the kernels are unchanged.
+
+    python -m paper_2506_13072_amd.profsum --kernel step2d_kernel<float, 16> --sources step2d \\
+        --stats DIR --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \\
+        --copy-bytes 4294967296 --algo-bytes B --title T --command C ... > profiles/x.md
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import os
+import sys
+
+if __package__ in (None, ""):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+from paper_2506_13072_amd.build import kernel_sources_sha  # noqa: E402
+
+
+def _one(pattern):
+    found = sorted(glob.glob(pattern, recursive=True))
+    if not found:
+        raise SystemExit(f"no file matches {pattern}")
+    return found[0]
+
+
+def counter_per_dispatch(directory, kernel):
+    """Mean counter value (KiB) per dispatch of the kernels whose name
+    contains `kernel`, and the number of dispatches."""
+    rows = collections.defaultdict(list)
+    with open(_one(os.path.join(directory, "**", "*counter_collection.csv"))) as fh:
+        for r in csv.DictReader(fh):
+            rows[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    vals = [v for k, vs in rows.items() if kernel in k for v in vs]
+    if not vals:
+        raise SystemExit(f"kernel {kernel!r} not in {directory}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def kernel_stats(directory, kernel):
+    with open(_one(os.path.join(directory, "**", "*kernel_stats.csv"))) as fh:
+        rows = list(csv.DictReader(fh))
+    hit = [r for r in rows if kernel in r["Name"]]
+    if not hit:
+        raise SystemExit(f"kernel {kernel!r} not in stats of {directory}")
+    r = hit[0]
+    return dict(name=r["Name"], calls=int(r["Calls"]), avg_ns=float(r["AverageNs"]),
+                pct=float(r["Percentage"])), rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--sources", required=True, choices=["step2d", "step3d"],
+                    help="which kernel's sources the record describes")
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--copy-kernel", default="stream_copy_kernel")
+    ap.add_argument("--copy-bytes", type=float, required=True,
+                    help="bytes read (= bytes written) by one copy launch")
+    ap.add_argument("--algo-bytes", type=float, required=True,
+                    help="algorithmic HBM bytes (read + write) per launch")
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--command", action="append", default=[])
+    a = ap.parse_args()
+
+    st, rows = kernel_stats(a.stats, a.kernel)
+    cf, _ = counter_per_dispatch(a.copy_fetch, a.copy_kernel)
+    cw, _ = counter_per_dispatch(a.copy_write, a.copy_kernel)
+    f_scale = a.copy_bytes / (cf * 1024)
+    w_scale = a.copy_bytes / (cw * 1024)
+    fk, nf = counter_per_dispatch(a.fetch, a.kernel)
+    wk, nw = counter_per_dispatch(a.write, a.kernel)
+    fetch = fk * 1024 * f_scale
+    write = wk * 1024 * w_scale
+    secs = st["avg_ns"] * 1e-9
+    out = [f"# {a.title}", "",
+           f"kernel: `{st['name'][:160]}`", "",
+           "Commands (run from the repository root, `export TMPDIR=/tmp`):", ""]
+    out += [f"    {c}" for c in a.command]
+    out += ["",
+            "| quantity | value |", "|---|---|",
+            f"| launches in the stats run | {st['calls']} |",
+            f"| average launch duration (stats) | {st['avg_ns'] / 1e3:.1f} us |",
+            f"| share of GPU time in the stats run | {st['pct']:.2f} % |",
+            f"| algorithmic bytes per launch | {a.algo_bytes / 1e9:.4f} GB |",
+            f"| algorithmic rate at that duration | {a.algo_bytes / secs / 1e9:.1f} GB/s |",
+            f"| FETCH_SIZE per launch (x{f_scale:.4f}, {nf} launches) | {fetch / 1e9:.4f} GB |",
+            f"| WRITE_SIZE per launch (x{w_scale:.4f}, {nw} launches) | {write / 1e9:.4f} GB |",
+            f"| measured / algorithmic bytes | {(fetch + write) / a.algo_bytes:.4f} |",
+            f"| measured traffic rate | {(fetch + write) / secs / 1e9:.1f} GB/s |",
+            "",
+            "Counter scale: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the streaming-copy",
+            f"kernel moving {a.copy_bytes / 2**30:.0f} GiB each way read {cf / 2**20:.4f} GiB and "
+            f"{cw / 2**20:.4f} GiB.", "",
+            "Other kernels in the stats run:", ""]
+    for r in rows[:6]:
+        out.append(f"- `{r['Name'][:90]}`: {r['Calls']} calls, "
+                   f"{float(r['AverageNs']) / 1e3:.1f} us average, {float(r['Percentage']):.2f} %")
+    out += ["", "Machine-read lines (bench.py):", "",
+            f"    sources_sha256: {kernel_sources_sha(a.sources)}",
+            f"    avg_launch_ns: {st['avg_ns']:.1f}",
+            f"    fetch_bytes_per_launch: {fetch:.0f}",
+            f"    write_bytes_per_launch: {write:.0f}", ""]
+    print("\n".join(out))
+
+
+if __name__ == "__main__":
+    main()
