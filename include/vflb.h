@@ -45,6 +45,7 @@ extern "C" {
 #endif
 
 typedef struct vflb_sim vflb_sim;
+typedef struct vflb_batch vflb_batch;
 
 typedef enum {
   VFLB_OK = 0,
@@ -229,12 +230,112 @@ vflb_status vflb_set_tile(vflb_sim *sim, int tile_y);
 vflb_status vflb_stream_copy(const void *src, void *dst, size_t nbytes,
                              void *hip_stream);
 
-/* Release the handle (not the caller's buffers). */
+/* Release the handle (not the caller's buffers).  Ignored for the
+ * instances of a batch, which the batch owns. */
 void vflb_destroy(vflb_sim *sim);
 
 /* Message of the last failed call on sim (or of the last failed
  * vflb_create when sim is NULL); never NULL. */
 const char *vflb_last_error(const vflb_sim *sim);
+
+/* ------------------------------------------------------------------ batches
+ * An ensemble of independent D2Q9 lattices of different sizes and
+ * parameters advanced together: every step is one persistent launch whose
+ * workgroups walk a flattened table of (instance, 64 x tile_y tile)
+ * entries, so small lattices do not each pay a launch and the GPU stays
+ * full.  Each tile runs the same per-node arithmetic as vflb_step, so an
+ * instance takes bitwise the values it would take alone.  Instances are
+ * configured, initialised and read through vflb_sim handles
+ * (vflb_batch_instance) with the single-lattice calls; stepping belongs to
+ * the batch.  Every call enqueues on the batch's stream.
+ */
+
+/* Outcome per instance of vflb_batch_run_until. */
+enum {
+  VFLB_RUN_ACTIVE = 0,    /* still running (not returned by run_until)       */
+  VFLB_RUN_CONVERGED = 1, /* residual fell below tol                         */
+  VFLB_RUN_CAPPED = 2,    /* reached its step cap first                      */
+  VFLB_RUN_UNSTABLE = 3,  /* a non-finite moment appeared                    */
+  VFLB_RUN_SKIPPED = 4    /* was inactive when run_until started             */
+};
+
+/* Create a batch of n D2Q9 lattices; dims holds n triples (nx, ny, nz),
+ * nz ignored.  Storage as for vflb_create.  EINVAL for another lattice or a
+ * bad size. */
+vflb_status vflb_batch_create(int lattice, int n, const int *dims, int storage,
+                              void *hip_stream, vflb_batch **out);
+
+/* Sizes of the VFLB_NBUF device buffers of the whole batch (each holds the
+ * instances' buffers back to back plus the batch's tables). */
+vflb_status vflb_batch_query_buffers(const vflb_batch *batch,
+                                     size_t bytes[VFLB_NBUF]);
+
+/* Hand over the caller-owned buffers; binds every instance to its slice.
+ * Instances must be initialised again afterwards. */
+vflb_status vflb_batch_bind_buffers(vflb_batch *batch,
+                                    void *const dev_ptrs[VFLB_NBUF]);
+
+/* Handle of instance i (owned by the batch; NULL when out of range).  Use
+ * it with vflb_set_params, vflb_set_force (not COS_T), vflb_set_boundaries,
+ * vflb_set_storage_scale, vflb_init_fields, vflb_reduce, vflb_read,
+ * vflb_save and vflb_load; vflb_step, vflb_bind_buffers and vflb_set_tile
+ * on it fail. */
+vflb_sim *vflb_batch_instance(vflb_batch *batch, int i);
+
+/* Number of instances. */
+int vflb_batch_size(const vflb_batch *batch);
+
+/* Tile height of the batched step (4, 8 or 16; 0: built-in 8), and the
+ * height in use. */
+vflb_status vflb_batch_set_tile(vflb_batch *batch, int tile_y);
+int vflb_batch_get_tile(const vflb_batch *batch);
+
+/* Include (active = 1) or leave out (0) instance i from the steps and
+ * reductions; a left-out instance keeps its state and time level. */
+vflb_status vflb_batch_set_active(vflb_batch *batch, int i, int active);
+int vflb_batch_is_active(const vflb_batch *batch, int i);
+
+/* Advance every active instance by nsteps.  The active instances must be
+ * initialised and at the same time level (ESTATE otherwise); COS_T forcing
+ * is not batched (EINVAL). */
+vflb_status vflb_batch_step(vflb_batch *batch, int64_t nsteps);
+
+/* vflb_reduce for every active instance in one pass (synchronises).  out
+ * holds 14 doubles per instance, instance-major, laid out as for
+ * vflb_reduce; an inactive instance keeps the values of its last
+ * reduction (NaN before any).  Non-finite moments are reported in
+ * out[14 i + 7], not as an error. */
+vflb_status vflb_batch_reduce(vflb_batch *batch, double *out);
+
+/* Run the active instances towards a steady state: every check_every steps
+ * (fewer when a cap is closer) reduce and leave out each instance whose
+ * residual R (vflb_reduce out[0]) fell below tol, whose step count reached
+ * max_steps[i], or that became non-finite; repeat until none is active.
+ * The tile table shrinks as instances leave.  Per instance: steps_out[i]
+ * its time level, resid_out[i] its last residual, status_out[i] a
+ * VFLB_RUN_* code.  A first reduction takes the residual snapshot when an
+ * instance has none. */
+vflb_status vflb_batch_run_until(vflb_batch *batch, double tol,
+                                 int64_t check_every, const int64_t *max_steps,
+                                 int64_t *steps_out, double *resid_out,
+                                 int *status_out);
+
+/* Choose the tile height of the batched step for the active set: looked up
+ * in the text cache file cache_path (NULL: the file named by the
+ * environment variable VFLB_AUTOTUNE_CACHE; no file: no cache), keyed by
+ * storage, size class, number of active instances and GPU architecture;
+ * otherwise measured by timing the candidates 4, 8 and 16, and appended to
+ * the cache.  Measuring overwrites the populations: the instances must be
+ * initialised afterwards.  *tile_y_out (may be NULL) receives the choice. */
+vflb_status vflb_batch_autotune(vflb_batch *batch, const char *cache_path,
+                                int *tile_y_out);
+
+/* Release the batch and its instance handles (not the caller's buffers). */
+void vflb_batch_destroy(vflb_batch *batch);
+
+/* Message of the last failed call on batch (or of the last failed
+ * vflb_batch_create when batch is NULL); never NULL. */
+const char *vflb_batch_last_error(const vflb_batch *batch);
 
 #ifdef __cplusplus
 }

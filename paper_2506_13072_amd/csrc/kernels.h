@@ -44,6 +44,18 @@ template <class S> struct StepArgs {
   int first;                 // t == 0: no previous source term
 };
 
+// Batched ensembles: one entry of the flattened tile table (a 64 x TY tile
+// of instance inst at origin (x0, y0)), and the per-instance arguments, with
+// pin in the population buffer of parity 0.
+struct BatchTile {
+  int inst, x0, y0, pad;
+};
+template <class S> struct BatchInst {
+  StepArgs<S> a;
+  typename StoreT<S>::R* snap;  // u, tau at the previous reduction
+  int snap_valid;
+};
+
 __device__ inline size_t node_of(int x, int y, int z, const Geo& g) {
   return ((size_t)z * g.ny + y) * g.nx + x;
 }
@@ -291,66 +303,66 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Accumulate one node's contribution to the reductions and refresh its
+// snapshot of u and tau (the residual compares against the snapshot taken
+// at the previous reduction).
 template <int D, class S>
-__global__ void __launch_bounds__(256) reduce_kernel(
-    const S* pin, typename StoreT<S>::R* snap, int snap_valid,
-    Geo g, Phys<typename StoreT<S>::R> P, ForceArgs<typename StoreT<S>::R> fa,
-    typename StoreT<S>::R inv_sf, typename StoreT<S>::R inv_sh,
-    double* partials) {
-  using R = typename StoreT<S>::R;
+__device__ inline void reduce_node(const S* pin, typename StoreT<S>::R* snap, int snap_valid,
+                                   int x, int y, int z, const Geo& g,
+                                   const Phys<typename StoreT<S>::R>& P,
+                                   const ForceArgs<typename StoreT<S>::R>& fa,
+                                   typename StoreT<S>::R inv_sf, typename StoreT<S>::R inv_sh,
+                                   double* acc) {
   using L = Lat<D>;
   constexpr int Q = L::Q, NC = L::NC;
-  double acc[NRED];
-#pragma unroll
-  for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
-  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
-       n += (size_t)gridDim.x * blockDim.x) {
-    int x, y, z;
-    node_xyz<D>(n, g, x, y, z);
-    NodeMoments<D, S> m;
-    node_moments<D, S>(pin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
-    bool finite = true;
-    for (int b = 0; b < D; ++b) {
-      const double ub = (double)m.u[b];
-      finite = finite && isfinite(ub);
-      if (snap_valid) {
-        const double d = ub - (double)snap[(size_t)b * g.N + n];
-        acc[0] += d * d;
-      }
-      acc[1] += ub * ub;
-      snap[(size_t)b * g.N + n] = m.u[b];
+  const size_t n = node_of(x, y, z, g);
+  NodeMoments<D, S> m;
+  node_moments<D, S>(pin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
+  bool finite = true;
+  for (int b = 0; b < D; ++b) {
+    const double ub = (double)m.u[b];
+    finite = finite && isfinite(ub);
+    if (snap_valid) {
+      const double d = ub - (double)snap[(size_t)b * g.N + n];
+      acc[0] += d * d;
     }
-    double tr = 0.0;
-    for (int c = 0; c < NC; ++c) {
-      const double tc = (double)m.tau[c];
-      finite = finite && isfinite(tc);
-      const double wgt = (L::ca(c) == L::cb(c)) ? 1.0 : 2.0;  // tensor norm
-      if (snap_valid) {
-        const double d = tc - (double)snap[(size_t)(D + c) * g.N + n];
-        acc[2] += wgt * d * d;
-      }
-      acc[3] += wgt * tc * tc;
-      if (L::ca(c) == L::cb(c)) tr += tc;
-      acc[11 + c] += (double)m.e[c] + ((L::ca(c) == L::cb(c)) ? 1.0 : 0.0);
-      snap[(size_t)(D + c) * g.N + n] = m.tau[c];
-    }
-    double M = 0.0, Pm[3] = {0, 0, 0};
-    for (int i = 0; i < Q; ++i) {
-      const double fi = (double)m.f[i];
-      M += fi;
-      for (int b = 0; b < D; ++b) Pm[b] += cdir<D>(i, b) * fi;
-    }
-    finite = finite && isfinite(M) && isfinite((double)m.p);
-    acc[4] += M;
-    acc[5] += Pm[0];
-    acc[6] += Pm[1];
-    acc[7] += Pm[2];
-    acc[8] += 0.5 * ((double)m.u[0] * m.u[0] + (double)m.u[1] * m.u[1] +
-                     (double)m.u[2] * m.u[2]);
-    acc[9] += 0.5 * tr;
-    acc[10] += finite ? 0.0 : 1.0;
+    acc[1] += ub * ub;
+    snap[(size_t)b * g.N + n] = m.u[b];
   }
-  __shared__ double red[256 / 64][NRED];
+  double tr = 0.0;
+  for (int c = 0; c < NC; ++c) {
+    const double tc = (double)m.tau[c];
+    finite = finite && isfinite(tc);
+    const double wgt = (L::ca(c) == L::cb(c)) ? 1.0 : 2.0;  // tensor norm
+    if (snap_valid) {
+      const double d = tc - (double)snap[(size_t)(D + c) * g.N + n];
+      acc[2] += wgt * d * d;
+    }
+    acc[3] += wgt * tc * tc;
+    if (L::ca(c) == L::cb(c)) tr += tc;
+    acc[11 + c] += (double)m.e[c] + ((L::ca(c) == L::cb(c)) ? 1.0 : 0.0);
+    snap[(size_t)(D + c) * g.N + n] = m.tau[c];
+  }
+  double M = 0.0, Pm[3] = {0, 0, 0};
+  for (int i = 0; i < Q; ++i) {
+    const double fi = (double)m.f[i];
+    M += fi;
+    for (int b = 0; b < D; ++b) Pm[b] += cdir<D>(i, b) * fi;
+  }
+  finite = finite && isfinite(M) && isfinite((double)m.p);
+  acc[4] += M;
+  acc[5] += Pm[0];
+  acc[6] += Pm[1];
+  acc[7] += Pm[2];
+  acc[8] += 0.5 * ((double)m.u[0] * m.u[0] + (double)m.u[1] * m.u[1] +
+                   (double)m.u[2] * m.u[2]);
+  acc[9] += 0.5 * tr;
+  acc[10] += finite ? 0.0 : 1.0;
+}
+
+// Sum acc over a 256-lane workgroup in a fixed order into out[0..NRED).
+__device__ inline void block_partials(const double* acc, double* out) {
+  __shared__ double red[4][NRED];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NRED; ++k) {
@@ -360,18 +372,67 @@ __global__ void __launch_bounds__(256) reduce_kernel(
   __syncthreads();
   if (threadIdx.x < NRED) {
     double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
-    partials[(size_t)blockIdx.x * NRED + threadIdx.x] = s;
+    for (int w = 0; w < 4; ++w) s += red[w][threadIdx.x];
+    out[threadIdx.x] = s;
   }
 }
 
-__global__ void reduce_finish_kernel(const double* partials, int nblocks,
-                                     double* out) {
-  const int k = threadIdx.x;
-  if (k >= NRED) return;
+template <int D, class S>
+__global__ void __launch_bounds__(256) reduce_kernel(
+    const S* pin, typename StoreT<S>::R* snap, int snap_valid,
+    Geo g, Phys<typename StoreT<S>::R> P, ForceArgs<typename StoreT<S>::R> fa,
+    typename StoreT<S>::R inv_sf, typename StoreT<S>::R inv_sh,
+    double* partials) {
+  double acc[NRED];
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    node_xyz<D>(n, g, x, y, z);
+    reduce_node<D, S>(pin, snap, snap_valid, x, y, z, g, P, fa, inv_sf, inv_sh, acc);
+  }
+  block_partials(acc, partials + (size_t)blockIdx.x * NRED);
+}
+
+// out[r][k] = sum of partials[b][k] over b in [ranges[2r], ranges[2r+1])
+// (ranges == nullptr: the single range [0, nb)), for r = blockIdx.x and
+// k = blockIdx.y.  Lane j sums b = begin + j, begin + j + 256, ... and the
+// lanes combine in a fixed tree, so the result does not depend on timing.
+__global__ void __launch_bounds__(256) reduce_finish_kernel(const double* partials,
+                                                            const int* ranges, int nb,
+                                                            double* out) {
+  const int r = blockIdx.x, k = blockIdx.y;
+  const int b0 = ranges ? ranges[2 * r] : 0, b1 = ranges ? ranges[2 * r + 1] : nb;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * NRED + k];
-  out[k] = s;
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += 256) s += partials[(size_t)b * NRED + k];
+  __shared__ double red[4];
+  const double v = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[(size_t)r * NRED + k] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Reductions of a batched ensemble: one workgroup per tile-table entry
+// (tile_h rows of 64 nodes), partials[k] for entry k.
+template <class S>
+__global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchInst<S>* __restrict__ desc,
+                                                           const BatchTile* __restrict__ tiles,
+                                                           int tile_h, int parity,
+                                                           double* partials) {
+  const BatchTile e = tiles[blockIdx.x];
+  const BatchInst<S>& d = desc[e.inst];
+  const S* pin = parity ? d.a.pout : d.a.pin;
+  double acc[NRED];
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+  for (int j = threadIdx.x; j < 64 * tile_h; j += blockDim.x) {
+    const int x = e.x0 + (j & 63), y = e.y0 + (j >> 6);
+    if (x < d.a.g.nx && y < d.a.g.ny)
+      reduce_node<2, S>(pin, d.snap, d.snap_valid, x, y, 0, d.a.g, d.a.P, d.a.F, d.a.inv_sf,
+                        d.a.inv_sh, acc);
+  }
+  block_partials(acc, partials + (size_t)blockIdx.x * NRED);
 }
 
 // plain streaming copy: one 16-byte vector per lane, non-temporal

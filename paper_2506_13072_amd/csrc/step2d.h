@@ -57,12 +57,22 @@ __device__ inline void velocity2(const R* f, const R* F, R* u) {
   u[1] = (f[2] - f[4] + f[5] + f[6] - f[7] - f[8]) + (R)0.5 * F[1];
 }
 
+// LDS of one 64 x TY tile: the velocity on the tile and its one-node halo
+template <class R, int TY>
+struct Tile2Lds {
+  R su[2][66 * (TY + 2)];
+};
+
+// One 64 x TY tile of the step at origin (x0, y0).  The workgroup's lanes
+// are (threadIdx.x, threadIdx.y) = (0..63, 0..TY-1); the tile contains one
+// barrier, so every lane of the workgroup calls it.
 template <class S, int TY>
-__global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx, int nty) {
+__device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
+                                   Tile2Lds<typename StoreT<S>::R, TY>& lds) {
   using R = typename StoreT<S>::R;
-  constexpr int Q = 9, NC = 3, TX = 64, SX = TX + 2, SY = TY + 2, NS = SX * SY;
+  constexpr int Q = 9, NC = 3, TX = 64, SX = TX + 2, SY = TY + 2;
   constexpr int H = 2 * SX + 2 * TY;  // halo nodes of the tile
-  __shared__ R su[2][NS];
+  R (*su)[SX * SY] = lds.su;
 
   const Geo g = a.g;
   const S* __restrict__ pin = a.pin;
@@ -70,10 +80,6 @@ __global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx,
   R* __restrict__ aux = a.aux;
   const size_t N = g.N;
   using P2 = Pops<2, S>;
-
-  const int tile = blockIdx.x;
-  const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
-  (void)nty;
 
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * TX + tx;
@@ -185,6 +191,38 @@ __global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx,
     P2::store(pout, (size_t)i * N + n, N, a.sf, a.sh, f[i], hv);
   }
   Aux<2, R>::store(aux, n, N, chi, u);
+}
+
+template <class S, int TY>
+__global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx, int nty) {
+  __shared__ Tile2Lds<typename StoreT<S>::R, TY> lds;
+  (void)nty;
+  step2d_tile<S, TY>(a, (blockIdx.x % ntx) * 64, (blockIdx.x / ntx) * TY, lds);
+}
+
+// Batched step over many lattices: a persistent launch whose workgroups walk
+// a flattened table of (instance, tile) entries.  desc[inst] holds the
+// instance's step arguments with pin in the buffer of parity 0; for parity 1
+// the two population buffers swap.  Each tile runs the very same tile
+// function as the single-lattice kernel, so a lattice advanced inside a
+// batch takes bitwise the values it takes alone.
+template <class S, int TY>
+__global__ void __launch_bounds__(64 * TY) batch2d_kernel(const BatchInst<S>* __restrict__ desc,
+                                                         const BatchTile* __restrict__ tiles,
+                                                         int ntiles, int parity, int first) {
+  __shared__ Tile2Lds<typename StoreT<S>::R, TY> lds;
+  for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
+    const BatchTile e = tiles[k];
+    StepArgs<S> a = desc[e.inst].a;
+    if (parity) {
+      const S* in = a.pout;
+      a.pout = const_cast<S*>(a.pin);
+      a.pin = in;
+    }
+    a.first = first;
+    step2d_tile<S, TY>(a, e.x0, e.y0, lds);
+    __syncthreads();  // the next tile reuses the LDS
+  }
 }
 
 }  // namespace vflb

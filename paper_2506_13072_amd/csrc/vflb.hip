@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "../../include/vflb.h"
 #include "kernels.h"
@@ -53,6 +55,7 @@ struct vflb_sim {
   int tile_y = 0;
   size_t off_tab = 0, off_part = 0, off_res = 0, off_hdr = 0;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  bool is_view = false;  // an instance of a batch: buffers and stepping belong to the batch
   std::string err;
 
   size_t store_bytes() const {
@@ -148,8 +151,9 @@ int grid1d(const vflb_sim* s, int block) {
 }
 
 // ----------------------------------------------------------- templated ops
-template <int D, class S>
-vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
+// arguments of one step from buffer parity `parity` at time level t
+template <class S>
+StepArgs<S> make_step_args(const vflb_sim* s, int64_t t, int parity) {
   using R = typename StoreT<S>::R;
   StepArgs<S> a;
   a.pin = static_cast<const S*>(s->buf[VFLB_BUF_POP0 + parity]);
@@ -164,6 +168,12 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
   a.inv_sh = (R)std::ldexp(1.0, -s->log2_sh);
   if (s->storage != VFLB_F16S) a.sf = a.inv_sf = a.sh = a.inv_sh = (R)1;
   a.first = (t == 0);
+  return a;
+}
+
+template <int D, class S>
+vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
+  const StepArgs<S> a = make_step_args<S>(s, t, parity);
   if constexpr (D == 2) {
     const int ty = default_tile_y(s);
     const int ntx = (s->nx + 63) / 64, nty = (s->ny + ty - 1) / ty;
@@ -250,8 +260,8 @@ vflb_status launch_reduce(vflb_sim* s, double* dev_res) {
                      static_cast<R*>(s->buf[VFLB_BUF_SNAP]), s->snap_valid ? 1 : 0,
                      geo_of(s), phys_of<R>(s), force_of<R>(s, s->t), isf, ish, part);
   HIP_TRY(s, hipGetLastError());
-  hipLaunchKernelGGL(reduce_finish_kernel, dim3(1), dim3(64), 0, s->stream, part, nb,
-                     dev_res);
+  hipLaunchKernelGGL(reduce_finish_kernel, dim3(1, NRED), dim3(256), 0, s->stream, part,
+                     (const int*)nullptr, nb, dev_res);
   HIP_TRY(s, hipGetLastError());
   return VFLB_OK;
 }
@@ -294,6 +304,29 @@ template <int D, class S> struct RedOp {
   static vflb_status run(vflb_sim* s, double* res) { return launch_reduce<D, S>(s, res); }
 };
 
+// The 14 reported values from the NRED sums; marks the snapshot valid.
+vflb_status finish_reduce(vflb_sim* s, const double* r, double out[14]) {
+  const bool had = s->snap_valid;
+  s->snap_valid = true;
+  double R = INFINITY;
+  if (had) {
+    const double ru = r[1] > 0 ? std::sqrt(r[0] / r[1]) : (r[0] > 0 ? INFINITY : 0.0);
+    const double rt = r[3] > 0 ? std::sqrt(r[2] / r[3]) : (r[2] > 0 ? INFINITY : 0.0);
+    R = ru > rt ? ru : rt;
+  }
+  out[0] = R;
+  out[1] = r[4];
+  out[2] = r[5];
+  out[3] = r[6];
+  out[4] = r[7];
+  out[5] = r[8] / (double)s->N;
+  out[6] = r[9] / (double)s->N;
+  out[7] = r[10];
+  for (int c = 0; c < 6; ++c) out[8 + c] = c < s->NC ? r[11 + c] : 0.0;
+  if (r[10] > 0) return fail(s, VFLB_EUNSTABLE, "%.0f nodes hold non-finite moments", r[10]);
+  return VFLB_OK;
+}
+
 vflb_status need_ready(vflb_sim* s) {
   if (!s) return VFLB_EINVAL;
   if (!s->bound) return fail(s, VFLB_ESTATE, "device buffers are not bound");
@@ -330,8 +363,12 @@ vflb_status build_graph(vflb_sim* s, int parity) {
 // ====================================================================== ABI
 extern "C" {
 
-vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
-                        void* hip_stream, vflb_sim** out) {
+namespace {
+
+// A lattice and the sizes of its buffers.  A view (an instance of a batch)
+// has no capture stream: it is stepped by its batch.
+vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_t stream,
+                    bool view, vflb_sim** out) {
   if (!out) return fail(nullptr, VFLB_EINVAL, "out is NULL");
   *out = nullptr;
   if (lattice != VFLB_D2Q9 && lattice != VFLB_D3Q19)
@@ -358,7 +395,8 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
   s->nz = nz;
   s->N = N;
   s->storage = storage;
-  s->stream = static_cast<hipStream_t>(hip_stream);
+  s->stream = stream;
+  s->is_view = view;
   const size_t sb = s->store_bytes(), ab = s->arith_bytes();
   const size_t words =
       lattice == VFLB_D2Q9 ? Pops<2, float>::words(N) : Pops<3, float>::words(N);
@@ -370,12 +408,19 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
   s->off_res = s->off_part + align256(sizeof(double) * NRED * kRedBlocksMax);
   s->off_hdr = s->off_res + align256(sizeof(double) * NRED);
   s->bytes[VFLB_BUF_WORK] = s->off_hdr + 256;
-  if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+  if (!view && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete s;
     return fail(nullptr, VFLB_EDEVICE, "hipStreamCreate failed");
   }
   *out = s;
   return VFLB_OK;
+}
+
+}  // namespace
+
+vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
+                        void* hip_stream, vflb_sim** out) {
+  return sim_new(lattice, nx, ny, nz, storage, static_cast<hipStream_t>(hip_stream), false, out);
 }
 
 vflb_status vflb_query_buffers(const vflb_sim* s, size_t bytes[VFLB_NBUF]) {
@@ -386,6 +431,7 @@ vflb_status vflb_query_buffers(const vflb_sim* s, size_t bytes[VFLB_NBUF]) {
 
 vflb_status vflb_bind_buffers(vflb_sim* s, void* const dev_ptrs[VFLB_NBUF]) {
   if (!s || !dev_ptrs) return VFLB_EINVAL;
+  if (s->is_view) return fail(s, VFLB_EINVAL, "a batch instance uses the batch's buffers");
   for (int k = 0; k < VFLB_NBUF; ++k)
     if (!dev_ptrs[k]) return fail(s, VFLB_EINVAL, "buffer %d is NULL", k);
   for (int k = 0; k < VFLB_NBUF; ++k) s->buf[k] = dev_ptrs[k];
@@ -501,6 +547,7 @@ vflb_status vflb_set_storage_scale(vflb_sim* s, int log2_f, int log2_h) {
 
 vflb_status vflb_set_tile(vflb_sim* s, int tile_y) {
   if (!s) return VFLB_EINVAL;
+  if (s->is_view) return fail(s, VFLB_EINVAL, "set the tile shape on the batch");
   if (tile_y != 0 && tile_y != 4 && tile_y != 8 && (tile_y != 16 || s->D == 3))
     return fail(s, VFLB_EINVAL, "tile_y must be 0, 4, 8 or 16 (D2Q9), 0, 4 or 8 (D3Q19)");
   s->tile_y = tile_y;
@@ -524,6 +571,7 @@ vflb_status vflb_init_fields(vflb_sim* s, const double* u, const double* tau,
 vflb_status vflb_step(vflb_sim* s, int64_t nsteps) {
   vflb_status rc = need_ready(s);
   if (rc != VFLB_OK) return rc;
+  if (s->is_view) return fail(s, VFLB_ESTATE, "a batch instance is stepped by vflb_batch_step");
   if (!s->inited) return fail(s, VFLB_ESTATE, "initialise the fields before stepping");
   if (nsteps < 0) return fail(s, VFLB_EINVAL, "nsteps < 0");
   while (nsteps > 0) {
@@ -561,25 +609,7 @@ vflb_status vflb_reduce(vflb_sim* s, double out[14]) {
   double r[NRED];
   HIP_TRY(s, hipMemcpyAsync(r, dres, sizeof r, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(s, hipStreamSynchronize(s->stream));
-  const bool had = s->snap_valid;
-  s->snap_valid = true;
-  double R = INFINITY;
-  if (had) {
-    const double ru = r[1] > 0 ? std::sqrt(r[0] / r[1]) : (r[0] > 0 ? INFINITY : 0.0);
-    const double rt = r[3] > 0 ? std::sqrt(r[2] / r[3]) : (r[2] > 0 ? INFINITY : 0.0);
-    R = ru > rt ? ru : rt;
-  }
-  out[0] = R;
-  out[1] = r[4];
-  out[2] = r[5];
-  out[3] = r[6];
-  out[4] = r[7];
-  out[5] = r[8] / (double)s->N;
-  out[6] = r[9] / (double)s->N;
-  out[7] = r[10];
-  for (int c = 0; c < 6; ++c) out[8 + c] = c < s->NC ? r[11 + c] : 0.0;
-  if (r[10] > 0) return fail(s, VFLB_EUNSTABLE, "%.0f nodes hold non-finite moments", r[10]);
-  return VFLB_OK;
+  return finish_reduce(s, r, out);
 }
 
 vflb_status vflb_read(vflb_sim* s, int field, double* dev_dst, size_t n) {
@@ -703,7 +733,7 @@ vflb_status vflb_stream_copy(const void* src, void* dst, size_t nbytes, void* hi
 }
 
 void vflb_destroy(vflb_sim* s) {
-  if (!s) return;
+  if (!s || s->is_view) return;
   drop_graphs(s);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
@@ -712,6 +742,570 @@ void vflb_destroy(vflb_sim* s) {
 const char* vflb_last_error(const vflb_sim* s) {
   if (!s) return g_create_error.c_str();
   return s->err.c_str();
+}
+
+
+// ================================================================ batches
+}  // extern "C"
+
+struct vflb_batch {
+  int D = 2, storage = VFLB_F32, n = 0;
+  hipStream_t stream = nullptr, cap_stream = nullptr;
+  void* buf[VFLB_NBUF] = {};
+  size_t bytes[VFLB_NBUF] = {};
+  bool bound = false;
+  std::vector<vflb_sim*> views;
+  std::vector<size_t> off[VFLB_NBUF];  // per-instance byte offsets into the pools
+  size_t off_desc = 0, off_tiles = 0, off_part = 0, off_rng = 0, off_res = 0;
+  size_t max_tiles = 0;
+  std::vector<char> active;
+  std::vector<double> last;  // last reduction per instance (14 values)
+  int tile_y = 0;            // 0: built-in choice
+  // tables of the active set (host copies of what the device holds)
+  bool tables_ok = false;
+  int tables_ty = 0;
+  std::vector<BatchTile> tiles;
+  std::vector<int> ranges;  // per active instance: [begin, end) in tiles
+  std::vector<int> act;     // active instance ids in table order
+  std::vector<char> desc_host, desc_dev;  // descriptor bytes built / last uploaded
+  int grid_cap[3] = {0, 0, 0};  // persistent grid per tile height 4, 8, 16
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_create_error;
+
+vflb_status bfail(vflb_batch* b, vflb_status code, const char* fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  if (b)
+    b->err = msg;
+  else
+    g_batch_create_error = msg;
+  return code;
+}
+
+#define BHIP_TRY(b, call)                                                  \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return bfail((b), VFLB_EDEVICE, "%s failed: %s", #call,              \
+                   hipGetErrorString(e_));                                 \
+  } while (0)
+
+void bdrop_graphs(vflb_batch* b) {
+  for (int k = 0; k < 2; ++k) {
+    if (b->gexec[k]) (void)hipGraphExecDestroy(b->gexec[k]);
+    b->gexec[k] = nullptr;
+  }
+}
+
+int batch_ty(const vflb_batch* b) { return b->tile_y ? b->tile_y : 8; }
+int ty_slot(int ty) { return ty == 4 ? 0 : (ty == 8 ? 1 : 2); }
+
+size_t desc_size(int storage) {
+  switch (storage) {
+    case VFLB_F64: return sizeof(BatchInst<double>);
+    case VFLB_F32: return sizeof(BatchInst<float>);
+    case VFLB_F16S: return sizeof(BatchInst<_Float16>);
+    default: return sizeof(BatchInst<bf16_t>);
+  }
+}
+
+// Tile table of the active instances for tile height ty: per instance its
+// 64 x ty tiles in row-major order, instances in index order.
+vflb_status build_tables(vflb_batch* b, int ty) {
+  b->tiles.clear();
+  b->ranges.clear();
+  b->act.clear();
+  for (int i = 0; i < b->n; ++i) {
+    if (!b->active[i]) continue;
+    const vflb_sim* v = b->views[i];
+    const int ntx = (v->nx + 63) / 64, nty = (v->ny + ty - 1) / ty;
+    b->ranges.push_back((int)b->tiles.size());
+    for (int yt = 0; yt < nty; ++yt)
+      for (int xt = 0; xt < ntx; ++xt) b->tiles.push_back(BatchTile{i, xt * 64, yt * ty, 0});
+    b->ranges.push_back((int)b->tiles.size());
+    b->act.push_back(i);
+  }
+  char* w = static_cast<char*>(b->buf[VFLB_BUF_WORK]);
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));  // earlier uploads may still read the host copies
+  if (!b->tiles.empty())
+    BHIP_TRY(b, hipMemcpyAsync(w + b->off_tiles, b->tiles.data(),
+                               b->tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
+                               b->stream));
+  if (!b->ranges.empty())
+    BHIP_TRY(b, hipMemcpyAsync(w + b->off_rng, b->ranges.data(), b->ranges.size() * sizeof(int),
+                               hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  b->tables_ok = true;
+  b->tables_ty = ty;
+  bdrop_graphs(b);
+  return VFLB_OK;
+}
+
+template <class S>
+void fill_desc(vflb_batch* b) {
+  using R = typename StoreT<S>::R;
+  b->desc_host.assign((size_t)b->n * sizeof(BatchInst<S>), 0);
+  BatchInst<S>* d = reinterpret_cast<BatchInst<S>*>(b->desc_host.data());
+  for (int i = 0; i < b->n; ++i) {
+    const vflb_sim* v = b->views[i];
+    d[i].a = make_step_args<S>(v, 1, 0);
+    d[i].snap = static_cast<R*>(v->buf[VFLB_BUF_SNAP]);
+    d[i].snap_valid = v->snap_valid ? 1 : 0;
+  }
+}
+
+// (Re)build the per-instance descriptors from the instance views and upload
+// them when they changed.
+vflb_status sync_desc(vflb_batch* b) {
+  switch (b->storage) {
+    case VFLB_F64: fill_desc<double>(b); break;
+    case VFLB_F32: fill_desc<float>(b); break;
+    case VFLB_F16S: fill_desc<_Float16>(b); break;
+    default: fill_desc<bf16_t>(b); break;
+  }
+  if (b->desc_host == b->desc_dev) return VFLB_OK;
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  b->desc_dev = b->desc_host;
+  BHIP_TRY(b, hipMemcpyAsync(static_cast<char*>(b->buf[VFLB_BUF_WORK]) + b->off_desc,
+                             b->desc_dev.data(), b->desc_dev.size(), hipMemcpyHostToDevice,
+                             b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  return VFLB_OK;
+}
+
+template <class S, int TY>
+vflb_status launch_batch_ty(vflb_batch* b, hipStream_t st, int parity, int first) {
+  int& cap = b->grid_cap[ty_slot(TY)];
+  if (cap == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    BHIP_TRY(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch2d_kernel<S, TY>,
+                                                             64 * TY, 0));
+    BHIP_TRY(b, hipGetDevice(&dev));
+    BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    cap = std::max(1, per_cu) * std::max(1, cus);
+  }
+  const int ntiles = (int)b->tiles.size();
+  const int grid = std::min(ntiles, cap);
+  const char* w = static_cast<const char*>(b->buf[VFLB_BUF_WORK]);
+  hipLaunchKernelGGL((batch2d_kernel<S, TY>), dim3(grid), dim3(64, TY), 0, st,
+                     reinterpret_cast<const BatchInst<S>*>(w + b->off_desc),
+                     reinterpret_cast<const BatchTile*>(w + b->off_tiles), ntiles, parity, first);
+  BHIP_TRY(b, hipGetLastError());
+  return VFLB_OK;
+}
+
+template <class S>
+vflb_status launch_batch_s(vflb_batch* b, hipStream_t st, int parity, int first) {
+  switch (b->tables_ty) {
+    case 4: return launch_batch_ty<S, 4>(b, st, parity, first);
+    case 16: return launch_batch_ty<S, 16>(b, st, parity, first);
+    default: return launch_batch_ty<S, 8>(b, st, parity, first);
+  }
+}
+
+vflb_status launch_batch(vflb_batch* b, hipStream_t st, int parity, int first) {
+  if (b->tiles.empty()) return VFLB_OK;
+  switch (b->storage) {
+    case VFLB_F64: return launch_batch_s<double>(b, st, parity, first);
+    case VFLB_F32: return launch_batch_s<float>(b, st, parity, first);
+    case VFLB_F16S: return launch_batch_s<_Float16>(b, st, parity, first);
+    default: return launch_batch_s<bf16_t>(b, st, parity, first);
+  }
+}
+
+vflb_status build_batch_graph(vflb_batch* b, int parity) {
+  BHIP_TRY(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  vflb_status rc = VFLB_OK;
+  for (int k = 0; k < kGraphSteps && rc == VFLB_OK; ++k)
+    rc = launch_batch(b, b->cap_stream, parity ^ (k & 1), 0);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+  if (rc != VFLB_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return bfail(b, VFLB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&b->gexec[parity], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    b->gexec[parity] = nullptr;
+    return bfail(b, VFLB_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  return VFLB_OK;
+}
+
+// The active instances must share their time level and buffer parity.
+vflb_status check_active(vflb_batch* b, int64_t* t, int* cur) {
+  if (!b->bound) return bfail(b, VFLB_ESTATE, "device buffers are not bound");
+  bool any = false;
+  for (int i = 0; i < b->n; ++i) {
+    if (!b->active[i]) continue;
+    const vflb_sim* v = b->views[i];
+    if (!v->have_params) return bfail(b, VFLB_ESTATE, "instance %d has no parameters", i);
+    if (!v->inited) return bfail(b, VFLB_ESTATE, "instance %d is not initialised", i);
+    if (v->fkind == VFLB_FORCE_COS_T)
+      return bfail(b, VFLB_EINVAL, "instance %d: time-periodic forcing is not batched", i);
+    if (!any) {
+      *t = v->t;
+      *cur = v->cur;
+      any = true;
+    } else if (v->t != *t || v->cur != *cur) {
+      return bfail(b, VFLB_ESTATE, "active instances are at different time levels");
+    }
+  }
+  if (!any) {
+    *t = 0;
+    *cur = 0;
+  }
+  return VFLB_OK;
+}
+
+vflb_status ensure_tables(vflb_batch* b) {
+  const int ty = batch_ty(b);
+  if (!b->tables_ok || b->tables_ty != ty) return build_tables(b, ty);
+  return VFLB_OK;
+}
+
+template <class S>
+vflb_status launch_batch_reduce_s(vflb_batch* b, int parity) {
+  char* w = static_cast<char*>(b->buf[VFLB_BUF_WORK]);
+  double* part = reinterpret_cast<double*>(w + b->off_part);
+  hipLaunchKernelGGL((batch_reduce_kernel<S>), dim3((unsigned)b->tiles.size()), dim3(256), 0,
+                     b->stream, reinterpret_cast<const BatchInst<S>*>(w + b->off_desc),
+                     reinterpret_cast<const BatchTile*>(w + b->off_tiles), b->tables_ty, parity,
+                     part);
+  BHIP_TRY(b, hipGetLastError());
+  hipLaunchKernelGGL(reduce_finish_kernel, dim3((unsigned)b->act.size(), NRED), dim3(256), 0,
+                     b->stream, part, reinterpret_cast<const int*>(w + b->off_rng), 0,
+                     reinterpret_cast<double*>(w + b->off_res));
+  BHIP_TRY(b, hipGetLastError());
+  return VFLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vflb_status vflb_batch_create(int lattice, int n, const int* dims, int storage,
+                              void* hip_stream, vflb_batch** out) {
+  if (!out) return bfail(nullptr, VFLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (lattice != VFLB_D2Q9) return bfail(nullptr, VFLB_EINVAL, "batches hold D2Q9 lattices");
+  if (n < 1 || !dims) return bfail(nullptr, VFLB_EINVAL, "need n >= 1 and dims");
+  if (storage < VFLB_F64 || storage > VFLB_BF16S)
+    return bfail(nullptr, VFLB_EINVAL, "unknown storage %d", storage);
+  vflb_batch* b = new vflb_batch();
+  b->D = lattice;
+  b->storage = storage;
+  b->n = n;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  size_t total[VFLB_NBUF] = {};
+  for (int i = 0; i < n; ++i) {
+    vflb_sim* v = nullptr;
+    if (sim_new(lattice, dims[3 * i], dims[3 * i + 1], 1, storage, b->stream, true, &v) !=
+        VFLB_OK) {
+      const std::string msg = g_create_error;
+      vflb_batch_destroy(b);
+      return bfail(nullptr, VFLB_EINVAL, "instance %d: %s", i, msg.c_str());
+    }
+    b->views.push_back(v);
+    for (int k = 0; k < VFLB_NBUF; ++k) {
+      b->off[k].push_back(total[k]);
+      total[k] += align256(v->bytes[k]);
+    }
+    b->max_tiles += (size_t)((v->nx + 63) / 64) * ((v->ny + 3) / 4);
+  }
+  size_t w = total[VFLB_BUF_WORK];
+  b->off_desc = w;
+  w += align256((size_t)n * desc_size(storage));
+  b->off_tiles = w;
+  w += align256(b->max_tiles * sizeof(BatchTile));
+  b->off_part = w;
+  w += align256(b->max_tiles * NRED * sizeof(double));
+  b->off_rng = w;
+  w += align256((size_t)2 * n * sizeof(int));
+  b->off_res = w;
+  w += align256((size_t)n * NRED * sizeof(double));
+  total[VFLB_BUF_WORK] = w;
+  for (int k = 0; k < VFLB_NBUF; ++k) b->bytes[k] = total[k];
+  b->active.assign(n, 1);
+  b->last.assign((size_t)14 * n, NAN);
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    vflb_batch_destroy(b);
+    return bfail(nullptr, VFLB_EDEVICE, "hipStreamCreate failed");
+  }
+  *out = b;
+  return VFLB_OK;
+}
+
+vflb_status vflb_batch_query_buffers(const vflb_batch* b, size_t bytes[VFLB_NBUF]) {
+  if (!b || !bytes) return VFLB_EINVAL;
+  for (int k = 0; k < VFLB_NBUF; ++k) bytes[k] = b->bytes[k];
+  return VFLB_OK;
+}
+
+vflb_status vflb_batch_bind_buffers(vflb_batch* b, void* const dev_ptrs[VFLB_NBUF]) {
+  if (!b || !dev_ptrs) return VFLB_EINVAL;
+  for (int k = 0; k < VFLB_NBUF; ++k)
+    if (!dev_ptrs[k]) return bfail(b, VFLB_EINVAL, "buffer %d is NULL", k);
+  for (int k = 0; k < VFLB_NBUF; ++k) b->buf[k] = dev_ptrs[k];
+  for (int i = 0; i < b->n; ++i) {
+    vflb_sim* v = b->views[i];
+    for (int k = 0; k < VFLB_NBUF; ++k) v->buf[k] = static_cast<char*>(dev_ptrs[k]) + b->off[k][i];
+    v->bound = true;
+    v->inited = false;
+  }
+  b->bound = true;
+  b->tables_ok = false;
+  b->desc_dev.clear();
+  bdrop_graphs(b);
+  return VFLB_OK;
+}
+
+vflb_sim* vflb_batch_instance(vflb_batch* b, int i) {
+  if (!b || i < 0 || i >= b->n) return nullptr;
+  return b->views[i];
+}
+
+int vflb_batch_size(const vflb_batch* b) { return b ? b->n : -1; }
+
+vflb_status vflb_batch_set_tile(vflb_batch* b, int tile_y) {
+  if (!b) return VFLB_EINVAL;
+  if (tile_y != 0 && tile_y != 4 && tile_y != 8 && tile_y != 16)
+    return bfail(b, VFLB_EINVAL, "tile_y must be 0, 4, 8 or 16");
+  b->tile_y = tile_y;
+  bdrop_graphs(b);
+  return VFLB_OK;
+}
+
+int vflb_batch_get_tile(const vflb_batch* b) { return b ? batch_ty(b) : -1; }
+
+vflb_status vflb_batch_set_active(vflb_batch* b, int i, int active) {
+  if (!b || i < 0 || i >= b->n) return VFLB_EINVAL;
+  if ((b->active[i] != 0) != (active != 0)) {
+    b->active[i] = active ? 1 : 0;
+    b->tables_ok = false;
+    bdrop_graphs(b);
+  }
+  return VFLB_OK;
+}
+
+int vflb_batch_is_active(const vflb_batch* b, int i) {
+  if (!b || i < 0 || i >= b->n) return -1;
+  return b->active[i] ? 1 : 0;
+}
+
+vflb_status vflb_batch_step(vflb_batch* b, int64_t nsteps) {
+  if (!b) return VFLB_EINVAL;
+  if (nsteps < 0) return bfail(b, VFLB_EINVAL, "nsteps < 0");
+  int64_t t;
+  int cur;
+  vflb_status rc = check_active(b, &t, &cur);
+  if (rc != VFLB_OK) return rc;
+  if ((rc = ensure_tables(b)) != VFLB_OK) return rc;
+  if (b->act.empty() || nsteps == 0) return VFLB_OK;
+  if ((rc = sync_desc(b)) != VFLB_OK) return rc;
+  int64_t left = nsteps;
+  while (left > 0) {
+    if (t > 0 && left >= kGraphSteps && b->stream != nullptr) {
+      if (!b->gexec[cur] && (rc = build_batch_graph(b, cur)) != VFLB_OK) return rc;
+      BHIP_TRY(b, hipGraphLaunch(b->gexec[cur], b->stream));
+      t += kGraphSteps;  // even: parity unchanged
+      left -= kGraphSteps;
+      continue;
+    }
+    if ((rc = launch_batch(b, b->stream, cur, t == 0 ? 1 : 0)) != VFLB_OK) return rc;
+    cur ^= 1;
+    t += 1;
+    left -= 1;
+  }
+  for (int i : b->act) {
+    b->views[i]->t = t;
+    b->views[i]->cur = cur;
+  }
+  return VFLB_OK;
+}
+
+vflb_status vflb_batch_reduce(vflb_batch* b, double* out) {
+  if (!b || !out) return VFLB_EINVAL;
+  int64_t t;
+  int cur;
+  vflb_status rc = check_active(b, &t, &cur);
+  if (rc != VFLB_OK) return rc;
+  if ((rc = ensure_tables(b)) != VFLB_OK) return rc;
+  if (!b->act.empty()) {
+    if ((rc = sync_desc(b)) != VFLB_OK) return rc;
+    switch (b->storage) {
+      case VFLB_F64: rc = launch_batch_reduce_s<double>(b, cur); break;
+      case VFLB_F32: rc = launch_batch_reduce_s<float>(b, cur); break;
+      case VFLB_F16S: rc = launch_batch_reduce_s<_Float16>(b, cur); break;
+      default: rc = launch_batch_reduce_s<bf16_t>(b, cur); break;
+    }
+    if (rc != VFLB_OK) return rc;
+    std::vector<double> r(b->act.size() * NRED);
+    BHIP_TRY(b, hipMemcpyAsync(r.data(), static_cast<char*>(b->buf[VFLB_BUF_WORK]) + b->off_res,
+                               r.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    for (size_t k = 0; k < b->act.size(); ++k) {
+      const int i = b->act[k];
+      (void)finish_reduce(b->views[i], &r[k * NRED], &b->last[(size_t)14 * i]);
+    }
+  }
+  std::copy(b->last.begin(), b->last.end(), out);
+  return VFLB_OK;
+}
+
+vflb_status vflb_batch_run_until(vflb_batch* b, double tol, int64_t check_every,
+                                 const int64_t* max_steps, int64_t* steps_out,
+                                 double* resid_out, int* status_out) {
+  if (!b || !max_steps || !steps_out || !resid_out || !status_out) return VFLB_EINVAL;
+  if (!(tol >= 0) || check_every < 1) return bfail(b, VFLB_EINVAL, "need tol >= 0 and check_every >= 1");
+  int64_t t;
+  int cur;
+  vflb_status rc = check_active(b, &t, &cur);
+  if (rc != VFLB_OK) return rc;
+  std::vector<double> red((size_t)14 * b->n);
+  for (int i = 0; i < b->n; ++i) status_out[i] = b->active[i] ? VFLB_RUN_ACTIVE : VFLB_RUN_SKIPPED;
+  bool need_snap = false;
+  for (int i = 0; i < b->n; ++i) need_snap = need_snap || (b->active[i] && !b->views[i]->snap_valid);
+  if (need_snap && (rc = vflb_batch_reduce(b, red.data())) != VFLB_OK) return rc;
+  for (;;) {
+    int64_t k = check_every;
+    for (int i = 0; i < b->n; ++i) {
+      if (!b->active[i]) continue;
+      const int64_t rem = max_steps[i] - b->views[i]->t;
+      if (rem <= 0) {
+        status_out[i] = VFLB_RUN_CAPPED;
+        vflb_batch_set_active(b, i, 0);
+      } else if (rem < k) {
+        k = rem;
+      }
+    }
+    bool any = false;
+    for (int i = 0; i < b->n; ++i) any = any || b->active[i];
+    if (!any) break;
+    if ((rc = vflb_batch_step(b, k)) != VFLB_OK) return rc;
+    if ((rc = vflb_batch_reduce(b, red.data())) != VFLB_OK) return rc;
+    for (int i = 0; i < b->n; ++i) {
+      if (!b->active[i]) continue;
+      const double R = red[(size_t)14 * i], bad = red[(size_t)14 * i + 7];
+      if (bad > 0) status_out[i] = VFLB_RUN_UNSTABLE;
+      else if (R < tol) status_out[i] = VFLB_RUN_CONVERGED;
+      else if (b->views[i]->t >= max_steps[i]) status_out[i] = VFLB_RUN_CAPPED;
+      else continue;
+      vflb_batch_set_active(b, i, 0);
+    }
+  }
+  for (int i = 0; i < b->n; ++i) {
+    steps_out[i] = b->views[i]->t;
+    resid_out[i] = b->last[(size_t)14 * i];
+  }
+  return VFLB_OK;
+}
+
+vflb_status vflb_batch_autotune(vflb_batch* b, const char* cache_path, int* tile_y_out) {
+  if (!b) return VFLB_EINVAL;
+  if (!b->bound) return bfail(b, VFLB_ESTATE, "device buffers are not bound");
+  size_t nodes = 0;
+  for (int i = 0; i < b->n; ++i)
+    if (b->active[i]) nodes += b->views[i]->N;
+  if (nodes == 0) return bfail(b, VFLB_ESTATE, "no active instance");
+  int dev = 0;
+  hipDeviceProp_t prop;
+  BHIP_TRY(b, hipGetDevice(&dev));
+  BHIP_TRY(b, hipGetDeviceProperties(&prop, dev));
+  char key[256];
+  snprintf(key, sizeof key, "d2q9-batch storage=%d log2nodes=%d active=%d arch=%s", b->storage,
+           (int)std::lround(std::log2((double)nodes)), (int)std::count(b->active.begin(), b->active.end(), 1),
+           prop.gcnArchName);
+  std::string path;
+  if (cache_path && *cache_path) path = cache_path;
+  else if (const char* e = getenv("VFLB_AUTOTUNE_CACHE")) path = e;
+  if (!path.empty()) {
+    if (FILE* fp = fopen(path.c_str(), "r")) {
+      char line[512];
+      int found = 0;
+      while (fgets(line, sizeof line, fp)) {
+        const size_t kl = strlen(key);
+        int ty = 0;
+        if (strncmp(line, key, kl) == 0 && line[kl] == ' ' && sscanf(line + kl + 1, "%d", &ty) == 1 &&
+            (ty == 4 || ty == 8 || ty == 16))
+          found = ty;
+      }
+      fclose(fp);
+      if (found) {
+        b->tile_y = found;
+        bdrop_graphs(b);
+        if (tile_y_out) *tile_y_out = found;
+        return VFLB_OK;
+      }
+    }
+  }
+  // time each tile height on zeroed populations; the state is clobbered
+  for (int k = 0; k < 3; ++k)
+    if (k != VFLB_BUF_SNAP) BHIP_TRY(b, hipMemsetAsync(b->buf[k], 0, b->bytes[k], b->stream));
+  vflb_status rc = sync_desc(b);
+  if (rc != VFLB_OK) return rc;
+  hipEvent_t e0, e1;
+  BHIP_TRY(b, hipEventCreate(&e0));
+  BHIP_TRY(b, hipEventCreate(&e1));
+  const int cand[3] = {4, 8, 16};
+  int best = 8;
+  float best_ms = INFINITY;
+  for (int c = 0; c < 3 && rc == VFLB_OK; ++c) {
+    if ((rc = build_tables(b, cand[c])) != VFLB_OK) break;
+    for (int k = 0; k < 3 && rc == VFLB_OK; ++k) rc = launch_batch(b, b->stream, k & 1, 0);
+    if (rc != VFLB_OK) break;
+    (void)hipEventRecord(e0, b->stream);
+    for (int k = 0; k < 10 && rc == VFLB_OK; ++k) rc = launch_batch(b, b->stream, k & 1, 0);
+    (void)hipEventRecord(e1, b->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) rc = bfail(b, VFLB_EDEVICE, "timing failed");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rc == VFLB_OK && ms < best_ms) {
+      best_ms = ms;
+      best = cand[c];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (vflb_sim* v : b->views) {
+    v->inited = false;
+    v->snap_valid = false;
+  }
+  b->tables_ok = false;
+  if (rc != VFLB_OK) return rc;
+  b->tile_y = best;
+  bdrop_graphs(b);
+  if (!path.empty()) {
+    if (FILE* fp = fopen(path.c_str(), "a")) {
+      fprintf(fp, "%s %d\n", key, best);
+      fclose(fp);
+    }
+  }
+  if (tile_y_out) *tile_y_out = best;
+  return VFLB_OK;
+}
+
+void vflb_batch_destroy(vflb_batch* b) {
+  if (!b) return;
+  bdrop_graphs(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (vflb_sim* v : b->views) delete v;
+  delete b;
+}
+
+const char* vflb_batch_last_error(const vflb_batch* b) {
+  if (!b) return g_batch_create_error.c_str();
+  return b->err.c_str();
 }
 
 }  // extern "C"

@@ -28,6 +28,7 @@ PERIODIC, WALLS = 0, 1
  FIELD_CHI_PREV, FIELD_U_PREV) = range(9)
 NBUF = 5
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = range(6)
+RUN_ACTIVE, RUN_CONVERGED, RUN_CAPPED, RUN_UNSTABLE, RUN_SKIPPED = range(5)
 
 
 class VflbError(RuntimeError):
@@ -85,6 +86,32 @@ def lib():
         L.vflb_stream_copy.restype = I
         L.vflb_destroy.argtypes = [P]
         L.vflb_destroy.restype = None
+        L.vflb_batch_create.argtypes = [I, I, ctypes.POINTER(I), I, P, ctypes.POINTER(P)]
+        L.vflb_batch_query_buffers.argtypes = [P, ctypes.POINTER(SZ)]
+        L.vflb_batch_bind_buffers.argtypes = [P, ctypes.POINTER(P)]
+        L.vflb_batch_instance.argtypes = [P, I]
+        L.vflb_batch_instance.restype = P
+        L.vflb_batch_size.argtypes = [P]
+        L.vflb_batch_size.restype = I
+        L.vflb_batch_set_tile.argtypes = [P, I]
+        L.vflb_batch_get_tile.argtypes = [P]
+        L.vflb_batch_get_tile.restype = I
+        L.vflb_batch_set_active.argtypes = [P, I, I]
+        L.vflb_batch_is_active.argtypes = [P, I]
+        L.vflb_batch_is_active.restype = I
+        L.vflb_batch_step.argtypes = [P, I64]
+        L.vflb_batch_reduce.argtypes = [P, ctypes.POINTER(D)]
+        L.vflb_batch_run_until.argtypes = [P, D, I64, ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                           ctypes.POINTER(D), ctypes.POINTER(I)]
+        L.vflb_batch_autotune.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I)]
+        L.vflb_batch_destroy.argtypes = [P]
+        L.vflb_batch_destroy.restype = None
+        L.vflb_batch_last_error.argtypes = [P]
+        L.vflb_batch_last_error.restype = ctypes.c_char_p
+        for name in ("vflb_batch_create", "vflb_batch_query_buffers", "vflb_batch_bind_buffers",
+                     "vflb_batch_set_tile", "vflb_batch_set_active", "vflb_batch_step",
+                     "vflb_batch_reduce", "vflb_batch_run_until", "vflb_batch_autotune"):
+            getattr(L, name).restype = I
         L.vflb_last_error.argtypes = [P]
         L.vflb_last_error.restype = ctypes.c_char_p
         for name in ("vflb_create", "vflb_query_buffers", "vflb_bind_buffers",
@@ -100,6 +127,12 @@ def lib():
 def _check(handle, code):
     if code != OK:
         msg = lib().vflb_last_error(handle)
+        raise VflbError(code, msg.decode() if msg else "")
+
+
+def _bcheck(handle, code):
+    if code != OK:
+        msg = lib().vflb_batch_last_error(handle)
         raise VflbError(code, msg.decode() if msg else "")
 
 
@@ -121,7 +154,7 @@ class Sim:
     """
 
     def __init__(self, lattice, nx, ny, nz=1, storage="f32", device="cuda:0",
-                 stream=None):
+                 stream=None, _handle=None):
         import torch
         self.torch = torch
         self.D = 2 if lattice in (2, "d2q9", "D2Q9") else 3
@@ -133,6 +166,10 @@ class Sim:
         self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        if _handle is not None:  # an instance of a Batch: the batch owns handle and buffers
+            self._h = None
+            self._view = ctypes.c_void_p(_handle)
+            return
         h = ctypes.c_void_p()
         _check(None, lib().vflb_create(self.D, self.nx, self.ny, self.nz, self.storage,
                                        ctypes.c_void_p(self.stream.cuda_stream),
@@ -151,31 +188,35 @@ class Sim:
             lib().vflb_destroy(h)
             self._h = None
 
+    @property
+    def handle(self):
+        return self._h if self._h is not None else self._view
+
     # ---------------------------------------------------------- set-up
     def set_params(self, Re, Wi, beta, U0, L, lam=0.0, tau_h=0.0):
         p = Params(Re, Wi, beta, U0, L, lam, tau_h)
-        _check(self._h, lib().vflb_set_params(self._h, ctypes.byref(p)))
+        _check(self.handle, lib().vflb_set_params(self.handle, ctypes.byref(p)))
 
     def lattice_params(self):
         lp = LatticeParams()
-        _check(self._h, lib().vflb_get_lattice_params(self._h, ctypes.byref(lp)))
+        _check(self.handle, lib().vflb_get_lattice_params(self.handle, ctypes.byref(lp)))
         return dict(nu_s=lp.nu_s, nu_p=lp.nu_p, tau_f=lp.tau_f, tau_h=lp.tau_h,
                     lam=lp.lam, eta_p=lp.eta_p)
 
     def set_force(self, kind, amp=(0.0, 0.0, 0.0), omega=0.0):
         a = (ctypes.c_double * 3)(*(list(amp) + [0.0] * (3 - len(amp))))
-        _check(self._h, lib().vflb_set_force(self._h, int(kind), a, float(omega)))
+        _check(self.handle, lib().vflb_set_force(self.handle, int(kind), a, float(omega)))
 
     def set_boundaries(self, walls):
         w = list(walls) + [0] * (3 - len(walls))
         k = (ctypes.c_int * 3)(*[int(x) for x in w])
-        _check(self._h, lib().vflb_set_boundaries(self._h, k))
+        _check(self.handle, lib().vflb_set_boundaries(self.handle, k))
 
     def set_storage_scale(self, log2_f, log2_h):
-        _check(self._h, lib().vflb_set_storage_scale(self._h, int(log2_f), int(log2_h)))
+        _check(self.handle, lib().vflb_set_storage_scale(self.handle, int(log2_f), int(log2_h)))
 
     def set_tile(self, tile_y):
-        _check(self._h, lib().vflb_set_tile(self._h, int(tile_y)))
+        _check(self.handle, lib().vflb_set_tile(self.handle, int(tile_y)))
 
     def _dev_field(self, a, ncomp):
         """Node-major [N, ncomp] host/torch array -> component-major FP64
@@ -195,7 +236,7 @@ class Sim:
             assert t is None or (t.is_cuda and t.dtype == self.torch.float64 and t.is_contiguous())
         self.torch.cuda.current_stream(self.device).synchronize()
         ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
-        _check(self._h, lib().vflb_init_fields(self._h, ptr(u), ptr(tau), ptr(p)))
+        _check(self.handle, lib().vflb_init_fields(self.handle, ptr(u), ptr(tau), ptr(p)))
         self.stream.synchronize()
 
     def init_fields(self, u=None, tau=None, p=None):
@@ -205,26 +246,26 @@ class Sim:
         self.torch.cuda.current_stream(self.device).synchronize()
         ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
         with self.torch.cuda.stream(self.stream):
-            _check(self._h, lib().vflb_init_fields(self._h, ptr(tu), ptr(tt), ptr(tp)))
+            _check(self.handle, lib().vflb_init_fields(self.handle, ptr(tu), ptr(tt), ptr(tp)))
         self.stream.synchronize()
         self._keep = (tu, tt, tp)
 
     # ------------------------------------------------------------ run
     def step(self, n=1):
-        _check(self._h, lib().vflb_step(self._h, int(n)))
+        _check(self.handle, lib().vflb_step(self.handle, int(n)))
 
     @property
     def t(self):
-        return lib().vflb_time(self._h)
+        return lib().vflb_time(self.handle)
 
     def synchronize(self):
         self.stream.synchronize()
 
     def reduce(self, allow_unstable=False):
         out = (ctypes.c_double * 14)()
-        rc = lib().vflb_reduce(self._h, out)
+        rc = lib().vflb_reduce(self.handle, out)
         if rc != OK and not (allow_unstable and rc == EUNSTABLE):
-            _check(self._h, rc)
+            _check(self.handle, rc)
         o = list(out)
         return dict(R=o[0], M=o[1], P=o[2:2 + self.D], KE=o[5], PE=o[6],
                     nonfinite=o[7], A_sum=o[8:8 + self.NC], status=rc)
@@ -236,7 +277,7 @@ class Sim:
                  FIELD_CHI_PREV: self.NC, FIELD_U_PREV: self.D}[field]
         out = self.torch.empty(ncomp * self.N, dtype=self.torch.float64,
                                device=self.device)
-        _check(self._h, lib().vflb_read(self._h, int(field),
+        _check(self.handle, lib().vflb_read(self.handle, int(field),
                                         ctypes.c_void_p(out.data_ptr()), out.numel()))
         return out.view(ncomp, self.N)
 
@@ -262,11 +303,98 @@ class Sim:
     # ----------------------------------------------------- checkpoint
     def save(self):
         n = ctypes.c_size_t()
-        _check(self._h, lib().vflb_state_size(self._h, ctypes.byref(n)))
+        _check(self.handle, lib().vflb_state_size(self.handle, ctypes.byref(n)))
         blob = self.torch.empty(n.value, dtype=self.torch.uint8, device=self.device)
-        _check(self._h, lib().vflb_save(self._h, ctypes.c_void_p(blob.data_ptr()), n.value))
+        _check(self.handle, lib().vflb_save(self.handle, ctypes.c_void_p(blob.data_ptr()), n.value))
         return blob
 
     def load(self, blob):
-        _check(self._h, lib().vflb_load(self._h, ctypes.c_void_p(blob.data_ptr()),
+        _check(self.handle, lib().vflb_load(self.handle, ctypes.c_void_p(blob.data_ptr()),
                                         blob.numel()))
+
+
+class Batch:
+    """An ensemble of D2Q9 lattices stepped together:
+    ``Batch([(nx, ny), ...], storage)``.  ``batch[i]`` is a :class:`Sim`
+    handle of instance i for set-up, initialisation and read-back;
+    stepping and reductions go through the batch."""
+
+    def __init__(self, dims, storage="f32", device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.n = len(dims)
+        self.dims = [(int(d[0]), int(d[1])) for d in dims]
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        flat = (ctypes.c_int * (3 * self.n))(*[v for d in self.dims for v in (d[0], d[1], 1)])
+        h = ctypes.c_void_p()
+        _bcheck(None, lib().vflb_batch_create(D2Q9, self.n, flat, self.storage,
+                                              ctypes.c_void_p(self.stream.cuda_stream),
+                                              ctypes.byref(h)))
+        self._h = h
+        sizes = (ctypes.c_size_t * NBUF)()
+        _bcheck(self._h, lib().vflb_batch_query_buffers(self._h, sizes))
+        self.buffers = [torch.empty(int(b), dtype=torch.uint8, device=self.device)
+                        for b in sizes]
+        ptrs = (ctypes.c_void_p * NBUF)(*[b.data_ptr() for b in self.buffers])
+        _bcheck(self._h, lib().vflb_batch_bind_buffers(self._h, ptrs))
+        self.instances = []
+        for i, (nx, ny) in enumerate(self.dims):
+            hv = lib().vflb_batch_instance(self._h, i)
+            view = Sim(2, nx, ny, 1, self.storage, device, self.stream, _handle=hv)
+            view._batch = self  # the batch owns the handle: keep it alive
+            self.instances.append(view)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().vflb_batch_destroy(h)
+            self._h = None
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, i):
+        return self.instances[i]
+
+    def set_tile(self, tile_y):
+        _bcheck(self._h, lib().vflb_batch_set_tile(self._h, int(tile_y)))
+
+    @property
+    def tile(self):
+        return lib().vflb_batch_get_tile(self._h)
+
+    def set_active(self, i, active):
+        _bcheck(self._h, lib().vflb_batch_set_active(self._h, int(i), 1 if active else 0))
+
+    def is_active(self, i):
+        return bool(lib().vflb_batch_is_active(self._h, int(i)))
+
+    def step(self, n=1):
+        _bcheck(self._h, lib().vflb_batch_step(self._h, int(n)))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def reduce(self):
+        """[n, 14] array, one vflb_reduce row per instance."""
+        out = (ctypes.c_double * (14 * self.n))()
+        _bcheck(self._h, lib().vflb_batch_reduce(self._h, out))
+        return np.array(out[:], dtype=np.float64).reshape(self.n, 14)
+
+    def run_until(self, tol, check_every, max_steps):
+        ms = (ctypes.c_int64 * self.n)(*[int(m) for m in np.broadcast_to(max_steps, (self.n,))])
+        steps = (ctypes.c_int64 * self.n)()
+        res = (ctypes.c_double * self.n)()
+        st = (ctypes.c_int * self.n)()
+        _bcheck(self._h, lib().vflb_batch_run_until(self._h, float(tol), int(check_every), ms,
+                                                     steps, res, st))
+        return (np.array(steps[:], dtype=np.int64), np.array(res[:], dtype=np.float64),
+                np.array(st[:], dtype=np.int32))
+
+    def autotune(self, cache_path=None):
+        ty = ctypes.c_int()
+        path = cache_path.encode() if cache_path else None
+        _bcheck(self._h, lib().vflb_batch_autotune(self._h, path, ctypes.byref(ty)))
+        return ty.value

@@ -58,3 +58,18 @@ def test_python_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(vflb, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError, match="missing"):
         vflb.lib()
+
+
+def test_batch_create_validates_arguments_on_host(lib):
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int * 6)(64, 64, 1, 32, 16, 1)
+    lib.vflb_batch_last_error.restype = ctypes.c_char_p
+    assert lib.vflb_batch_create(3, 2, dims, 1, None, ctypes.byref(h)) == 1   # D3Q19
+    assert b"D2Q9" in lib.vflb_batch_last_error(None)
+    assert lib.vflb_batch_create(2, 0, dims, 1, None, ctypes.byref(h)) == 1   # empty
+    assert lib.vflb_batch_create(2, 2, None, 1, None, ctypes.byref(h)) == 1   # no dims
+    assert lib.vflb_batch_create(2, 2, dims, 7, None, ctypes.byref(h)) == 1   # storage
+    bad = (ctypes.c_int * 6)(64, 64, 1, 0, 16, 1)
+    assert lib.vflb_batch_create(2, 2, bad, 1, None, ctypes.byref(h)) == 1    # size
+    assert b"instance 1" in lib.vflb_batch_last_error(None)
+    assert not h.value
