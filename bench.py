@@ -117,6 +117,75 @@ def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0):
     return dict(step_ms=ms, GLUPS=n ** 3 / ms / 1e6, KE=r["KE"], nonfinite=r["nonfinite"])
 
 
+def ensemble_specs(n):
+    """The four-roll ensemble: per instance a side in {64..512}, Wi and beta
+    from the seeded draws, Re = 1, U0 = 0.01, L = side / (2 pi), the force
+    amplitude 2 nu_s U0 k^2 with k = 2 pi / side."""
+    import math
+    from paper_2506_13072_amd.workloads import ensemble_draws
+    return [dict(side=d["side"], Re=d["Re"], Wi=d["Wi"], beta=d["beta"], U0=d["U0"],
+                 L=d["side"] / (2 * math.pi)) for d in ensemble_draws(n)]
+
+
+def setup_instance(V, sim, sp):
+    import math
+    sim.set_params(sp["Re"], sp["Wi"], sp["beta"], sp["U0"], sp["L"])
+    lp = sim.lattice_params()
+    k2 = (2 * math.pi / sp["side"]) ** 2
+    a = 2 * lp["nu_s"] * sp["U0"] * k2
+    sim.set_force(V.FORCE_FOUR_ROLL, (a, -a, 0.0))
+
+
+def run_gpu_ensemble(n, steps, warmup, storage="f32", compare_unbatched=True):
+    """n four-roll instances as one batch: MLUPS of the batched step, and of
+    the same instances stepped one lattice at a time (same kernels)."""
+    import tempfile
+    import torch
+    from paper_2506_13072_amd import vflb as V
+    specs = ensemble_specs(n)
+    b = V.Batch([(sp["side"], sp["side"]) for sp in specs], storage)
+    for i, sp in enumerate(specs):
+        setup_instance(V, b[i], sp)
+    cache = os.path.join(tempfile.gettempdir(), "vflb_autotune.txt")
+    tile = b.autotune(cache)
+    for i in range(n):
+        b[i].init_fields()
+    nodes = sum(sp["side"] ** 2 for sp in specs)
+    b.step(warmup)
+    b.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    red = b.reduce()
+    out = dict(step_ms=ms, MLUPS=nodes / ms / 1e3, nodes=nodes, tile=tile,
+               nonfinite=float(red[:, 7].sum()))
+    del b
+    if compare_unbatched:
+        torch.cuda.empty_cache()
+        st = torch.cuda.Stream()
+        sims = []
+        for sp in specs:
+            g = V.Sim(2, sp["side"], sp["side"], 1, storage, stream=st)
+            setup_instance(V, g, sp)
+            g.init_fields()
+            sims.append(g)
+        for g in sims:
+            g.step(warmup)
+        st.synchronize()
+        e0.record(st)
+        for g in sims:
+            g.step(steps)
+        e1.record(st)
+        e1.synchronize()
+        ms1 = e0.elapsed_time(e1) / steps
+        out.update(unbatched_step_ms=ms1, unbatched_MLUPS=nodes / ms1 / 1e3)
+    return out
+
+
 def measured_traffic(record, kernel):
     """HBM bytes per launch of the step kernel (FETCH_SIZE + WRITE_SIZE,
     scaled against the streaming-copy kernel) from a committed rocprofv3
@@ -198,9 +267,11 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile height: D2Q9 4, 8, 16; D3Q19 4, 8")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy kernel (counter calibration)")
-    ap.add_argument("--workload", default="channel", choices=["channel", "tgv"],
+    ap.add_argument("--workload", default="channel", choices=["channel", "tgv", "ensemble"],
                     help="channel: the 8192x1024 D2Q9 headline; tgv: 512^3 D3Q19 "
-                         "Taylor-Green vortex (reported, not the headline)")
+                         "Taylor-Green vortex; ensemble: 256 four-roll lattices of "
+                         "sides 64..512 as one batch (both reported, not the headline)")
+    ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--tgv-n", type=int, default=512)
     args = ap.parse_args()
     if args.copy_probe:
@@ -210,6 +281,27 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "ensemble":
+        r = run_gpu_ensemble(args.instances, args.steps, args.warmup, args.storage)
+        bpl = bytes_per_lup(2, args.storage)
+        ach = bpl * r["nodes"] / (r["step_ms"] / 1e3) / 1e9
+        print(json.dumps({"metric": "MLUPS (batched fused stream-collide, D2Q9 ensemble)",
+                          "value": round(r["MLUPS"], 1), "unit": "MLUPS", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": round(r["step_ms"], 4), "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
+                          "config": {"workload": f"four-roll ensemble, {args.instances} D2Q9 "
+                                                 "lattices, sides 64..512, seeded Wi and beta",
+                                     "storage": args.storage, "nodes": r["nodes"],
+                                     "tile_y": r["tile"]},
+                          "roofline": {"bound": "hbm", "achieved": round(ach, 1),
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                                       "bytes_per_lup": bpl},
+                          "unbatched_MLUPS": round(r.get("unbatched_MLUPS", 0.0), 1),
+                          "nonfinite": r["nonfinite"]}), flush=True)
+        return
     if args.workload == "tgv":
         r = run_gpu_tgv(args.tgv_n, args.steps, args.warmup, args.storage, args.tile)
         bpl = bytes_per_lup(3, args.storage)
