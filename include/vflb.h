@@ -46,6 +46,7 @@ extern "C" {
 
 typedef struct vflb_sim vflb_sim;
 typedef struct vflb_batch vflb_batch;
+typedef struct vflb_mlp vflb_mlp;
 
 typedef enum {
   VFLB_OK = 0,
@@ -336,6 +337,89 @@ void vflb_batch_destroy(vflb_batch *batch);
 /* Message of the last failed call on batch (or of the last failed
  * vflb_batch_create when batch is NULL); never NULL. */
 const char *vflb_batch_last_error(const vflb_batch *batch);
+
+/* ---------------------------------------------------------- warm start
+ * A learned initial guess for steady states: a Fourier-feature network
+ * maps (x/nx, y/ny, ln Wi, beta, ln Re) to the normalised steady fields
+ * (u/U, v/U, txx/S, txy/S, tyy/S); vflb_init_from_mlp evaluates it at every
+ * node and starts the lattice from the equilibrium of those fields, after
+ * which the method itself runs to the steady state.  The network:
+ * phi(x) = [sin(2 pi B x), cos(2 pi B x)] with n_freq fixed Gaussian
+ * frequencies B (standard deviation sigma), `hidden` tanh layers of
+ * `width`, a linear output layer.  Products run on the matrix cores in BF16
+ * with FP32 accumulation; master weights and Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8) are FP32; the loss is the mean squared error.  Not part of the
+ * paper: a way to reach the steady states faster.
+ */
+typedef struct {
+  int in_dim;     /* inputs per point, 1..8 (5 for the warm start)          */
+  int n_freq;     /* Fourier frequencies, multiple of 32 in [32, 256]        */
+  int width;      /* hidden width, multiple of 64 in [64, 1024]              */
+  int hidden;     /* hidden layers, 1..16                                    */
+  int out_dim;    /* outputs per point, 1..64 (5 for the warm start)         */
+  int max_batch;  /* rows per train / gradient call, multiple of 64          */
+  double sigma;   /* standard deviation of the frequencies                   */
+} vflb_mlp_cfg;
+
+enum {
+  VFLB_MLP_BUF_PARAMS = 0, /* frequencies, weights, Adam moments, gradients */
+  VFLB_MLP_BUF_WORK = 1,   /* activations of max_batch rows, partial sums    */
+  VFLB_MLP_NBUF = 2
+};
+
+/* Create a network (EINVAL for a configuration outside the ranges above);
+ * work is enqueued on hip_stream. */
+vflb_status vflb_mlp_create(const vflb_mlp_cfg *cfg, void *hip_stream,
+                            vflb_mlp **out);
+vflb_status vflb_mlp_query_buffers(const vflb_mlp *mlp,
+                                   size_t bytes[VFLB_MLP_NBUF]);
+/* Caller-owned device buffers (256-byte aligned); parameters must be set
+ * (vflb_mlp_init or vflb_mlp_set_params) afterwards. */
+vflb_status vflb_mlp_bind_buffers(vflb_mlp *mlp,
+                                  void *const dev_ptrs[VFLB_MLP_NBUF]);
+
+/* Number of parameters in the flat host order used below: the
+ * frequencies [n_freq][in_dim], then per layer W [out][in] and b [out]. */
+size_t vflb_mlp_param_count(const vflb_mlp *mlp);
+
+/* Seeded initial parameters (SplitMix64): frequencies N(0, sigma^2),
+ * Glorot-uniform weights, zero biases; resets Adam. */
+vflb_status vflb_mlp_init(vflb_mlp *mlp, uint64_t seed);
+
+/* Host copies of the parameters (n = vflb_mlp_param_count); set resets
+ * Adam.  Both synchronise. */
+vflb_status vflb_mlp_set_params(vflb_mlp *mlp, const float *host, size_t n);
+vflb_status vflb_mlp_get_params(vflb_mlp *mlp, float *host, size_t n);
+
+/* Network outputs y [n][out_dim] for inputs x [n][in_dim] (FP32 device
+ * arrays; any n, processed max_batch rows at a time). */
+vflb_status vflb_mlp_forward(vflb_mlp *mlp, const float *dev_x, float *dev_y,
+                             int64_t n);
+
+/* Gradient of the loss on n <= max_batch rows (targets t [n][out_dim]),
+ * in the flat parameter order (zeros for the frequencies, which are not
+ * trained), and the loss; no update.  Synchronises. */
+vflb_status vflb_mlp_grad(vflb_mlp *mlp, const float *dev_x, const float *dev_t,
+                          int64_t n, float *host_grad, double *loss);
+
+/* One Adam step on n <= max_batch rows with learning rate lr; *loss_out
+ * (may be NULL, then nothing synchronises) receives the loss before the
+ * step. */
+vflb_status vflb_mlp_train_step(vflb_mlp *mlp, const float *dev_x,
+                                const float *dev_t, int64_t n, float lr,
+                                double *loss_out);
+
+/* Initialise a D2Q9 simulation from the network: inputs (x/nx, y/ny,
+ * extra[0], extra[1], extra[2]) at every node, u = u_scale (y0, y1),
+ * tau = tau_scale (y2, y3, y4), pressure 0, then as vflb_init_fields.  The
+ * simulation's residual snapshot buffer serves as scratch; both handles
+ * must use the same stream. */
+vflb_status vflb_init_from_mlp(vflb_sim *sim, vflb_mlp *mlp,
+                               const double extra[3], double u_scale,
+                               double tau_scale);
+
+void vflb_mlp_destroy(vflb_mlp *mlp);
+const char *vflb_mlp_last_error(const vflb_mlp *mlp);
 
 #ifdef __cplusplus
 }

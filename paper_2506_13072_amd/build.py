@@ -9,7 +9,7 @@ import hashlib
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libvflb.so")
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, "vflb.hip")]
+SOURCES = [os.path.join(CSRC, "vflb.hip"), os.path.join(CSRC, "mlp.hip")]
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vflb.h")
 
 HIPCC_FLAGS = [

@@ -1,0 +1,23 @@
+// internal.h -- calls between the translation units of libvflb (not part of
+// the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/vflb.h"
+
+namespace vflb {
+namespace internal {
+
+// Shape, stream and the residual-snapshot buffer of a simulation, which a
+// caller may use as scratch before (re)initialising it: FP32 fields of up
+// to `bytes` bytes.  Needs bound buffers and parameters.
+vflb_status sim_scratch(vflb_sim* s, int* D, int* nx, int* ny, hipStream_t* stream,
+                        void** scratch, size_t* bytes);
+
+// vflb_init_fields from FP32 component-major device fields u [D][N] and
+// tau [NC][N] (pressure 0).
+vflb_status sim_init_f32(vflb_sim* s, const float* u, const float* tau);
+
+}  // namespace internal
+}  // namespace vflb

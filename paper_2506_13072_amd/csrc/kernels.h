@@ -252,10 +252,10 @@ __global__ void __launch_bounds__(256) moments_kernel(
 // Equilibrium-only state: f = f^eq(p, u), h = h^eq(A, u) (shifted), with
 // A = I + lambda tau / eta_p; each value is written where the pull of the
 // first step reads it, so that the first step sees exactly this state.
-template <int D, class S>
+template <int D, class S, class T>
 __global__ void __launch_bounds__(256) init_kernel(
     S* pbuf, typename StoreT<S>::R* aux, Geo g,
-    const double* u_in, const double* tau_in, const double* p_in,
+    const T* u_in, const T* tau_in, const T* p_in,
     double lam_over_eta, typename StoreT<S>::R sf, typename StoreT<S>::R sh) {
   using St = StoreT<S>;
   using R = typename St::R;

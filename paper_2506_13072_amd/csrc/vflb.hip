@@ -15,6 +15,7 @@
 #include "kernels.h"
 #include "step2d.h"
 #include "step3d.h"
+#include "internal.h"
 
 using namespace vflb;
 
@@ -211,9 +212,8 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
   return VFLB_OK;
 }
 
-template <int D, class S>
-vflb_status launch_init(vflb_sim* s, const double* u, const double* tau,
-                        const double* p) {
+template <int D, class S, class T>
+vflb_status launch_init(vflb_sim* s, const T* u, const T* tau, const T* p) {
   using R = typename StoreT<S>::R;
   const double loe = s->lp.eta_p > 0.0 ? s->lp.lambda / s->lp.eta_p : 0.0;
   R sf = (R)1, sh = (R)1;
@@ -221,7 +221,7 @@ vflb_status launch_init(vflb_sim* s, const double* u, const double* tau,
     sf = (R)std::ldexp(1.0, s->log2_sf);
     sh = (R)std::ldexp(1.0, s->log2_sh);
   }
-  hipLaunchKernelGGL((init_kernel<D, S>), dim3(grid1d(s, 256)), dim3(256), 0,
+  hipLaunchKernelGGL((init_kernel<D, S, T>), dim3(grid1d(s, 256)), dim3(256), 0,
                      s->stream, static_cast<S*>(s->buf[VFLB_BUF_POP0]),
                      static_cast<R*>(s->buf[VFLB_BUF_AUX]), geo_of(s), u, tau, p,
                      loe, sf, sh);
@@ -291,8 +291,9 @@ template <int D, class S> struct StepOp {
   }
 };
 template <int D, class S> struct InitOp {
-  static vflb_status run(vflb_sim* s, const double* u, const double* tau, const double* p) {
-    return launch_init<D, S>(s, u, tau, p);
+  template <class T>
+  static vflb_status run(vflb_sim* s, const T* u, const T* tau, const T* p) {
+    return launch_init<D, S, T>(s, u, tau, p);
   }
 };
 template <int D, class S> struct MomOp {
@@ -1309,3 +1310,35 @@ const char* vflb_batch_last_error(const vflb_batch* b) {
 }
 
 }  // extern "C"
+
+// --------------------------------------------- calls from other units
+namespace vflb {
+namespace internal {
+
+vflb_status sim_scratch(vflb_sim* s, int* D, int* nx, int* ny, hipStream_t* stream,
+                        void** scratch, size_t* bytes) {
+  vflb_status rc = need_ready(s);
+  if (rc != VFLB_OK) return rc;
+  *D = s->D;
+  *nx = s->nx;
+  *ny = s->ny;
+  *stream = s->stream;
+  *scratch = s->buf[VFLB_BUF_SNAP];
+  *bytes = s->bytes[VFLB_BUF_SNAP];
+  return VFLB_OK;
+}
+
+vflb_status sim_init_f32(vflb_sim* s, const float* u, const float* tau) {
+  vflb_status rc = need_ready(s);
+  if (rc != VFLB_OK) return rc;
+  s->cur = 0;
+  rc = dispatch<InitOp>(s, u, tau, (const float*)nullptr);
+  if (rc != VFLB_OK) return rc;
+  s->t = 0;
+  s->inited = true;
+  s->snap_valid = false;  // the snapshot buffer held the fields
+  return VFLB_OK;
+}
+
+}  // namespace internal
+}  // namespace vflb

@@ -44,6 +44,12 @@ class Params(ctypes.Structure):
                 ("tau_h", ctypes.c_double)]
 
 
+class MlpCfg(ctypes.Structure):
+    _fields_ = [("in_dim", ctypes.c_int), ("n_freq", ctypes.c_int), ("width", ctypes.c_int),
+                ("hidden", ctypes.c_int), ("out_dim", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("sigma", ctypes.c_double)]
+
+
 class LatticeParams(ctypes.Structure):
     _fields_ = [("nu_s", ctypes.c_double), ("nu_p", ctypes.c_double),
                 ("tau_f", ctypes.c_double), ("tau_h", ctypes.c_double),
@@ -104,6 +110,27 @@ def lib():
         L.vflb_batch_run_until.argtypes = [P, D, I64, ctypes.POINTER(I64), ctypes.POINTER(I64),
                                            ctypes.POINTER(D), ctypes.POINTER(I)]
         L.vflb_batch_autotune.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I)]
+        L.vflb_mlp_create.argtypes = [ctypes.POINTER(MlpCfg), P, ctypes.POINTER(P)]
+        L.vflb_mlp_query_buffers.argtypes = [P, ctypes.POINTER(SZ)]
+        L.vflb_mlp_bind_buffers.argtypes = [P, ctypes.POINTER(P)]
+        L.vflb_mlp_param_count.argtypes = [P]
+        L.vflb_mlp_param_count.restype = SZ
+        L.vflb_mlp_init.argtypes = [P, ctypes.c_uint64]
+        L.vflb_mlp_set_params.argtypes = [P, P, SZ]
+        L.vflb_mlp_get_params.argtypes = [P, P, SZ]
+        L.vflb_mlp_forward.argtypes = [P, P, P, I64]
+        L.vflb_mlp_grad.argtypes = [P, P, P, I64, P, ctypes.POINTER(D)]
+        L.vflb_mlp_train_step.argtypes = [P, P, P, I64, ctypes.c_float, ctypes.POINTER(D)]
+        L.vflb_init_from_mlp.argtypes = [P, P, ctypes.POINTER(D), D, D]
+        L.vflb_mlp_destroy.argtypes = [P]
+        L.vflb_mlp_destroy.restype = None
+        L.vflb_mlp_last_error.argtypes = [P]
+        L.vflb_mlp_last_error.restype = ctypes.c_char_p
+        for name in ("vflb_mlp_create", "vflb_mlp_query_buffers", "vflb_mlp_bind_buffers",
+                     "vflb_mlp_init", "vflb_mlp_set_params", "vflb_mlp_get_params",
+                     "vflb_mlp_forward", "vflb_mlp_grad", "vflb_mlp_train_step",
+                     "vflb_init_from_mlp"):
+            getattr(L, name).restype = I
         L.vflb_batch_destroy.argtypes = [P]
         L.vflb_batch_destroy.restype = None
         L.vflb_batch_last_error.argtypes = [P]
@@ -133,6 +160,12 @@ def _check(handle, code):
 def _bcheck(handle, code):
     if code != OK:
         msg = lib().vflb_batch_last_error(handle)
+        raise VflbError(code, msg.decode() if msg else "")
+
+
+def _mcheck(handle, code):
+    if code != OK:
+        msg = lib().vflb_mlp_last_error(handle)
         raise VflbError(code, msg.decode() if msg else "")
 
 
@@ -308,6 +341,13 @@ class Sim:
         _check(self.handle, lib().vflb_save(self.handle, ctypes.c_void_p(blob.data_ptr()), n.value))
         return blob
 
+    def init_from_mlp(self, mlp, extra, u_scale, tau_scale):
+        """Start from the network's prediction at every node (inputs
+        (x/nx, y/ny, *extra)); the network must use this simulation's stream."""
+        e = (ctypes.c_double * 3)(*[float(v) for v in extra])
+        _mcheck(mlp._h, lib().vflb_init_from_mlp(self.handle, mlp._h, e, float(u_scale),
+                                                  float(tau_scale)))
+
     def load(self, blob):
         _check(self.handle, lib().vflb_load(self.handle, ctypes.c_void_p(blob.data_ptr()),
                                         blob.numel()))
@@ -398,3 +438,85 @@ class Batch:
         path = cache_path.encode() if cache_path else None
         _bcheck(self._h, lib().vflb_batch_autotune(self._h, path, ctypes.byref(ty)))
         return ty.value
+
+
+class Mlp:
+    """The warm-start network: ``Mlp(in_dim=5, n_freq=128, width=256,
+    hidden=3, out_dim=5, max_batch=16384, sigma=4.0, stream=...)``."""
+
+    def __init__(self, in_dim=5, n_freq=128, width=256, hidden=3, out_dim=5, max_batch=16384,
+                 sigma=4.0, device="cuda:0", stream=None, seed=None):
+        import torch
+        self.torch = torch
+        self.cfg = dict(in_dim=in_dim, n_freq=n_freq, width=width, hidden=hidden,
+                        out_dim=out_dim, max_batch=max_batch, sigma=sigma)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        c = MlpCfg(in_dim, n_freq, width, hidden, out_dim, max_batch, sigma)
+        h = ctypes.c_void_p()
+        _mcheck(None, lib().vflb_mlp_create(ctypes.byref(c), ctypes.c_void_p(self.stream.cuda_stream),
+                                            ctypes.byref(h)))
+        self._h = h
+        sizes = (ctypes.c_size_t * 2)()
+        _mcheck(self._h, lib().vflb_mlp_query_buffers(self._h, sizes))
+        self.buffers = [torch.empty(int(b), dtype=torch.uint8, device=self.device) for b in sizes]
+        ptrs = (ctypes.c_void_p * 2)(*[b.data_ptr() for b in self.buffers])
+        _mcheck(self._h, lib().vflb_mlp_bind_buffers(self._h, ptrs))
+        self.nparams = lib().vflb_mlp_param_count(self._h)
+        if seed is not None:
+            self.init(seed)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().vflb_mlp_destroy(h)
+            self._h = None
+
+    def init(self, seed):
+        _mcheck(self._h, lib().vflb_mlp_init(self._h, int(seed)))
+
+    def get_params(self):
+        a = np.empty(self.nparams, dtype=np.float32)
+        _mcheck(self._h, lib().vflb_mlp_get_params(self._h, a.ctypes.data_as(ctypes.c_void_p),
+                                                   self.nparams))
+        return a
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.nparams
+        _mcheck(self._h, lib().vflb_mlp_set_params(self._h, a.ctypes.data_as(ctypes.c_void_p),
+                                                   self.nparams))
+
+    def _dev(self, a, width):
+        t = self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device)
+        return t.reshape(-1, width).contiguous()
+
+    def forward(self, x):
+        """Outputs [n, out_dim] (device tensor) for inputs x [n, in_dim]."""
+        tx = self._dev(x, self.cfg["in_dim"])
+        y = self.torch.empty(tx.shape[0], self.cfg["out_dim"], dtype=self.torch.float32,
+                             device=self.device)
+        self.torch.cuda.current_stream(self.device).synchronize()
+        _mcheck(self._h, lib().vflb_mlp_forward(self._h, ctypes.c_void_p(tx.data_ptr()),
+                                                ctypes.c_void_p(y.data_ptr()), tx.shape[0]))
+        self.stream.synchronize()
+        return y
+
+    def grad(self, x, t):
+        tx, tt = self._dev(x, self.cfg["in_dim"]), self._dev(t, self.cfg["out_dim"])
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = ctypes.c_double()
+        self.torch.cuda.current_stream(self.device).synchronize()
+        _mcheck(self._h, lib().vflb_mlp_grad(self._h, ctypes.c_void_p(tx.data_ptr()),
+                                             ctypes.c_void_p(tt.data_ptr()), tx.shape[0],
+                                             g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x_dev, t_dev, lr, want_loss=True):
+        """One Adam step on device tensors x [n, in_dim], t [n, out_dim]."""
+        loss = ctypes.c_double()
+        _mcheck(self._h, lib().vflb_mlp_train_step(self._h, ctypes.c_void_p(x_dev.data_ptr()),
+                                                   ctypes.c_void_p(t_dev.data_ptr()),
+                                                   x_dev.shape[0], float(lr),
+                                                   ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
