@@ -231,6 +231,21 @@ vflb_status vflb_set_tile(vflb_sim *sim, int tile_y);
 vflb_status vflb_stream_copy(const void *src, void *dst, size_t nbytes,
                              void *hip_stream);
 
+/* Settling towards prescribed fields (D2Q9): nsteps steps in which every
+ * collision takes the FP32 device fields u [2][N] and tau [3][N], stored
+ * back to back at dev_targets, in place of the state's own moment u (flags
+ * VFLB_SETTLE_U) and/or A (VFLB_SETTLE_A); the pressure follows from the
+ * populations.  After an equilibrium-only initialisation this builds the
+ * non-equilibrium parts of f and h and a consistent pressure before the
+ * real run (with both flags: the iterative initialisation of Mei, Luo,
+ * Lallemand and d'Humieres, 2006, which needs a divergence-free u; with A
+ * alone the flow adjusts to the prescribed stress).  The time level
+ * advances by nsteps.  On a batch instance only right after its
+ * initialisation.  EINVAL for other flags or a D3Q19 lattice. */
+enum { VFLB_SETTLE_U = 1, VFLB_SETTLE_A = 2 };
+vflb_status vflb_settle(vflb_sim *sim, const float *dev_targets,
+                        int64_t nsteps, int flags);
+
 /* Release the handle (not the caller's buffers).  Ignored for the
  * instances of a batch, which the batch owns. */
 void vflb_destroy(vflb_sim *sim);
@@ -411,12 +426,15 @@ vflb_status vflb_mlp_train_step(vflb_mlp *mlp, const float *dev_x,
 
 /* Initialise a D2Q9 simulation from the network: inputs (x/nx, y/ny,
  * extra[0], extra[1], extra[2]) at every node, u = u_scale (y0, y1),
- * tau = tau_scale (y2, y3, y4), pressure 0, then as vflb_init_fields.  The
- * simulation's residual snapshot buffer serves as scratch; both handles
- * must use the same stream. */
+ * tau = tau_scale (y2, y3, y4), pressure 0, then as vflb_init_fields,
+ * followed by settle_steps settling steps towards those fields with
+ * settle_flags (as vflb_settle; ignored when settle_steps is 0).  The
+ * simulation's residual snapshot buffer serves as scratch; both handles must
+ * use the same stream. */
 vflb_status vflb_init_from_mlp(vflb_sim *sim, vflb_mlp *mlp,
                                const double extra[3], double u_scale,
-                               double tau_scale);
+                               double tau_scale, int64_t settle_steps,
+                               int settle_flags);
 
 void vflb_mlp_destroy(vflb_mlp *mlp);
 const char *vflb_mlp_last_error(const vflb_mlp *mlp);

@@ -19,5 +19,11 @@ vflb_status sim_scratch(vflb_sim* s, int* D, int* nx, int* ny, hipStream_t* stre
 // tau [NC][N] (pressure 0).
 vflb_status sim_init_f32(vflb_sim* s, const float* u, const float* tau);
 
+// Settling: nsteps steps whose collisions use the prescribed FP32 fields
+// targets = u [2][N] followed by tau [3][N] in place of the moment u
+// (flags bit 0) and the moment A (bit 1) (D2Q9); the time level advances
+// by nsteps.
+vflb_status sim_settle_f32(vflb_sim* s, const float* targets, int64_t nsteps, int flags);
+
 }  // namespace internal
 }  // namespace vflb

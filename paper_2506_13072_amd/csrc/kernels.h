@@ -42,6 +42,12 @@ template <class S> struct StepArgs {
   ForceArgs<R> F;
   R sf, inv_sf, sh, inv_sh;  // storage scales (1 unless FP16)
   int first;                 // t == 0: no previous source term
+  // Settling (D2Q9 only; nullptr otherwise): FP32 fields u [2][N] and tau
+  // [3][N] that replace the moment u (clamp_flags bit 0) and the moment A
+  // (bit 1) of every node in the collision, so that the rest of the state
+  // develops consistently with prescribed fields before the run starts.
+  const float* clamp;
+  int clamp_flags;
 };
 
 // Batched ensembles: one entry of the flattened tile table (a 64 x TY tile

@@ -505,10 +505,11 @@ vflb_status vflb_mlp_train_step(vflb_mlp* m, const float* dev_x, const float* de
 }
 
 vflb_status vflb_init_from_mlp(vflb_sim* sim, vflb_mlp* m, const double extra[3], double u_scale,
-                               double tau_scale) {
+                               double tau_scale, int64_t settle_steps, int settle_flags) {
   vflb_status rc = need_mlp(m);
   if (rc != VFLB_OK) return rc;
   if (!sim || !extra) return mfail(m, VFLB_EINVAL, "NULL argument");
+  if (settle_steps < 0) return mfail(m, VFLB_EINVAL, "settle_steps < 0");
   if (m->cfg.in_dim != 5 || m->cfg.out_dim != 5)
     return mfail(m, VFLB_EINVAL, "the network must map 5 inputs to 5 outputs");
   int D = 0, nx = 0, ny = 0;
@@ -537,6 +538,9 @@ vflb_status vflb_init_from_mlp(vflb_sim* sim, vflb_mlp* m, const double extra[3]
     MHIP_TRY(m, hipGetLastError());
   }
   if ((rc = vflb::internal::sim_init_f32(sim, u, tau)) != VFLB_OK)
+    return mfail(m, rc, "simulation: %s", vflb_last_error(sim));
+  if (settle_steps > 0 &&
+      (rc = vflb::internal::sim_settle_f32(sim, u, settle_steps, settle_flags)) != VFLB_OK)
     return mfail(m, rc, "simulation: %s", vflb_last_error(sim));
   return VFLB_OK;
 }

@@ -138,6 +138,10 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
   if (valid) {
     force_at<R>(a.F, wx, wy, g.nx, g.ny, F);
     velocity2(f, F, u);
+    if (a.clamp && (a.clamp_flags & 1)) {
+      u[0] = (R)a.clamp[(size_t)wy * g.nx + wx];
+      u[1] = (R)a.clamp[N + (size_t)wy * g.nx + wx];
+    }
     const int slot = (ty + 1) * SX + tx + 1;
     su[0][slot] = u[0];
     su[1][slot] = u[1];
@@ -146,6 +150,10 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
     R Fh[3], uh[3];
     force_at<R>(a.F, hx, hy, g.nx, g.ny, Fh);
     velocity2(fh, Fh, uh);
+    if (a.clamp && (a.clamp_flags & 1)) {
+      uh[0] = (R)a.clamp[(size_t)hy * g.nx + hx];
+      uh[1] = (R)a.clamp[N + (size_t)hy * g.nx + hx];
+    }
     su[0][hslot] = uh[0];
     su[1][hslot] = uh[1];
   }
@@ -159,6 +167,11 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
 #pragma unroll
       for (int i = 0; i < Q; ++i) s += h[c][i];
       e[c] = s;
+    }
+    if (a.clamp && (a.clamp_flags & 2)) {  // A - I = tau lambda / eta_p
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        e[c] = a.P.eta_over_lam > 0 ? (R)a.clamp[(2 + c) * N + n] / a.P.eta_over_lam : (R)0;
     }
     collide_f<2, R>(f, e, u, F, a.P);
   }

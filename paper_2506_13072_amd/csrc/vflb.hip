@@ -57,6 +57,8 @@ struct vflb_sim {
   size_t off_tab = 0, off_part = 0, off_res = 0, off_hdr = 0;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   bool is_view = false;  // an instance of a batch: buffers and stepping belong to the batch
+  const float* clamp = nullptr;  // settling targets while vflb::internal::sim_settle runs
+  int clamp_flags = 0;
   std::string err;
 
   size_t store_bytes() const {
@@ -169,12 +171,18 @@ StepArgs<S> make_step_args(const vflb_sim* s, int64_t t, int parity) {
   a.inv_sh = (R)std::ldexp(1.0, -s->log2_sh);
   if (s->storage != VFLB_F16S) a.sf = a.inv_sf = a.sh = a.inv_sh = (R)1;
   a.first = (t == 0);
+  a.clamp = nullptr;
+  a.clamp_flags = 0;
   return a;
 }
 
 template <int D, class S>
 vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
-  const StepArgs<S> a = make_step_args<S>(s, t, parity);
+  StepArgs<S> a = make_step_args<S>(s, t, parity);
+  if (D == 2) {
+    a.clamp = s->clamp;
+    a.clamp_flags = s->clamp_flags;
+  }
   if constexpr (D == 2) {
     const int ty = default_tile_y(s);
     const int ntx = (s->nx + 63) / 64, nty = (s->ny + ty - 1) / ty;
@@ -731,6 +739,13 @@ vflb_status vflb_stream_copy(const void* src, void* dst, size_t nbytes, void* hi
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(nullptr, VFLB_EDEVICE, "copy launch failed: %s", hipGetErrorString(e));
   return VFLB_OK;
+}
+
+vflb_status vflb_settle(vflb_sim* s, const float* dev_targets, int64_t nsteps, int flags) {
+  if (!s) return VFLB_EINVAL;
+  if (!dev_targets || nsteps < 0) return fail(s, VFLB_EINVAL, "need targets and nsteps >= 0");
+  if (s->is_view && s->t != 0) return fail(s, VFLB_ESTATE, "settle a batch instance right after its initialisation");
+  return vflb::internal::sim_settle_f32(s, dev_targets, nsteps, flags);
 }
 
 void vflb_destroy(vflb_sim* s) {
@@ -1338,6 +1353,26 @@ vflb_status sim_init_f32(vflb_sim* s, const float* u, const float* tau) {
   s->inited = true;
   s->snap_valid = false;  // the snapshot buffer held the fields
   return VFLB_OK;
+}
+
+vflb_status sim_settle_f32(vflb_sim* s, const float* targets, int64_t nsteps, int flags) {
+  vflb_status rc = need_ready(s);
+  if (rc != VFLB_OK) return rc;
+  if (!s->inited) return fail(s, VFLB_ESTATE, "initialise the fields first");
+  if (s->D != 2) return fail(s, VFLB_EINVAL, "settling is implemented for D2Q9");
+  if (flags < 1 || flags > 3) return fail(s, VFLB_EINVAL, "settle flags must be 1, 2 or 3");
+  s->clamp = targets;
+  s->clamp_flags = flags;
+  for (int64_t k = 0; k < nsteps && rc == VFLB_OK; ++k) {
+    rc = dispatch<StepOp>(s, s->t, s->stream, s->cur);
+    if (rc == VFLB_OK) {
+      s->cur ^= 1;
+      s->t += 1;
+    }
+  }
+  s->clamp = nullptr;
+  s->clamp_flags = 0;
+  return rc;
 }
 
 }  // namespace internal

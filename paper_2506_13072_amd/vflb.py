@@ -29,6 +29,7 @@ PERIODIC, WALLS = 0, 1
 NBUF = 5
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = range(6)
 RUN_ACTIVE, RUN_CONVERGED, RUN_CAPPED, RUN_UNSTABLE, RUN_SKIPPED = range(5)
+SETTLE_U, SETTLE_A = 1, 2
 
 
 class VflbError(RuntimeError):
@@ -121,7 +122,9 @@ def lib():
         L.vflb_mlp_forward.argtypes = [P, P, P, I64]
         L.vflb_mlp_grad.argtypes = [P, P, P, I64, P, ctypes.POINTER(D)]
         L.vflb_mlp_train_step.argtypes = [P, P, P, I64, ctypes.c_float, ctypes.POINTER(D)]
-        L.vflb_init_from_mlp.argtypes = [P, P, ctypes.POINTER(D), D, D]
+        L.vflb_init_from_mlp.argtypes = [P, P, ctypes.POINTER(D), D, D, I64, I]
+        L.vflb_settle.argtypes = [P, P, I64, I]
+        L.vflb_settle.restype = I
         L.vflb_mlp_destroy.argtypes = [P]
         L.vflb_mlp_destroy.restype = None
         L.vflb_mlp_last_error.argtypes = [P]
@@ -217,8 +220,8 @@ class Sim:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().vflb_destroy(h)
+        if h and _lib is not None:
+            _lib.vflb_destroy(h)
             self._h = None
 
     @property
@@ -341,12 +344,25 @@ class Sim:
         _check(self.handle, lib().vflb_save(self.handle, ctypes.c_void_p(blob.data_ptr()), n.value))
         return blob
 
-    def init_from_mlp(self, mlp, extra, u_scale, tau_scale):
+    def init_from_mlp(self, mlp, extra, u_scale, tau_scale, settle_steps=0,
+                      settle_flags=SETTLE_A):
         """Start from the network's prediction at every node (inputs
-        (x/nx, y/ny, *extra)); the network must use this simulation's stream."""
+        (x/nx, y/ny, *extra)), then settle_steps settling steps; the network
+        must use this simulation's stream."""
         e = (ctypes.c_double * 3)(*[float(v) for v in extra])
         _mcheck(mlp._h, lib().vflb_init_from_mlp(self.handle, mlp._h, e, float(u_scale),
-                                                  float(tau_scale)))
+                                                  float(tau_scale), int(settle_steps),
+                                                  int(settle_flags)))
+
+    def settle(self, u, tau, nsteps, flags=3):
+        """Settling steps towards node-major fields u [N, 2], tau [N, 3]."""
+        t = np.concatenate([np.asarray(u, np.float64).T.ravel(),
+                            np.asarray(tau, np.float64).T.ravel()]).astype(np.float32)
+        dt = self.torch.as_tensor(t, device=self.device)
+        self.torch.cuda.current_stream(self.device).synchronize()
+        _check(self.handle, lib().vflb_settle(self.handle, ctypes.c_void_p(dt.data_ptr()),
+                                              int(nsteps), int(flags)))
+        self.stream.synchronize()
 
     def load(self, blob):
         _check(self.handle, lib().vflb_load(self.handle, ctypes.c_void_p(blob.data_ptr()),
@@ -388,8 +404,8 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().vflb_batch_destroy(h)
+        if h and _lib is not None:
+            _lib.vflb_batch_destroy(h)
             self._h = None
 
     def __len__(self):
@@ -468,8 +484,8 @@ class Mlp:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().vflb_mlp_destroy(h)
+        if h and _lib is not None:
+            _lib.vflb_mlp_destroy(h)
             self._h = None
 
     def init(self, seed):

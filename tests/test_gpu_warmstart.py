@@ -1,0 +1,71 @@
+"""The learned warm start end to end on small four-roll lattices: steady
+states from a batch train the network, the network initialises held-out
+lattices, and the fallback rule replaces a bad prediction by the cold run.
+Also the settling steps: from the exact steady fields they remove the
+transient that an equilibrium-only start excites."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_13072_amd import vflb as V
+    from paper_2506_13072_amd import warmstart as W
+    from paper_2506_13072_amd.workloads import ensemble_draws
+    draws = ensemble_draws(28, seed=4242)
+    specs = [dict(side=64, Re=1.0, Wi=min(d["Wi"], 1.0), beta=d["beta"], U0=0.01) for d in draws]
+    run = W.steady_states(V, specs[:24], tol=1e-5)
+    ok = [i for i in range(24) if run["status"][i] == V.RUN_CONVERGED]
+    assert len(ok) >= 20
+    X, T = W.training_set(V, run, specs, ok)
+    mlp = V.Mlp(max_batch=8192, seed=3, sigma=1.5)
+    hist = W.train(mlp, X, T, iters=1500, rows=8192, lr=2e-3, log_every=500)
+    return dict(V=V, W=W, specs=specs, run=run, mlp=mlp, hist=hist)
+
+
+def test_training_fits_the_steady_states(env):
+    first, last = env["hist"][0][1], env["hist"][-1][1]
+    assert last < 0.02 * first, env["hist"]
+
+
+def test_warm_start_lowers_the_early_residual(env):
+    V, W = env["V"], env["W"]
+    res = W.warm_vs_cold(V, env["mlp"], env["specs"][24:], tol=1e-5, K0=1000)
+    better = res["R_warm_K0"] < res["R_cold_K0"]
+    assert better.sum() >= 3, (res["R_warm_K0"], res["R_cold_K0"])
+    assert np.all(res["effective_warm_steps"][~res["fallback"]] ==
+                  res["warm_steps"][~res["fallback"]])
+
+
+def test_bad_prediction_falls_back_to_the_cold_run(env):
+    V, W = env["V"], env["W"]
+    specs = env["specs"][24:]
+    res = W.warm_vs_cold(V, env["mlp"], specs, tol=1e-5, K0=1000, u_scale_factor=100.0)
+    assert np.all(res["fallback"])
+    assert np.all(res["effective_warm_steps"] == 1000 + res["cold_steps"])
+    for i in range(len(specs)):
+        assert not res["warm"].is_active(i)
+        assert res["warm_status"][i] == V.RUN_SKIPPED
+
+
+def test_settling_removes_the_initial_transient(env):
+    V, W = env["V"], env["W"]
+    specs, run = env["specs"][:4], env["run"]
+    fields = [(run["batch"][i].read(V.FIELD_U), run["batch"][i].read(V.FIELD_TAU))
+              for i in range(4)]
+    r = {}
+    for settle in (0, 1000):
+        b, _ = W.four_roll_batch(V, specs)
+        for i, (u, tau) in enumerate(fields):
+            b[i].init_fields(u, tau, None)
+            if settle:
+                b[i].settle(u, tau, settle, V.SETTLE_U | V.SETTLE_A)
+        b.reduce()
+        b.step(100)
+        r[settle] = b.reduce()[:, 0]
+    assert np.all(r[1000] < 0.1 * r[0]), r
