@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -186,6 +188,38 @@ def run_gpu_ensemble(n, steps, warmup, storage="f32", compare_unbatched=True):
     return out
 
 
+def run_gpu_warmstart(n_train=96, n_test=16, side=64, tol=1e-6, iters=8000, K0=1000):
+    """Time to a steady state (R < tol) of held-out four-roll lattices,
+    started from rest and from the trained network (fallback rule at K0)."""
+    import torch
+    from paper_2506_13072_amd import vflb as V
+    from paper_2506_13072_amd import warmstart as W
+    from paper_2506_13072_amd.workloads import ensemble_draws
+    draws = ensemble_draws(n_train + n_test, seed=777)
+    specs = [dict(side=side, Re=1.0, Wi=d["Wi"], beta=d["beta"], U0=0.01) for d in draws]
+    t0 = time.perf_counter()
+    run = W.steady_states(V, specs[:n_train], tol=tol)
+    t_data = time.perf_counter() - t0
+    ok = [i for i in range(n_train) if run["status"][i] == V.RUN_CONVERGED]
+    X, T = W.training_set(V, run, specs, ok)
+    mlp = V.Mlp(max_batch=16384, seed=1, sigma=1.5)
+    t0 = time.perf_counter()
+    hist = W.train(mlp, X, T, iters=iters, rows=16384, lr=2e-3, log_every=iters // 4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = W.warm_vs_cold(V, mlp, specs[n_train:], tol=tol, K0=K0)
+    return dict(n_train=len(ok), t_data=t_data, t_train=t_train, loss=hist[-1][1],
+                cold_steps=int(res["cold_steps"].sum()),
+                warm_steps=int(res["effective_warm_steps"].sum()),
+                fallbacks=int(res["fallback"].sum()),
+                R_K0_cold_median=float(np.median(res["R_cold_K0"])),
+                R_K0_warm_median=float(np.median(res["R_warm_K0"])),
+                cold_converged=int((res["cold_status"] == V.RUN_CONVERGED).sum()),
+                warm_converged=int(((res["warm_status"] == V.RUN_CONVERGED) |
+                                    res["fallback"]).sum()),
+                t_cold=res["seconds_cold_after_K0"], t_warm=res["seconds_warm_after_K0"])
+
+
 def measured_traffic(record, kernel):
     """HBM bytes per launch of the step kernel (FETCH_SIZE + WRITE_SIZE,
     scaled against the streaming-copy kernel) from a committed rocprofv3
@@ -267,7 +301,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile height: D2Q9 4, 8, 16; D3Q19 4, 8")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy kernel (counter calibration)")
-    ap.add_argument("--workload", default="channel", choices=["channel", "tgv", "ensemble"],
+    ap.add_argument("--workload", default="channel",
+                    choices=["channel", "tgv", "ensemble", "warmstart"],
                     help="channel: the 8192x1024 D2Q9 headline; tgv: 512^3 D3Q19 "
                          "Taylor-Green vortex; ensemble: 256 four-roll lattices of "
                          "sides 64..512 as one batch (both reported, not the headline)")
@@ -281,6 +316,17 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "warmstart":
+        r = run_gpu_warmstart()
+        print(json.dumps({"metric": "time to steady state (R<1e-6), held-out four-roll 64x64, "
+                                    "steps summed over 16 lattices",
+                          "value": r["warm_steps"], "unit": "steps", "n_gpus": 1,
+                          "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
+                          "data": "synthetic", "cold_steps": r["cold_steps"],
+                          "warm_over_cold": round(r["warm_steps"] / r["cold_steps"], 3),
+                          "detail": {k: (round(v, 6) if isinstance(v, float) else v)
+                                     for k, v in r.items()}}), flush=True)
+        return
     if args.workload == "ensemble":
         r = run_gpu_ensemble(args.instances, args.steps, args.warmup, args.storage)
         bpl = bytes_per_lup(2, args.storage)

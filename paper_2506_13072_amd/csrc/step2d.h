@@ -66,7 +66,7 @@ struct Tile2Lds {
 // One 64 x TY tile of the step at origin (x0, y0).  The workgroup's lanes
 // are (threadIdx.x, threadIdx.y) = (0..63, 0..TY-1); the tile contains one
 // barrier, so every lane of the workgroup calls it.
-template <class S, int TY>
+template <class S, int TY, bool CLAMP = false>
 __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
                                    Tile2Lds<typename StoreT<S>::R, TY>& lds) {
   using R = typename StoreT<S>::R;
@@ -138,7 +138,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
   if (valid) {
     force_at<R>(a.F, wx, wy, g.nx, g.ny, F);
     velocity2(f, F, u);
-    if (a.clamp && (a.clamp_flags & 1)) {
+    if (CLAMP && (a.clamp_flags & 1)) {
       u[0] = (R)a.clamp[(size_t)wy * g.nx + wx];
       u[1] = (R)a.clamp[N + (size_t)wy * g.nx + wx];
     }
@@ -150,7 +150,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
     R Fh[3], uh[3];
     force_at<R>(a.F, hx, hy, g.nx, g.ny, Fh);
     velocity2(fh, Fh, uh);
-    if (a.clamp && (a.clamp_flags & 1)) {
+    if (CLAMP && (a.clamp_flags & 1)) {
       uh[0] = (R)a.clamp[(size_t)hy * g.nx + hx];
       uh[1] = (R)a.clamp[N + (size_t)hy * g.nx + hx];
     }
@@ -168,7 +168,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
       for (int i = 0; i < Q; ++i) s += h[c][i];
       e[c] = s;
     }
-    if (a.clamp && (a.clamp_flags & 2)) {  // A - I = tau lambda / eta_p
+    if (CLAMP && (a.clamp_flags & 2)) {  // A - I = tau lambda / eta_p
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         e[c] = a.P.eta_over_lam > 0 ? (R)a.clamp[(2 + c) * N + n] / a.P.eta_over_lam : (R)0;
@@ -206,11 +206,13 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
   Aux<2, R>::store(aux, n, N, chi, u);
 }
 
-template <class S, int TY>
+// CLAMP: a settling step (StepArgs::clamp); compiled separately so that the
+// production step carries none of it
+template <class S, int TY, bool CLAMP = false>
 __global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx, int nty) {
   __shared__ Tile2Lds<typename StoreT<S>::R, TY> lds;
   (void)nty;
-  step2d_tile<S, TY>(a, (blockIdx.x % ntx) * 64, (blockIdx.x / ntx) * TY, lds);
+  step2d_tile<S, TY, CLAMP>(a, (blockIdx.x % ntx) * 64, (blockIdx.x / ntx) * TY, lds);
 }
 
 // Batched step over many lattices: a persistent launch whose workgroups walk

@@ -187,16 +187,21 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
     const int ty = default_tile_y(s);
     const int ntx = (s->nx + 63) / 64, nty = (s->ny + ty - 1) / ty;
     const dim3 grid((unsigned)(ntx * nty));
-    switch (ty) {
-      case 4:
-        hipLaunchKernelGGL((step2d_kernel<S, 4>), grid, dim3(64, 4), 0, st, a, ntx, nty);
-        break;
-      case 16:
-        hipLaunchKernelGGL((step2d_kernel<S, 16>), grid, dim3(64, 16), 0, st, a, ntx, nty);
-        break;
-      default:
-        hipLaunchKernelGGL((step2d_kernel<S, 8>), grid, dim3(64, 8), 0, st, a, ntx, nty);
-        break;
+    if (a.clamp) {  // settling steps: one tile height suffices
+      hipLaunchKernelGGL((step2d_kernel<S, 8, true>), dim3(ntx * ((s->ny + 7) / 8)), dim3(64, 8),
+                         0, st, a, ntx, (s->ny + 7) / 8);
+    } else {
+      switch (ty) {
+        case 4:
+          hipLaunchKernelGGL((step2d_kernel<S, 4>), grid, dim3(64, 4), 0, st, a, ntx, nty);
+          break;
+        case 16:
+          hipLaunchKernelGGL((step2d_kernel<S, 16>), grid, dim3(64, 16), 0, st, a, ntx, nty);
+          break;
+        default:
+          hipLaunchKernelGGL((step2d_kernel<S, 8>), grid, dim3(64, 8), 0, st, a, ntx, nty);
+          break;
+      }
     }
   } else {
     constexpr int ZC = 32;
