@@ -210,6 +210,14 @@ vflb_status vflb_reduce(vflb_sim *sim, double out[14]);
  * array of n doubles (n must equal the field size). */
 vflb_status vflb_read(vflb_sim *sim, int field, double *dev_dst, size_t n);
 
+/* vflb_read restricted to a box of size[0] x size[1] x size[2] nodes with
+ * origin lo (size[2] = 1, lo[2] = 0 in 2D): component-major, x fastest
+ * within the box; n = width of the field x box nodes.  Coordinates wrap on
+ * periodic axes; on a wall axis the box must lie inside the lattice
+ * (EINVAL otherwise). */
+vflb_status vflb_read_box(vflb_sim *sim, int field, const int lo[3],
+                          const int size[3], double *dev_dst, size_t n);
+
 /* Checkpoint: vflb_state_size() bytes describe the full state (populations,
  * auxiliary fields, time level).  vflb_save copies it into a caller device
  * blob, vflb_load restores it (same lattice, size and storage). */

@@ -190,64 +190,82 @@ __device__ inline void node_xyz(size_t n, const Geo& g, int& x, int& y, int& z) 
   z = (int)(n / ((size_t)g.nx * g.ny));
 }
 
+// A box of nodes for read-back: origin lo (any integers; coordinates wrap
+// periodically) and extent n; box node k (x fastest) maps to a lattice node.
+struct Box {
+  int lo[3], n[3];
+  size_t N;  // n[0] n[1] n[2]
+};
+
+__device__ inline void box_node(size_t k, const Box& b, const Geo& g, int& x, int& y, int& z) {
+  const int bx = (int)(k % b.n[0]), by = (int)((k / b.n[0]) % b.n[1]),
+            bz = (int)(k / ((size_t)b.n[0] * b.n[1]));
+  x = ((b.lo[0] + bx) % g.nx + g.nx) % g.nx;
+  y = ((b.lo[1] + by) % g.ny + g.ny) % g.ny;
+  z = ((b.lo[2] + bz) % g.nz + g.nz) % g.nz;
+}
+
 // ------------------------------------------------------------- read-back
 enum { FIELD_U = 0, FIELD_P = 1, FIELD_RHO = 2, FIELD_A = 3, FIELD_TAU = 4,
        FIELD_F = 5, FIELD_H = 6, FIELD_CHI_PREV = 7, FIELD_U_PREV = 8 };
 
 // auxiliary state chi(t-1) (field 7) or u(t-1) (field 8), component-major FP64
 template <int D, class R>
-__global__ void __launch_bounds__(256) aux_read_kernel(const R* aux, Geo g, int field,
+__global__ void __launch_bounds__(256) aux_read_kernel(const R* aux, Geo g, Box box, int field,
                                                        double* out) {
   constexpr int NC = Lat<D>::NC;
-  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
-       n += (size_t)gridDim.x * blockDim.x) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < box.N;
+       k += (size_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    box_node(k, box, g, x, y, z);
+    const size_t n = node_of(x, y, z, g);
     R chi[NC], u[3] = {0, 0, 0};
     Aux<D, R>::load(aux, n, g.N, chi, u);
     if (field == FIELD_CHI_PREV)
-      for (int c = 0; c < NC; ++c) out[(size_t)c * g.N + n] = (double)chi[c];
+      for (int c = 0; c < NC; ++c) out[(size_t)c * box.N + k] = (double)chi[c];
     else
-      for (int b = 0; b < D; ++b) out[(size_t)b * g.N + n] = (double)u[b];
+      for (int b = 0; b < D; ++b) out[(size_t)b * box.N + k] = (double)u[b];
   }
 }
 
 template <int D, class S>
 __global__ void __launch_bounds__(256) moments_kernel(
-    const S* pin, Geo g, Phys<typename StoreT<S>::R> P,
+    const S* pin, Geo g, Box box, Phys<typename StoreT<S>::R> P,
     ForceArgs<typename StoreT<S>::R> fa, typename StoreT<S>::R inv_sf,
     typename StoreT<S>::R inv_sh, int field, double* out) {
   using L = Lat<D>;
   constexpr int Q = L::Q, NC = L::NC;
-  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
-       n += (size_t)gridDim.x * blockDim.x) {
+  const size_t M = box.N;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < M;
+       k += (size_t)gridDim.x * blockDim.x) {
     int x, y, z;
-    node_xyz<D>(n, g, x, y, z);
+    box_node(k, box, g, x, y, z);
     NodeMoments<D, S> m;
     node_moments<D, S>(pin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
     switch (field) {
       case FIELD_U:
-        for (int b = 0; b < D; ++b) out[(size_t)b * g.N + n] = (double)m.u[b];
+        for (int b = 0; b < D; ++b) out[(size_t)b * M + k] = (double)m.u[b];
         break;
       case FIELD_P:
-        out[n] = (double)m.p;
+        out[k] = (double)m.p;
         break;
       case FIELD_RHO:
-        out[n] = 1.0 + 3.0 * (double)m.p;
+        out[k] = 1.0 + 3.0 * (double)m.p;
         break;
       case FIELD_A:
         for (int c = 0; c < NC; ++c)
-          out[(size_t)c * g.N + n] =
-              (double)m.e[c] + ((L::ca(c) == L::cb(c)) ? 1.0 : 0.0);
+          out[(size_t)c * M + k] = (double)m.e[c] + ((L::ca(c) == L::cb(c)) ? 1.0 : 0.0);
         break;
       case FIELD_TAU:
-        for (int c = 0; c < NC; ++c) out[(size_t)c * g.N + n] = (double)m.tau[c];
+        for (int c = 0; c < NC; ++c) out[(size_t)c * M + k] = (double)m.tau[c];
         break;
       case FIELD_F:
-        for (int i = 0; i < Q; ++i) out[(size_t)i * g.N + n] = (double)m.f[i];
+        for (int i = 0; i < Q; ++i) out[(size_t)i * M + k] = (double)m.f[i];
         break;
       case FIELD_H:
         for (int c = 0; c < NC; ++c)
           for (int i = 0; i < Q; ++i)
-            out[((size_t)c * Q + i) * g.N + n] =
+            out[((size_t)c * Q + i) * M + k] =
                 (double)m.h[c][i] + ((L::ca(c) == L::cb(c)) ? L::w(i) : 0.0);
         break;
     }

@@ -242,17 +242,33 @@ vflb_status launch_init(vflb_sim* s, const T* u, const T* tau, const T* p) {
   return VFLB_OK;
 }
 
+Box whole_box(const vflb_sim* s) {
+  Box b;
+  b.lo[0] = b.lo[1] = b.lo[2] = 0;
+  b.n[0] = s->nx;
+  b.n[1] = s->ny;
+  b.n[2] = s->nz;
+  b.N = s->N;
+  return b;
+}
+
+int grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > (size_t)kRedBlocksMax) b = kRedBlocksMax;
+  return (int)(b ? b : 1);
+}
+
 template <int D, class S>
-vflb_status launch_moments(vflb_sim* s, int field, double* out) {
+vflb_status launch_moments(vflb_sim* s, int field, double* out, const Box& box) {
   using R = typename StoreT<S>::R;
   R isf = (R)1, ish = (R)1;
   if (s->storage == VFLB_F16S) {
     isf = (R)std::ldexp(1.0, -s->log2_sf);
     ish = (R)std::ldexp(1.0, -s->log2_sh);
   }
-  hipLaunchKernelGGL((moments_kernel<D, S>), dim3(grid1d(s, 256)), dim3(256), 0,
+  hipLaunchKernelGGL((moments_kernel<D, S>), dim3(grid_for(box.N)), dim3(256), 0,
                      s->stream, static_cast<const S*>(s->buf[VFLB_BUF_POP0 + s->cur]),
-                     geo_of(s),
+                     geo_of(s), box,
                      phys_of<R>(s), force_of<R>(s, s->t), isf, ish, field, out);
   HIP_TRY(s, hipGetLastError());
   return VFLB_OK;
@@ -310,8 +326,8 @@ template <int D, class S> struct InitOp {
   }
 };
 template <int D, class S> struct MomOp {
-  static vflb_status run(vflb_sim* s, int field, double* out) {
-    return launch_moments<D, S>(s, field, out);
+  static vflb_status run(vflb_sim* s, int field, double* out, Box box) {
+    return launch_moments<D, S>(s, field, out, box);
   }
 };
 template <int D, class S> struct RedOp {
@@ -626,45 +642,87 @@ vflb_status vflb_reduce(vflb_sim* s, double out[14]) {
   return finish_reduce(s, r, out);
 }
 
+namespace {
+
+// values per node of a read-back field (0: unknown field)
+size_t field_width(const vflb_sim* s, int field) {
+  switch (field) {
+    case VFLB_FIELD_U: return (size_t)s->D;
+    case VFLB_FIELD_P:
+    case VFLB_FIELD_RHO: return 1;
+    case VFLB_FIELD_A:
+    case VFLB_FIELD_TAU: return (size_t)s->NC;
+    case VFLB_FIELD_F: return (size_t)s->Q;
+    case VFLB_FIELD_H: return (size_t)s->NC * s->Q;
+    case VFLB_FIELD_CHI_PREV: return (size_t)s->NC;
+    case VFLB_FIELD_U_PREV: return (size_t)s->D;
+    default: return 0;
+  }
+}
+
+vflb_status read_box(vflb_sim* s, int field, const Box& box, double* dev_dst) {
+  if (field == VFLB_FIELD_CHI_PREV || field == VFLB_FIELD_U_PREV) {
+    const int nb = grid_for(box.N);
+    const Geo g = geo_of(s);
+    void* aux = s->buf[VFLB_BUF_AUX];
+    if (s->D == 2 && s->storage == VFLB_F64)
+      hipLaunchKernelGGL((aux_read_kernel<2, double>), dim3(nb), dim3(256), 0, s->stream,
+                         static_cast<const double*>(aux), g, box, field, dev_dst);
+    else if (s->D == 2)
+      hipLaunchKernelGGL((aux_read_kernel<2, float>), dim3(nb), dim3(256), 0, s->stream,
+                         static_cast<const float*>(aux), g, box, field, dev_dst);
+    else if (s->storage == VFLB_F64)
+      hipLaunchKernelGGL((aux_read_kernel<3, double>), dim3(nb), dim3(256), 0, s->stream,
+                         static_cast<const double*>(aux), g, box, field, dev_dst);
+    else
+      hipLaunchKernelGGL((aux_read_kernel<3, float>), dim3(nb), dim3(256), 0, s->stream,
+                         static_cast<const float*>(aux), g, box, field, dev_dst);
+    HIP_TRY(s, hipGetLastError());
+    return VFLB_OK;
+  }
+  return dispatch<MomOp>(s, field, dev_dst, box);
+}
+
+}  // namespace
+
 vflb_status vflb_read(vflb_sim* s, int field, double* dev_dst, size_t n) {
   vflb_status rc = need_ready(s);
   if (rc != VFLB_OK) return rc;
   if (!s->inited) return fail(s, VFLB_ESTATE, "initialise the fields first");
   if (!dev_dst) return fail(s, VFLB_EINVAL, "destination is NULL");
-  size_t need;
-  switch (field) {
-    case VFLB_FIELD_U: need = (size_t)s->D * s->N; break;
-    case VFLB_FIELD_P:
-    case VFLB_FIELD_RHO: need = s->N; break;
-    case VFLB_FIELD_A:
-    case VFLB_FIELD_TAU: need = (size_t)s->NC * s->N; break;
-    case VFLB_FIELD_F: need = (size_t)s->Q * s->N; break;
-    case VFLB_FIELD_H: need = (size_t)s->NC * s->Q * s->N; break;
-    case VFLB_FIELD_CHI_PREV: need = (size_t)s->NC * s->N; break;
-    case VFLB_FIELD_U_PREV: need = (size_t)s->D * s->N; break;
-    default: return fail(s, VFLB_EINVAL, "unknown field %d", field);
+  const size_t w = field_width(s, field);
+  if (!w) return fail(s, VFLB_EINVAL, "unknown field %d", field);
+  if (n != w * s->N)
+    return fail(s, VFLB_EINVAL, "field %d holds %zu values, not %zu", field, w * s->N, n);
+  return read_box(s, field, whole_box(s), dev_dst);
+}
+
+vflb_status vflb_read_box(vflb_sim* s, int field, const int lo[3], const int size[3],
+                          double* dev_dst, size_t n) {
+  vflb_status rc = need_ready(s);
+  if (rc != VFLB_OK) return rc;
+  if (!s->inited) return fail(s, VFLB_ESTATE, "initialise the fields first");
+  if (!dev_dst || !lo || !size) return fail(s, VFLB_EINVAL, "NULL argument");
+  const size_t w = field_width(s, field);
+  if (!w) return fail(s, VFLB_EINVAL, "unknown field %d", field);
+  Box b;
+  const int dims[3] = {s->nx, s->ny, s->nz};
+  b.N = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int sz = a < s->D ? size[a] : 1, l = a < s->D ? lo[a] : 0;
+    if (sz < 1 || sz > dims[a])
+      return fail(s, VFLB_EINVAL, "box extent %d on axis %d outside [1, %d]", sz, a, dims[a]);
+    if ((s->walls >> a) & 1) {
+      if (l < 0 || l + sz > dims[a])
+        return fail(s, VFLB_EINVAL, "box leaves the walls of axis %d", a);
+    }
+    b.lo[a] = l;
+    b.n[a] = sz;
+    b.N *= (size_t)sz;
   }
-  if (n != need) return fail(s, VFLB_EINVAL, "field %d holds %zu values, not %zu", field, need, n);
-  if (field == VFLB_FIELD_CHI_PREV || field == VFLB_FIELD_U_PREV) {
-    const int nb = grid1d(s, 256);
-    const Geo g = geo_of(s);
-    void* aux = s->buf[VFLB_BUF_AUX];
-    if (s->D == 2 && s->storage == VFLB_F64)
-      hipLaunchKernelGGL((aux_read_kernel<2, double>), dim3(nb), dim3(256), 0, s->stream,
-                         static_cast<const double*>(aux), g, field, dev_dst);
-    else if (s->D == 2)
-      hipLaunchKernelGGL((aux_read_kernel<2, float>), dim3(nb), dim3(256), 0, s->stream,
-                         static_cast<const float*>(aux), g, field, dev_dst);
-    else if (s->storage == VFLB_F64)
-      hipLaunchKernelGGL((aux_read_kernel<3, double>), dim3(nb), dim3(256), 0, s->stream,
-                         static_cast<const double*>(aux), g, field, dev_dst);
-    else
-      hipLaunchKernelGGL((aux_read_kernel<3, float>), dim3(nb), dim3(256), 0, s->stream,
-                         static_cast<const float*>(aux), g, field, dev_dst);
-    HIP_TRY(s, hipGetLastError());
-    return VFLB_OK;
-  }
-  return dispatch<MomOp>(s, field, dev_dst);
+  if (n != w * b.N)
+    return fail(s, VFLB_EINVAL, "the box holds %zu values, not %zu", w * b.N, n);
+  return read_box(s, field, b, dev_dst);
 }
 
 // checkpoint blob: 256-byte header, then f, h, aux of the current state

@@ -85,6 +85,8 @@ def lib():
         L.vflb_time.restype = I64
         L.vflb_reduce.argtypes = [P, ctypes.POINTER(D)]
         L.vflb_read.argtypes = [P, I, P, SZ]
+        L.vflb_read_box.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), P, SZ]
+        L.vflb_read_box.restype = I
         L.vflb_state_size.argtypes = [P, ctypes.POINTER(SZ)]
         L.vflb_save.argtypes = [P, P, SZ]
         L.vflb_load.argtypes = [P, P, SZ]
@@ -324,6 +326,27 @@ class Sim:
         a = t.cpu().numpy().T.copy()
         if field == FIELD_H:
             a = a.reshape(self.N, self.NC, self.Q)
+        return a
+
+    def _ncomp(self, field):
+        return {FIELD_U: self.D, FIELD_P: 1, FIELD_RHO: 1, FIELD_A: self.NC,
+                FIELD_TAU: self.NC, FIELD_F: self.Q, FIELD_H: self.NC * self.Q,
+                FIELD_CHI_PREV: self.NC, FIELD_U_PREV: self.D}[field]
+
+    def read_box(self, field, lo, size):
+        """Field on a box of nodes (origin lo, extent size; x fastest) as a
+        node-major numpy array [box nodes, ncomp] (FP64)."""
+        lo3 = (ctypes.c_int * 3)(*(list(lo) + [0] * (3 - len(lo))))
+        sz3 = (ctypes.c_int * 3)(*(list(size) + [1] * (3 - len(size))))
+        nb = int(np.prod(list(sz3)))
+        ncomp = self._ncomp(field)
+        out = self.torch.empty(ncomp * nb, dtype=self.torch.float64, device=self.device)
+        _check(self.handle, lib().vflb_read_box(self.handle, int(field), lo3, sz3,
+                                                ctypes.c_void_p(out.data_ptr()), out.numel()))
+        self.stream.synchronize()
+        a = out.view(ncomp, nb).cpu().numpy().T.copy()
+        if field == FIELD_H:
+            a = a.reshape(nb, self.NC, self.Q)
         return a
 
     def moments(self):

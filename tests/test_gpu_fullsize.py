@@ -1,0 +1,104 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times (FP32 storage, the default tile shape, steps replayed from
+captured graphs), on sampled outputs: the state of boxes of nodes is read
+from the GPU, one oracle step advances each box, and the box interior (at
+least 3 nodes from a cut edge; a node's update depends on neighbours at
+distance 2) must agree with the GPU's next step.  Channel boxes span the
+full height, so both walls are exact; the 3D boxes wrap periodically.
+Bar: FP32 storage, relative L2 <= 1e-5 per field."""
+import numpy as np
+import pytest
+
+from oracle import analytic as AN
+from oracle import oracle as O
+from paper_2506_13072_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 3
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_13072_amd import vflb
+    vflb.lib()
+    return vflb
+
+
+def box_state(V, g, lo, size):
+    return dict(f=g.read_box(V.FIELD_F, lo, size), h=g.read_box(V.FIELD_H, lo, size),
+                chi_prev=g.read_box(V.FIELD_CHI_PREV, lo, size),
+                u_prev=g.read_box(V.FIELD_U_PREV, lo, size))
+
+
+def interior(a, size, d):
+    shape = tuple(size[::-1][-d:]) if d == 3 else (size[1], size[0])
+    a = a.reshape(shape + a.shape[1:])
+    if d == 2:  # periodic in x only: trim x
+        return a[:, MARGIN:-MARGIN].reshape((-1,) + a.shape[2:])
+    return a[MARGIN:-MARGIN, MARGIN:-MARGIN, MARGIN:-MARGIN].reshape((-1,) + a.shape[3:])
+
+
+def compare(V, g, o, lo, size, d):
+    after = box_state(V, g, lo, size)
+    ref = o.get_state()
+    out = {}
+    for k in ("f", "h", "chi_prev", "u_prev"):
+        out[k] = AN.rel_l2(interior(after[k], size, d), interior(ref[k], size, d))
+    assert all(v <= 1e-5 for v in out.values()), out
+    return out
+
+
+def test_channel_8192x1024_sampled_parity(V):
+    w = WL.CHANNEL_8192x1024
+    ny, nx = w["shape"]
+    g = V.Sim(2, nx, ny, 1, "f32")
+    g.set_params(w["Re"], w["Wi"], w["beta"], w["U0"], w["L"])
+    g.set_boundaries((V.PERIODIC, V.WALLS))
+    lp = g.lattice_params()
+    force = 8 * (lp["nu_s"] + lp["nu_p"]) * w["U0"] / w["L"] ** 2
+    g.set_force(V.FORCE_CONST, (force, 0.0, 0.0))
+    u, tau, p = WL.smooth_fields(2, (ny, nx), 11, amp_u=w["U0"], amp_tau=1e-2 * lp["eta_p"],
+                                 amp_p=w["U0"] ** 2)
+    g.init_fields(u, tau, p)
+    g.step(130)  # single launches and two 64-step graphs, tile 64 x 16
+    t = g.t
+    p_or = O.lattice_params(w["Re"], w["Wi"], w["beta"], w["U0"], w["L"])
+    size = (40, ny)
+    los = [(x0 - MARGIN, 0) for x0 in (0, 3000, nx - 20)]  # one box across the seam
+    befores = [box_state(V, g, lo, size) for lo in los]
+    g.step(1)
+    for lo, before in zip(los, befores):
+        o = O.OracleSim(2, size[0], size[1])
+        o.set_params(p_or["tau_f"], 0.501, p_or["lam"], p_or["eta_p"])
+        o.set_walls((0, 1, 0))
+        o.set_force(O.FORCE_CONST, (force, 0.0, 0.0))
+        o.set_state(**before, t=t)
+        o.step(1)
+        compare(V, g, o, lo, size, 2)
+
+
+def test_tgv_512_sampled_parity(V):
+    w = WL.TGV_512
+    n = w["shape"][0]
+    g = V.Sim(3, n, n, n, "f32")
+    g.set_params(w["Re"], w["Wi"], w["beta"], w["U0"], w["L"])
+    u, p = WL.taylor_green_3d_device(n, w["U0"])
+    g.init_fields_device(u, None, p)
+    del u, p
+    g.step(9)
+    t = g.t
+    p_or = O.lattice_params(w["Re"], w["Wi"], w["beta"], w["U0"], w["L"])
+    boxes = [(200, 17, 300), (n - 8, n - 11, 5)]  # the second wraps on all axes
+    size = (22, 22, 22)
+    befores = [box_state(V, g, lo, size) for lo in boxes]
+    g.step(1)
+    for lo, before in zip(boxes, befores):
+        o = O.OracleSim(3, *size)
+        o.set_params(p_or["tau_f"], 0.501, p_or["lam"], p_or["eta_p"])
+        o.set_state(**before, t=t)
+        o.step(1)
+        compare(V, g, o, lo, size, 3)
