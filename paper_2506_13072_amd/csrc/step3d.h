@@ -311,6 +311,9 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
     plane_u(z + 1, fn);
     __syncthreads();
     if (in_xy) {
+      // the collision may fuse multiply-adds (this node's own arithmetic
+      // only; velocities shared through LDS are formed without contraction)
+#pragma clang fp contract(fast)
       const int rc = ((z % 3) + 3) % 3, rm = (((z - 1) % 3) + 3) % 3, rp = ((z + 1) % 3 + 3) % 3;
       const R u[3] = {ring[rc][0][oslot], ring[rc][1][oslot], ring[rc][2][oslot]};
       const R* F = Fown;
@@ -339,22 +342,36 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
       // pressure (App. B): cs2/(1 - w0) = 1/2 for D3Q19
       const R p = (R)0.5 * (sum_f - (R)1.5 * w0 * uu + a.P.tau_f * F0 + a.P.tau_f * fB[0]);
 
-      // ---- f collision: BGK + Guo forcing + f^B (Sec. 2.2)
+      // ---- f collision: BGK + Guo forcing + f^B (Sec. 2.2), per direction
+      //   f* = (1 - w_f) f + w_f f^eq + f^B_i + F_i, written as
+      //   (1 - w_f) f + a0 + f^B_i + a1 cu (3 + 9/2 cu) + a2 cF (1 + 3 cu)
+      // with the weight-class constants a0 = w (w_f (3 p - 3/2 u.u) - 3 k_f F.u),
+      // a1 = w w_f, a2 = 3 w k_f (w_f = 1/tau_f; the same sum, reordered)
+      const R omf = a.P.inv_tau_f, keepf = (R)1 - omf;
       {
         const R feq = (R)(3.0 * (L::w(0) - 1.0)) * p - w0 * (R)1.5 * uu;
-        f[0] = f[0] - (f[0] - feq) * a.P.inv_tau_f + fB[0] + F0;
+        f[0] = f[0] - (f[0] - feq) * omf + fB[0] + F0;
       }
+      R a0[2], a1[2], a2[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const R w = q == 0 ? (R)(1.0 / 18.0) : (R)(1.0 / 36.0);
+        a0[q] = w * (omf * (3 * p - (R)1.5 * uu) - 3 * a.P.k_f * Fu);
+        a1[q] = w * omf;
+        a2[q] = 3 * w * a.P.k_f;
+      }
+      R cu[NP], cup[NP];
       R mp[3] = {0, 0, 0};
       for_pairs<1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         constexpr int i = 2 * k - 1;
         constexpr int c[3] = {L::cx(i), L::cy(i), L::cz(i)};
-        constexpr R wi = (R)L::w(i);
-        const R cu = sg * ((R)c[0] * u[0] + (R)c[1] * u[1] + (R)c[2] * u[2]);
+        constexpr int q = k <= 3 ? 0 : 1;
+        cu[k] = sg * ((R)c[0] * u[0] + (R)c[1] * u[1] + (R)c[2] * u[2]);
+        cup[k] = sg * ((R)c[0] * up[0] + (R)c[1] * up[1] + (R)c[2] * up[2]);
         const R cF = sg * ((R)c[0] * F[0] + (R)c[1] * F[1] + (R)c[2] * F[2]);
-        const R feq = 3 * wi * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
-        const R Fi = wi * a.P.k_f * (3 * cF + 9 * cF * cu - 3 * Fu);
-        f[k] = f[k] - (f[k] - feq) * a.P.inv_tau_f + fB[i] + Fi;
+        f[k] = keepf * f[k] + a0[q] + fB[i] + a1[q] * cu[k] * (3 + (R)4.5 * cu[k]) +
+               a2[q] * cF * (1 + 3 * cu[k]);
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb)
           if (c[bb] != 0) mp[bb] += (R)c[bb] * f[k];
@@ -387,27 +404,32 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
       source_tensor<3, R>(e, G, a.P.inv_lam, chi);
 
       // ---- h collision (Sec. 2.3); the rest population closes
-      // sum_i h*_i = A - I + chi + (chi - chi(t-1))/2
+      // sum_i h*_i = A - I + chi + (chi - chi(t-1))/2.  Per direction
+      //   h* = (1 - w_h) h + w_h h^eq + chi_i + (chi_i - chi_i(t-1))/2
+      //      = (1 - w_h) h + k0 + k1 cu - k2 cu(t-1)
+      // with per component and weight class k0 = w (w_h e + s chi - r chi_p),
+      // k1 = w (3 w_h A + s k chi), k2 = w r k chi_p, k = 3 (1 - 1/(2 tau_h)),
+      // s = 3/2, r = 1/2 (s = 1, r = 0 at the first step)
       const bool first = a.first != 0;
+      const R omh = a.P.inv_tau_h, keeph = (R)1 - omh;
+      const R sc = first ? (R)1 : (R)1.5, rc2 = first ? (R)0 : (R)0.5;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const R Ac = e[c] + (c < 3 ? (R)1 : (R)0);
         const R target = e[c] + chi[c] + (first ? (R)0 : (R)0.5 * (chi[c] - chip[c]));
+        R k0[2], k1[2], k2[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const R w = q == 0 ? (R)(1.0 / 18.0) : (R)(1.0 / 36.0);
+          k0[q] = w * (omh * e[c] + sc * chi[c] - rc2 * chip[c]);
+          k1[q] = w * (3 * omh * Ac + sc * a.P.k_h3 * chi[c]);
+          k2[q] = w * rc2 * a.P.k_h3 * chip[c];
+        }
         R hs = 0;
         for_pairs<1>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          constexpr int i = 2 * k - 1;
-          constexpr int cv[3] = {L::cx(i), L::cy(i), L::cz(i)};
-          constexpr R wi = (R)L::w(i);
-          const R cu = sg * ((R)cv[0] * u[0] + (R)cv[1] * u[1] + (R)cv[2] * u[2]);
-          const R heq = wi * e[c] + 3 * wi * Ac * cu;
-          const R chi_i = wi * chi[c] * (1 + a.P.k_h3 * cu);
-          R src = chi_i;
-          if (!first) {
-            const R cup = sg * ((R)cv[0] * up[0] + (R)cv[1] * up[1] + (R)cv[2] * up[2]);
-            src += (R)0.5 * (chi_i - wi * chip[c] * (1 + a.P.k_h3 * cup));
-          }
-          h[c][k] = h[c][k] - (h[c][k] - heq) * a.P.inv_tau_h + src;
+          constexpr int q = k <= 3 ? 0 : 1;
+          h[c][k] = keeph * h[c][k] + k0[q] + k1[q] * cu[k] - k2[q] * cup[k];
           hs += h[c][k];
         });
         h[c][0] = target - pair_sum(hs);
