@@ -35,11 +35,14 @@ REDUCE_EVERY = 100
 
 def bytes_per_lup(d, storage):
     """Algorithmic HBM bytes per lattice update: every f and h population
-    read once and written once, plus chi(t-1) and u(t-1) read and written."""
+    read once and written once, plus chi(t-1) and u(t-1) read and written;
+    16-bit D2Q9 storage also reads and writes each node's FP32 anchor
+    (A - I, p, u: 24 bytes)."""
     q, nc = (9, 3) if d == 2 else (19, 6)
     sb = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[storage]
     ab = 8 if storage == "f64" else 4
-    return 2 * q * (1 + nc) * sb + 2 * (nc + d) * ab
+    anchor = 2 * 24 if (d == 2 and sb == 2) else 0
+    return 2 * q * (1 + nc) * sb + 2 * (nc + d) * ab + anchor
 
 
 def run_gpu(steps, warmup, storage="f32", tile=0):

@@ -131,7 +131,8 @@ struct NodeMoments {
 };
 
 template <int D, class S>
-__device__ inline void node_moments(const S* pin, int x, int y, int z, const Geo& g,
+__device__ inline void node_moments(const S* pin, const typename StoreT<S>::R* aux, int x, int y,
+                                    int z, const Geo& g,
                                     const Phys<typename StoreT<S>::R>& P,
                                     const ForceArgs<typename StoreT<S>::R>& fa,
                                     typename StoreT<S>::R inv_sf,
@@ -141,10 +142,24 @@ __device__ inline void node_moments(const S* pin, int x, int y, int z, const Geo
   using R = typename St::R;
   using L = Lat<D>;
   constexpr int Q = L::Q, NC = L::NC;
+  constexpr bool ANCHOR = D == 2 && St::kAnchored;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     R hv[NC];
-    Pops<D, S>::load(pin, pull_index<D>(i, x, y, z, g), g.N, inv_sf, inv_sh, m.f[i], hv);
+    const size_t t = pull_index<D>(i, x, y, z, g);
+    Pops<D, S>::load(pin, t, g.N, inv_sf, inv_sh, m.f[i], hv);
+    if constexpr (ANCHOR) {  // reference of the writing node + deviation
+      const int j = (int)(t / g.N);
+      const size_t src = t % g.N;
+      float4 q;
+      float2 v;
+      Anchor2::load(pin, src, g.N, q, v);
+      const R ux = (R)v.x, uy = (R)v.y;
+      m.f[i] += fref2<R>(j, (R)1, (R)q.w, ux, uy);
+      hv[0] += href2<R>(j, 0, (R)1, (R)q.x, ux, uy);
+      hv[1] += href2<R>(j, 1, (R)1, (R)q.y, ux, uy);
+      hv[2] += href2<R>(j, 2, (R)1, (R)q.z, ux, uy);
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) m.h[c][i] = hv[c];
   }
@@ -230,7 +245,7 @@ __global__ void __launch_bounds__(256) aux_read_kernel(const R* aux, Geo g, Box 
 
 template <int D, class S>
 __global__ void __launch_bounds__(256) moments_kernel(
-    const S* pin, Geo g, Box box, Phys<typename StoreT<S>::R> P,
+    const S* pin, const typename StoreT<S>::R* aux, Geo g, Box box, Phys<typename StoreT<S>::R> P,
     ForceArgs<typename StoreT<S>::R> fa, typename StoreT<S>::R inv_sf,
     typename StoreT<S>::R inv_sh, int field, double* out) {
   using L = Lat<D>;
@@ -241,7 +256,7 @@ __global__ void __launch_bounds__(256) moments_kernel(
     int x, y, z;
     box_node(k, box, g, x, y, z);
     NodeMoments<D, S> m;
-    node_moments<D, S>(pin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
+    node_moments<D, S>(pin, aux, x, y, z, g, P, fa, inv_sf, inv_sh, m);
     switch (field) {
       case FIELD_U:
         for (int b = 0; b < D; ++b) out[(size_t)b * M + k] = (double)m.u[b];
@@ -276,6 +291,26 @@ __global__ void __launch_bounds__(256) moments_kernel(
 // Equilibrium-only state: f = f^eq(p, u), h = h^eq(A, u) (shifted), with
 // A = I + lambda tau / eta_p; each value is written where the pull of the
 // first step reads it, so that the first step sees exactly this state.
+// anchor of node m from the initial fields: (E = lambda tau / eta_p, p)
+template <class T>
+__device__ inline float4 init_anchor(size_t m, size_t N, const T* tau_in, const T* p_in,
+                                     double lam_over_eta) {
+  float4 q;
+  q.x = tau_in ? (float)(lam_over_eta * tau_in[m]) : 0.0f;
+  q.y = tau_in ? (float)(lam_over_eta * tau_in[N + m]) : 0.0f;
+  q.z = tau_in ? (float)(lam_over_eta * tau_in[2 * N + m]) : 0.0f;
+  q.w = p_in ? (float)p_in[m] : 0.0f;
+  return q;
+}
+
+template <class T>
+__device__ inline float2 init_velocity(size_t m, size_t N, const T* u_in) {
+  float2 v;
+  v.x = u_in ? (float)u_in[m] : 0.0f;
+  v.y = u_in ? (float)u_in[N + m] : 0.0f;
+  return v;
+}
+
 template <int D, class S, class T>
 __global__ void __launch_bounds__(256) init_kernel(
     S* pbuf, typename StoreT<S>::R* aux, Geo g,
@@ -285,6 +320,7 @@ __global__ void __launch_bounds__(256) init_kernel(
   using R = typename St::R;
   using L = Lat<D>;
   constexpr int Q = L::Q, NC = L::NC;
+  constexpr bool ANCHOR = D == 2 && St::kAnchored;
   for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
        n += (size_t)gridDim.x * blockDim.x) {
     int x, y, z;
@@ -303,18 +339,34 @@ __global__ void __launch_bounds__(256) init_kernel(
       const R wi = (R)L::w(i);
       const R lam_i = (R)(i == 0 ? 3.0 * (L::w(0) - 1.0) : 3.0 * L::w(i));
       const R cu = cdot<D, R>(i, u);
-      const R feq = lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
+      R feq = lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
       R hv[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const R Ac = e[c] + ((L::ca(c) == L::cb(c)) ? (R)1 : (R)0);
         hv[c] = wi * e[c] + 3 * wi * Ac * cu;
       }
-      Pops<D, S>::store(pbuf, pull_index<D>(i, x, y, z, g), g.N, sf, sh, feq, hv);
+      const size_t t = pull_index<D>(i, x, y, z, g);
+      if constexpr (ANCHOR) {
+        // deviation from the reference of the node that stores the value
+        const int j = (int)(t / g.N);
+        const size_t src = t % g.N;
+        const float4 q = init_anchor(src, g.N, tau_in, p_in, lam_over_eta);
+        const float2 v = init_velocity(src, g.N, u_in);
+        const R ux = (R)v.x, uy = (R)v.y;
+        feq -= fref2<R>(j, (R)1, (R)q.w, ux, uy);
+        hv[0] -= href2<R>(j, 0, (R)1, (R)q.x, ux, uy);
+        hv[1] -= href2<R>(j, 1, (R)1, (R)q.y, ux, uy);
+        hv[2] -= href2<R>(j, 2, (R)1, (R)q.z, ux, uy);
+      }
+      Pops<D, S>::store(pbuf, t, g.N, sf, sh, feq, hv);
     }
     R zero[NC];
     for (int c = 0; c < NC; ++c) zero[c] = 0;
     Aux<D, R>::store(aux, n, g.N, zero, u);
+    if constexpr (ANCHOR)
+      Anchor2::store(pbuf, n, g.N, init_anchor(n, g.N, tau_in, p_in, lam_over_eta),
+                     init_velocity(n, g.N, u_in));
   }
 }
 
@@ -331,7 +383,8 @@ __device__ inline double wave_sum(double v) {
 // snapshot of u and tau (the residual compares against the snapshot taken
 // at the previous reduction).
 template <int D, class S>
-__device__ inline void reduce_node(const S* pin, typename StoreT<S>::R* snap, int snap_valid,
+__device__ inline void reduce_node(const S* pin, const typename StoreT<S>::R* aux,
+                                   typename StoreT<S>::R* snap, int snap_valid,
                                    int x, int y, int z, const Geo& g,
                                    const Phys<typename StoreT<S>::R>& P,
                                    const ForceArgs<typename StoreT<S>::R>& fa,
@@ -341,7 +394,7 @@ __device__ inline void reduce_node(const S* pin, typename StoreT<S>::R* snap, in
   constexpr int Q = L::Q, NC = L::NC;
   const size_t n = node_of(x, y, z, g);
   NodeMoments<D, S> m;
-  node_moments<D, S>(pin, x, y, z, g, P, fa, inv_sf, inv_sh, m);
+  node_moments<D, S>(pin, aux, x, y, z, g, P, fa, inv_sf, inv_sh, m);
   bool finite = true;
   for (int b = 0; b < D; ++b) {
     const double ub = (double)m.u[b];
@@ -403,7 +456,7 @@ __device__ inline void block_partials(const double* acc, double* out) {
 
 template <int D, class S>
 __global__ void __launch_bounds__(256) reduce_kernel(
-    const S* pin, typename StoreT<S>::R* snap, int snap_valid,
+    const S* pin, const typename StoreT<S>::R* aux, typename StoreT<S>::R* snap, int snap_valid,
     Geo g, Phys<typename StoreT<S>::R> P, ForceArgs<typename StoreT<S>::R> fa,
     typename StoreT<S>::R inv_sf, typename StoreT<S>::R inv_sh,
     double* partials) {
@@ -414,7 +467,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(
        n += (size_t)gridDim.x * blockDim.x) {
     int x, y, z;
     node_xyz<D>(n, g, x, y, z);
-    reduce_node<D, S>(pin, snap, snap_valid, x, y, z, g, P, fa, inv_sf, inv_sh, acc);
+    reduce_node<D, S>(pin, aux, snap, snap_valid, x, y, z, g, P, fa, inv_sf, inv_sh, acc);
   }
   block_partials(acc, partials + (size_t)blockIdx.x * NRED);
 }
@@ -453,8 +506,8 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchInst<S>* _
   for (int j = threadIdx.x; j < 64 * tile_h; j += blockDim.x) {
     const int x = e.x0 + (j & 63), y = e.y0 + (j >> 6);
     if (x < d.a.g.nx && y < d.a.g.ny)
-      reduce_node<2, S>(pin, d.snap, d.snap_valid, x, y, 0, d.a.g, d.a.P, d.a.F, d.a.inv_sf,
-                        d.a.inv_sh, acc);
+      reduce_node<2, S>(pin, d.a.aux, d.snap, d.snap_valid, x, y, 0, d.a.g, d.a.P, d.a.F,
+                        d.a.inv_sf, d.a.inv_sh, acc);
   }
   block_partials(acc, partials + (size_t)blockIdx.x * NRED);
 }

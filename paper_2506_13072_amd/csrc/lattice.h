@@ -93,18 +93,23 @@ __device__ inline void stream_store(T* p, T v) {
 }
 
 template <class S> struct StoreT;
+// kAnchored: D2Q9 populations stored as 16-bit deviations from reference
+// populations built from their node's FP32 anchor (see layout.h)
 template <> struct StoreT<double> {
   using R = double;
+  static constexpr bool kAnchored = false;
   __device__ static R ld(const double* p, size_t i, R) { return p[i]; }
   __device__ static void st(double* p, size_t i, R v, R) { stream_store(p + i, v); }
 };
 template <> struct StoreT<float> {
   using R = float;
+  static constexpr bool kAnchored = false;
   __device__ static R ld(const float* p, size_t i, R) { return p[i]; }
   __device__ static void st(float* p, size_t i, R v, R) { stream_store(p + i, v); }
 };
 template <> struct StoreT<_Float16> {
   using R = float;
+  static constexpr bool kAnchored = true;
   // v = stored * 2^-k ; stored = RNE(v * 2^k)  (the scale is exact)
   __device__ static R ld(const _Float16* p, size_t i, R inv_scale) {
     return (float)p[i] * inv_scale;
@@ -115,6 +120,7 @@ template <> struct StoreT<_Float16> {
 };
 template <> struct StoreT<bf16_t> {
   using R = float;
+  static constexpr bool kAnchored = true;
   __device__ static R ld(const bf16_t* p, size_t i, R) {
     uint32_t b = (uint32_t)p[i].bits << 16;
     return __uint_as_float(b);

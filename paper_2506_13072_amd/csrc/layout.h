@@ -14,6 +14,16 @@
 // Auxiliary state chi(t-1), u(t-1):
 //  D2Q9:  chi [N][3] then u [N][2] (one 12-byte and one 8-byte access).
 //  D3Q19: chi [NC][N] then u [D][N].
+//
+// Anchored 16-bit storage (D2Q9, FP16 and BF16): every node also keeps, in
+// FP32 in the population buffer (Anchor2), its anchor (E_xx, E_xy, E_yy, p)
+// with E = A - I of its post-collision state, p its pressure and u its
+// velocity, from which follow reference populations f_ref(p, u) (the
+// equilibrium form) and h_ref(E, u) (the shifted equilibrium form).  A stored population is the
+// 16-bit deviation of the value from the reference of the node that wrote
+// it, and a reader rebuilds the value as reference + deviation.  The
+// conserved moment A then lives in FP32: 16-bit rounding touches only the
+// small deviations and can no longer random-walk A.
 #pragma once
 
 #include "lattice.h"
@@ -133,6 +143,47 @@ template <> struct Pops<3, float> : Pops3Split<float> {};
 template <> struct Pops<3, double> : Pops3Split<double> {};
 template <> struct Pops<3, _Float16> : Pops3Split<_Float16> {};
 template <> struct Pops<3, bf16_t> : Pops3Split<bf16_t> {};
+
+// reference populations of direction i from an anchor (E = A - I, p, u);
+// a bounce-back pull reads the opposite direction: sgn = -1 flips c_i
+template <class R>
+__device__ inline R fref2(int i, R sgn, R p, R ux, R uy) {
+  const R wi = (R)Lat<2>::w(i);
+  const R lam_i = (R)(i == 0 ? 3.0 * (Lat<2>::w(0) - 1.0) : 3.0 * Lat<2>::w(i));
+  const R cu = sgn * ((R)Lat<2>::cx(i) * ux + (R)Lat<2>::cy(i) * uy);
+  return lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * (ux * ux + uy * uy));
+}
+template <class R>
+__device__ inline R href2(int i, int c, R sgn, R E, R ux, R uy) {
+  const R wi = (R)Lat<2>::w(i);
+  const R cu = sgn * ((R)Lat<2>::cx(i) * ux + (R)Lat<2>::cy(i) * uy);
+  return wi * E + 3 * wi * (E + (c != 1 ? (R)1 : (R)0)) * cu;
+}
+
+// Anchor of node n, kept in the population buffer after the 16-bit tuples
+// (so that it ping-pongs with them: a step reads the anchors of the buffer
+// it pulls from and writes those of the other): (E_xx, E_xy, E_yy, p) as
+// [N] float4 from a 256-byte aligned offset, then u as [N] float2.
+struct Anchor2 {
+  __host__ __device__ static size_t offset(size_t N) {
+    return ((size_t)2 * 4 * 9 * N + 255) & ~(size_t)255;
+  }
+  __host__ __device__ static size_t bytes(size_t N) { return offset(N) + 24 * N; }
+  __device__ static void load(const void* pbuf, size_t n, size_t N, float4& ep, float2& u) {
+    const char* b = static_cast<const char*>(pbuf) + offset(N);
+    ep = reinterpret_cast<const float4*>(b)[n];
+    u = reinterpret_cast<const float2*>(b + 16 * N)[n];
+  }
+  __device__ static void store(void* pbuf, size_t n, size_t N, float4 ep, float2 u) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    char* b = static_cast<char*>(pbuf) + offset(N);
+    const f4 q = {ep.x, ep.y, ep.z, ep.w};
+    const f2 v = {u.x, u.y};
+    __builtin_nontemporal_store(q, reinterpret_cast<f4*>(b) + n);
+    __builtin_nontemporal_store(v, reinterpret_cast<f2*>(b + 16 * N) + n);
+  }
+};
 
 // auxiliary state
 template <int D, class R> struct Aux;

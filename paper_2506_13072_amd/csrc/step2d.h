@@ -57,21 +57,33 @@ __device__ inline void velocity2(const R* f, const R* F, R* u) {
   u[1] = (f[2] - f[4] + f[5] + f[6] - f[7] - f[8]) + (R)0.5 * F[1];
 }
 
-// LDS of one 64 x TY tile: the velocity on the tile and its one-node halo
-template <class R, int TY>
+// LDS of one 64 x TY tile: the velocity on the tile and its one-node halo;
+// for anchored storage also the anchors (E, p, u) of the tile and a
+// two-node halo (the sources of the halo nodes' pulls)
+template <class R, int TY, bool ANCHOR>
 struct Tile2Lds {
   R su[2][66 * (TY + 2)];
+};
+template <class R, int TY>
+struct Tile2Lds<R, TY, true> {
+  R su[2][66 * (TY + 2)];
+  float anc[6][68 * (TY + 4)];
 };
 
 // One 64 x TY tile of the step at origin (x0, y0).  The workgroup's lanes
 // are (threadIdx.x, threadIdx.y) = (0..63, 0..TY-1); the tile contains one
 // barrier, so every lane of the workgroup calls it.
+template <class S, int TY>
+using Tile2LdsOf = Tile2Lds<typename StoreT<S>::R, TY, StoreT<S>::kAnchored>;
+
 template <class S, int TY, bool CLAMP = false>
 __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
-                                   Tile2Lds<typename StoreT<S>::R, TY>& lds) {
+                                   Tile2LdsOf<S, TY>& lds) {
   using R = typename StoreT<S>::R;
+  constexpr bool ANCHOR = StoreT<S>::kAnchored;
   constexpr int Q = 9, NC = 3, TX = 64, SX = TX + 2, SY = TY + 2;
   constexpr int H = 2 * SX + 2 * TY;  // halo nodes of the tile
+  constexpr int AX = TX + 4, AY = TY + 4;  // anchor region (two-node halo)
   R (*su)[SX * SY] = lds.su;
 
   const Geo g = a.g;
@@ -133,6 +145,62 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
     for (int i = 1; i < Q; ++i) f[i] = P2::load_f(pin, pull2_index(i, p, N), N, a.inv_sf);
   }
 
+  if constexpr (ANCHOR) {
+    // anchors of the tile and a two-node halo into LDS (coordinates wrap
+    // like the pulls; slots beyond a wall stay unused)
+    for (int k = tid; k < AX * AY; k += TX * TY) {
+      int ax = x0 - 2 + k % AX, ay = y0 - 2 + k / AX;
+      if (wrap_coord(ax, g.nx, g.walls & 1) && wrap_coord(ay, g.ny, g.walls & 2)) {
+        float4 q;
+        float2 v;
+        Anchor2::load(pin, (size_t)ay * g.nx + ax, N, q, v);
+        lds.anc[0][k] = q.x;
+        lds.anc[1][k] = q.y;
+        lds.anc[2][k] = q.z;
+        lds.anc[3][k] = q.w;
+        lds.anc[4][k] = v.x;
+        lds.anc[5][k] = v.y;
+      }
+    }
+    __syncthreads();
+    // value = reference of the writing node + stored deviation; the writer
+    // of direction i is x - c_i, or the node itself (direction opp(i))
+    // behind a wall
+    auto rebuild = [&](int i, int cx0, int cy0, const Pull2& pp, R& fv, R* hv, bool with_h) {
+      const int cx = Lat<2>::cx(i), cy = Lat<2>::cy(i);
+      const bool bounce = (cx > 0 && pp.lo_x) || (cx < 0 && pp.hi_x) ||
+                          (cy > 0 && pp.lo_y) || (cy < 0 && pp.hi_y);
+      const int sx = bounce ? cx0 : cx0 - cx, sy = bounce ? cy0 : cy0 - cy;
+      const int k = (sy - (y0 - 2)) * AX + (sx - (x0 - 2));
+      const R sgn = bounce ? (R)-1 : (R)1;
+      const R ux = lds.anc[4][k], uy = lds.anc[5][k];
+      fv += fref2<R>(i, sgn, (R)lds.anc[3][k], ux, uy);
+      if (with_h) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) hv[c] += href2<R>(i, c, sgn, (R)lds.anc[c][k], ux, uy);
+      }
+    };
+    if (hvalid) {
+      Pull2 ph;
+      make_pull2(hx, hy, g, ph);
+      const int ux0 = x0 - 1 + (hslot % SX), uy0 = y0 - 1 + (hslot / SX);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) rebuild(i, ux0, uy0, ph, fh[i], nullptr, false);
+    }
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        R hv[NC] = {h[0][i], h[1][i], h[2][i]};
+        rebuild(i, x, y, p, f[i], hv, true);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) h[c][i] = hv[c];
+      }
+    } else if (valid) {
+#pragma unroll
+      for (int i = 1; i < Q; ++i) rebuild(i, x, y, p, f[i], nullptr, false);
+    }
+  }
+
   // ---- velocities into LDS
   R u[3] = {0, 0, 0}, F[3] = {0, 0, 0};
   if (valid) {
@@ -160,6 +228,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
 
   // ---- f collision and store (needs A from h, not the gradient)
   R e[NC];
+  R pnew = 0;
   if (active) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -173,7 +242,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
       for (int c = 0; c < NC; ++c)
         e[c] = a.P.eta_over_lam > 0 ? (R)a.clamp[(2 + c) * N + n] / a.P.eta_over_lam : (R)0;
     }
-    collide_f<2, R>(f, e, u, F, a.P);
+    pnew = collide_f<2, R>(f, e, u, F, a.P);
   }
   __syncthreads();
   if (!active) return;
@@ -198,10 +267,35 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
     const R Ac = e[c] + ((c != 1) ? (R)1 : (R)0);
     collide_h<2, R>(h[c], e[c], Ac, chi[c], chip[c], u, up, a.first != 0, a.P);
   }
+  if constexpr (ANCHOR) {
+    // new anchor: E = sum_i h*_i (the rest population closed that sum), the
+    // pressure and the velocity of this step; store the deviations from it
+    R En[NC];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const R hv[NC] = {h[0][i], h[1][i], h[2][i]};
-    P2::store(pout, (size_t)i * N + n, N, a.sf, a.sh, f[i], hv);
+    for (int c = 0; c < NC; ++c) {
+      R sm = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) sm += h[c][i];
+      En[c] = sm;
+    }
+    const float4 q = {(float)En[0], (float)En[1], (float)En[2], (float)pnew};
+    const float2 v = {(float)u[0], (float)u[1]};
+    const R e0 = (R)q.x, e1 = (R)q.y, e2 = (R)q.z, pp = (R)q.w, ux = (R)v.x, uy = (R)v.y;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R fd = f[i] - fref2<R>(i, (R)1, pp, ux, uy);
+      const R hv[NC] = {h[0][i] - href2<R>(i, 0, (R)1, e0, ux, uy),
+                        h[1][i] - href2<R>(i, 1, (R)1, e1, ux, uy),
+                        h[2][i] - href2<R>(i, 2, (R)1, e2, ux, uy)};
+      P2::store(pout, (size_t)i * N + n, N, a.sf, a.sh, fd, hv);
+    }
+    Anchor2::store(pout, n, N, q, v);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R hv[NC] = {h[0][i], h[1][i], h[2][i]};
+      P2::store(pout, (size_t)i * N + n, N, a.sf, a.sh, f[i], hv);
+    }
   }
   Aux<2, R>::store(aux, n, N, chi, u);
 }
@@ -210,7 +304,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
 // production step carries none of it
 template <class S, int TY, bool CLAMP = false>
 __global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx, int nty) {
-  __shared__ Tile2Lds<typename StoreT<S>::R, TY> lds;
+  __shared__ Tile2LdsOf<S, TY> lds;
   (void)nty;
   step2d_tile<S, TY, CLAMP>(a, (blockIdx.x % ntx) * 64, (blockIdx.x / ntx) * TY, lds);
 }
@@ -225,7 +319,7 @@ template <class S, int TY>
 __global__ void __launch_bounds__(64 * TY) batch2d_kernel(const BatchInst<S>* __restrict__ desc,
                                                          const BatchTile* __restrict__ tiles,
                                                          int ntiles, int parity, int first) {
-  __shared__ Tile2Lds<typename StoreT<S>::R, TY> lds;
+  __shared__ Tile2LdsOf<S, TY> lds;
   for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
     const BatchTile e = tiles[k];
     StepArgs<S> a = desc[e.inst].a;

@@ -268,7 +268,7 @@ vflb_status launch_moments(vflb_sim* s, int field, double* out, const Box& box) 
   }
   hipLaunchKernelGGL((moments_kernel<D, S>), dim3(grid_for(box.N)), dim3(256), 0,
                      s->stream, static_cast<const S*>(s->buf[VFLB_BUF_POP0 + s->cur]),
-                     geo_of(s), box,
+                     static_cast<const R*>(s->buf[VFLB_BUF_AUX]), geo_of(s), box,
                      phys_of<R>(s), force_of<R>(s, s->t), isf, ish, field, out);
   HIP_TRY(s, hipGetLastError());
   return VFLB_OK;
@@ -286,6 +286,7 @@ vflb_status launch_reduce(vflb_sim* s, double* dev_res) {
   double* part = reinterpret_cast<double*>(static_cast<char*>(s->buf[VFLB_BUF_WORK]) + s->off_part);
   hipLaunchKernelGGL((reduce_kernel<D, S>), dim3(nb), dim3(256), 0, s->stream,
                      static_cast<const S*>(s->buf[VFLB_BUF_POP0 + s->cur]),
+                     static_cast<const R*>(s->buf[VFLB_BUF_AUX]),
                      static_cast<R*>(s->buf[VFLB_BUF_SNAP]), s->snap_valid ? 1 : 0,
                      geo_of(s), phys_of<R>(s), force_of<R>(s, s->t), isf, ish, part);
   HIP_TRY(s, hipGetLastError());
@@ -430,7 +431,11 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
   const size_t sb = s->store_bytes(), ab = s->arith_bytes();
   const size_t words =
       lattice == VFLB_D2Q9 ? Pops<2, float>::words(N) : Pops<3, float>::words(N);
-  s->bytes[VFLB_BUF_POP0] = s->bytes[VFLB_BUF_POP1] = align256(sb * words);
+  // anchored 16-bit D2Q9 storage keeps an FP32 anchor per node after the
+  // tuples of each population buffer (layout.h)
+  const bool anchored = lattice == VFLB_D2Q9 && (storage == VFLB_F16S || storage == VFLB_BF16S);
+  s->bytes[VFLB_BUF_POP0] = s->bytes[VFLB_BUF_POP1] =
+      align256(anchored ? Anchor2::bytes(N) : sb * words);
   s->bytes[VFLB_BUF_AUX] = align256(ab * (s->NC + s->D) * N);
   s->bytes[VFLB_BUF_SNAP] = align256(ab * (s->NC + s->D) * N);
   s->off_tab = 0;
@@ -496,10 +501,17 @@ vflb_status vflb_set_params(vflb_sim* s, const vflb_params* p) {
   // moderate stretch.  Keep 2^14 * typical magnitude below the FP16 range.
   int ef;
   std::frexp(p->U0, &ef);
-  s->log2_sf = 8 - ef;
+  if (s->D == 2) {
+    // anchored D2Q9 storage holds deviations from a reference: non-
+    // equilibrium parts O(U0 k) and below, scaled into FP16's normal range
+    s->log2_sf = 10 - ef;
+    s->log2_sh = 12;
+  } else {
+    s->log2_sf = 8 - ef;
+    s->log2_sh = 6;
+  }
   if (s->log2_sf < 0) s->log2_sf = 0;
   if (s->log2_sf > 24) s->log2_sf = 24;
-  s->log2_sh = 6;
   drop_graphs(s);
   return VFLB_OK;
 }

@@ -126,13 +126,7 @@ def test_fp32_parity_four_roll_64(V, storage, tol):
     compare(o, g, tol, fields=("u", "tau", "Ae"))
 
 
-@pytest.mark.parametrize("storage,tol", [
-    ("f32", 1e-5),
-    pytest.param("f16s", 1e-3, marks=pytest.mark.xfail(
-        reason="shifted FP16 storage random-walks the conserved A: 1.1e-3 after 300 steps",
-        strict=False)),
-    pytest.param("bf16s", 1e-3, marks=pytest.mark.xfail(
-        reason="shifted BF16 storage (8-bit mantissa): ~1e-2 after 300 steps", strict=False))])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16s", 1e-3), ("bf16s", 1e-3)])
 def test_reduced_storage_smooth_state(V, storage, tol):
     o, g = setup_pair(V, 2, (37, 70), storage, (0, 1, 0), "const", init="smooth", seed=9,
                       L=37.0, Wi=0.5)
