@@ -5,19 +5,20 @@
 // (2k): lane s sees pair k with velocity (1 - 2s) c_{2k-1}.  The pair's
 // partial moments meet through one DPP lane swap each, so a lane keeps ten
 // populations of f and h (about 70 values) and two workgroups per CU stay
-// resident (two wavefronts per SIMD), one computing while the other waits
-// on HBM.  In HBM the two members of a pair sit side
-// by side (tuple_of), so a pair of lanes reads and writes adjacent tuples.
+// resident (two wavefronts per SIMD).  Each direction has its own plane in
+// HBM (one plane per direction); lane s of a pair addresses the pair's
+// plane base with the 32-bit offset s N + source node.
 //
 // A workgroup of TY wavefronts owns a 32 x TY column of nodes and walks a
 // chunk of ZC planes in z.  The velocity of three consecutive planes
 // (z-1, z, z+1) plus a one-node ring in x and y lives in LDS, so the
-// same-time gradient needs no halo in z.  Per plane the workgroup pulls the
-// moving f of plane z+1 (own nodes and the x/y ring) to form u(z+1); a lane
-// keeps the f it pulled for its own node and collides it one plane later,
-// so f crosses HBM once and h is pulled once, straight into registers.
-// Loads and stores address a uniform per-pair plane base with a 32-bit
-// offset.
+// same-time gradient needs no halo in z.  The walk is software-pipelined:
+// while plane z collides, the pulled h tuples, rest f and previous-step
+// source state of plane z+1 travel by LDS-DMA (global_load_lds) into an LDS
+// stage, and the moving f of plane z+2 (own column and ring, for u(z+2))
+// into registers.  A lane keeps the f it pulled for its own node and
+// collides it two planes later, so f crosses HBM once and h once.
+// Blocks are renumbered so that each XCD walks one contiguous run of tiles.
 #pragma once
 
 #include "kernels.h"
@@ -81,9 +82,10 @@ template <class S> struct Pair3 {
     h[0] = C::in(a.x, ish); h[1] = C::in(a.y, ish); h[2] = C::in(a.z, ish);
     h[3] = C::in(a.w, ish); h[4] = C::in(b.x, ish); h[5] = C::in(b.y, ish);
   }
-  __device__ static void store(S* p, int k, uint32_t o, size_t N, R sf, R sh, R f, const R* h) {
-    const v4 a = {C::out(h[0], sh), C::out(h[1], sh), C::out(h[2], sh), C::out(h[3], sh)};
-    const v2 b = {C::out(h[4], sh), C::out(h[5], sh)};
+  __device__ static void store(S* p, int k, uint32_t o, size_t N, R sf, R sh, R f, R hxx, R hyy,
+                               R hzz, R hxy, R hxz, R hyz) {
+    const v4 a = {C::out(hxx, sh), C::out(hyy, sh), C::out(hzz, sh), C::out(hxy, sh)};
+    const v2 b = {C::out(hxz, sh), C::out(hyz, sh)};
     __builtin_nontemporal_store(
         C::out(f, sf),
         reinterpret_cast<V*>(const_cast<char*>(fb(p, k, N)) + o * (uint32_t)sizeof(V)));
@@ -168,15 +170,143 @@ __device__ inline void for_pairs(F&& fn) {
   }
 }
 
-template <class S, int TY, int ZC, bool WALLS>
+// Workgroup barrier for the velocity ring in LDS: this wave's LDS accesses
+// complete, then all waves meet.  Unlike a fenced barrier it leaves global
+// loads, stores and LDS-DMA loads in flight (the LDS-DMA slots are private
+// to their lane and waited for explicitly).  The memory clobber keeps the
+// compiler from moving memory accesses across it.
+__device__ inline void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// s_waitcnt immediates (gfx9 family): vmcnt in bits 3:0 and 15:14, expcnt
+// in 6:4, lgkmcnt in 11:8; a field at its maximum does not wait.
+constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
+constexpr int waitcnt_lgkm(int n) { return 15 | (3 << 14) | (7 << 4) | (n << 8); }
+static_assert(waitcnt_vm(32) == 0x8F70 && waitcnt_vm(0) == 0x0F70 && waitcnt_lgkm(0) == 0xC07F,
+              "s_waitcnt encoding");
+
+// LDS-DMA (global_load_lds): each lane of a wave writes the bytes it loads
+// to a lane-contiguous slot of the wave's LDS block, at base + lane * bytes.
+template <int BYTES>
+__device__ inline void dma_to_lds(const void* src, void* wave_block) {
+  static_assert(BYTES == 4 || BYTES == 16, "LDS-DMA of 4 or 16 bytes per lane");
+  if constexpr (BYTES == 16)
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)wave_block, 16,
+                                     0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)wave_block, 4,
+                                     0, 0);
+}
+
+// One plane of a workgroup's pulled state, staged in LDS by LDS-DMA loads
+// issued one plane ahead of their use: per wave and pair the lane slots of
+// the h tuples, the rest f and the previous-step source state.  A lane reads
+// back only what it loaded itself.
+template <class S, int TY> struct Stage3 {
+  // 16-bit storage: (xx, yy) and (zz, xy) as the two 4-byte halves of the
+  // 8-byte 4-tuple, (xz, yz) as one 4-byte 2-tuple; the rest f as the
+  // aligned 4-byte word that holds it
+  uint32_t h4[2][TY][10][64];
+  uint32_t h2[TY][10][64];
+  uint32_t f0[TY][64];
+  float aux[9][TY][64];
+};
+template <int TY> struct Stage3<float, TY> {
+  float4 h4[TY][10][64];
+  float h2[2][TY][10][64];
+  float f0[TY][64];
+  float aux[9][TY][64];
+};
+template <int TY> struct Stage3<double, TY> {};  // FP64 loads straight to registers
+
+template <class S, int TY, bool WALLS>
+__device__ inline void stage_issue(Stage3<S, TY>& st, const S* pin, const typename StoreT<S>::R* aux,
+                                   const PairPull& pq, int s, size_t N, bool first, int ty) {
+  using PA = Pair3<S>;
+  const uint32_t N32 = (uint32_t)N, n = pq.self;
+  auto issue_h = [&](int k, uint32_t o) {
+    if constexpr (std::is_same<S, float>::value) {
+      const char* a = PA::h4b(pin, k, N) + o * 16u;
+      const char* b = PA::h2b(pin, k, N) + o * 8u;
+      dma_to_lds<16>(a, &st.h4[ty][k][0]);
+      dma_to_lds<4>(b, &st.h2[0][ty][k][0]);
+      dma_to_lds<4>(b + 4, &st.h2[1][ty][k][0]);
+    } else {
+      const char* a = PA::h4b(pin, k, N) + o * 8u;
+      const char* b = PA::h2b(pin, k, N) + o * 4u;
+      dma_to_lds<4>(a, &st.h4[0][ty][k][0]);
+      dma_to_lds<4>(a + 4, &st.h4[1][ty][k][0]);
+      dma_to_lds<4>(b, &st.h2[ty][k][0]);
+    }
+  };
+  issue_h(0, n);  // rest: both lanes, one address
+  for_pairs<1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    issue_h(k, pair_src<k, WALLS>(pq, s, N32));
+  });
+  if constexpr (std::is_same<S, float>::value)
+    dma_to_lds<4>(pin + n, &st.f0[ty][0]);
+  else
+    dma_to_lds<4>(reinterpret_cast<const char*>(pin) + 4 * (size_t)(n >> 1), &st.f0[ty][0]);
+  if (!first) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) dma_to_lds<4>(aux + (size_t)q * N + n, &st.aux[q][ty][0]);
+  }
+}
+
+template <class S, int TY, class R>
+__device__ inline void stage_read_h(const Stage3<S, TY>& st, int k, int ty, int tx, R ish, R* h) {
+  using C = Cvt<S>;
+  using V = typename C::V;
+  if constexpr (std::is_same<S, float>::value) {
+    const float4 a = st.h4[ty][k][tx];
+    h[0] = a.x; h[1] = a.y; h[2] = a.z; h[3] = a.w;
+    h[4] = st.h2[0][ty][k][tx];
+    h[5] = st.h2[1][ty][k][tx];
+  } else {
+    const uint32_t w[3] = {st.h4[0][ty][k][tx], st.h4[1][ty][k][tx], st.h2[ty][k][tx]};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const uint16_t lo = (uint16_t)(w[j] & 0xFFFFu), hi = (uint16_t)(w[j] >> 16);
+      V vl, vh;
+      __builtin_memcpy(&vl, &lo, 2);
+      __builtin_memcpy(&vh, &hi, 2);
+      h[2 * j] = C::in(vl, ish);
+      h[2 * j + 1] = C::in(vh, ish);
+    }
+  }
+}
+
+template <class S, int TY, class R>
+__device__ inline R stage_read_f0(const Stage3<S, TY>& st, uint32_t n, int ty, int tx, R isf) {
+  if constexpr (std::is_same<S, float>::value) {
+    return st.f0[ty][tx];
+  } else {
+    using C = Cvt<S>;
+    using V = typename C::V;
+    const uint32_t w = st.f0[ty][tx];
+    const uint16_t b = (uint16_t)((n & 1u) ? (w >> 16) : (w & 0xFFFFu));
+    V v;
+    __builtin_memcpy(&v, &b, 2);
+    return C::in(v, isf);
+  }
+}
+
+// Tiles are walked by full tiles (FULL: every lane owns a lattice node, so
+// no load or store is lane-conditional) and ragged tiles (the rest) in two
+// launches of the same code; a block whose tile is of the other kind returns.
+template <class S, int TY, int ZC, bool WALLS, bool FULL>
 __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int ntx, int nty) {
   using R = typename StoreT<S>::R;
   using PA = Pair3<S>;
   using L = Lat<3>;
+  constexpr bool kDma = !std::is_same<S, double>::value;
   constexpr int NP = 10, NC = 6, TXN = 32, SX = TXN + 2, SY = TY + 2, NS = SX * SY;
   constexpr int H = 2 * SX + 2 * TY;  // ring nodes
   static_assert(2 * H <= 64 * TY, "ring needs more lanes than the workgroup has");
   __shared__ R ring[3][3][NS];
+  __shared__ Stage3<S, TY> st;
 
   const Geo g = a.g;
   const S* __restrict__ pin = a.pin;
@@ -185,25 +315,36 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
   const size_t N = g.N;
   const uint32_t N32 = (uint32_t)N;  // N <= 2^27 (2^26 in FP64), checked on the host
 
-  const int b = blockIdx.x;
+  // Blocks are dealt to the eight XCDs in turn (block b to XCD b mod 8);
+  // renumbering gives each XCD one contiguous run of tiles, so tiles that
+  // share halo lines run side by side under the same L2.
+  int b = blockIdx.x;
+  {
+    const int G = gridDim.x, q = G >> 3, r = G & 7, xcd = b & 7, j = b >> 3;
+    b = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + j;
+  }
   const int tx_tile = b % ntx, rest = b / ntx;
   const int ty_tile = rest % nty, zc = rest / nty;
   const int x0 = tx_tile * TXN, y0 = ty_tile * TY;
+  if ((x0 + TXN <= g.nx && y0 + TY <= g.ny) != FULL) return;
   const int zs = zc * ZC, ze = min(zs + ZC, g.nz);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
   const int s = tx & 1;
   const R sg = s ? (R)-1 : (R)1;
   const int x = x0 + (tx >> 1), y = y0 + ty;
-  const bool in_xy = x < g.nx && y < g.ny;
+  const bool in_xy = FULL || (x < g.nx && y < g.ny);
   const int oslot = (ty + 1) * SX + (tx >> 1) + 1;
+  auto clampc = [](int c, int n) { return c < 0 ? 0 : (c >= n ? n - 1 : c); };
 
-  // own column (wrapped for lanes past a ragged edge: they supply the slot's
-  // velocity for the true last node's gradient) and, for the first 2H lanes,
-  // one node of the x/y ring
+  // Own column: wrapped for lanes past a ragged edge (they supply the
+  // slot's velocity for the true last node's gradient), clamped where the
+  // wrap would cross a wall (values unused).  Ring node for the first 2H
+  // lanes; other lanes shadow their own column.
   int wx = x, wy = y;
   const bool vxy = wrap_coord(wx, g.nx, g.walls & 1) && wrap_coord(wy, g.ny, g.walls & 2);
+  const int ox = clampc(wx, g.nx), oy = clampc(wy, g.ny);
   bool hxy = false;
-  int hx = 0, hy = 0, hslot = 0;
+  int hx = ox, hy = oy, hslot = 0;
   if (tid < 2 * H) {
     const int r = tid >> 1;
     int sxl, syl;
@@ -215,15 +356,37 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
     hx = x0 - 1 + sxl;
     hy = y0 - 1 + syl;
     hxy = wrap_coord(hx, g.nx, g.walls & 1) && wrap_coord(hy, g.ny, g.walls & 2);
+    hx = clampc(hx, g.nx);
+    hy = clampc(hy, g.ny);
   }
-  R Fown[3];
-  force_at<R>(a.F, wx, wy, g.nx, g.ny, Fown);
+  R Fown[3] = {0, 0, 0}, Fring[3] = {0, 0, 0};
+  force_at<R>(a.F, ox, oy, g.nx, g.ny, Fown);
+  force_at<R>(a.F, hx, hy, g.nx, g.ny, Fring);
 
-  // this lane's moving f streamed into the node of pp (slots 1..9)
-  auto pull_fs = [&](const PairPull& pp, R* f) {
+  // plane index for loads: wrapped, clamped beyond a wall (values unused)
+  auto load_z = [&](int zp) {
+    int zw = zp;
+    wrap_coord(zw, g.nz, g.walls & 4);
+    return clampc(zw, g.nz);
+  };
+  auto plane_ok = [&](int zp) {
+    int zw = zp;
+    return wrap_coord(zw, g.nz, g.walls & 4);
+  };
+  // moving f of plane zp streamed into the own column (fo) and the ring
+  // node (fr), for every lane
+  auto pull_plane = [&](int zp, R* fo, R* fr) {
+    const int zw = load_z(zp);
+    PairPull pp;
+    make_pair_pull(ox, oy, zw, s, g, pp);
     for_pairs<1>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      f[k] = PA::load_f(pin, k, pair_src<k, WALLS>(pp, s, N32), N, a.inv_sf);
+      fo[k] = PA::load_f(pin, k, pair_src<k, WALLS>(pp, s, N32), N, a.inv_sf);
+    });
+    make_pair_pull(hx, hy, zw, s, g, pp);
+    for_pairs<1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      fr[k] = PA::load_f(pin, k, pair_src<k, WALLS>(pp, s, N32), N, a.inv_sf);
     });
   };
   // u = sum c f + F/2: each lane sums its members, the pair adds the halves
@@ -240,64 +403,99 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
 #pragma unroll
     for (int bb = 0; bb < 3; ++bb) u[bb] = pair_sum(sg * m[bb]) + (R)0.5 * F[bb];
   };
-  // velocity of plane zp (unwrapped index) into its ring slots; the lane's
-  // own pulled f are returned in fo for the collision of that plane
-  auto plane_u = [&](int zp, R* fo) {
-    int zw = zp;
-    const bool vz = wrap_coord(zw, g.nz, g.walls & 4);
-    const int rs = ((zp % 3) + 3) % 3;
-    if (vz && vxy) {
-      PairPull pp;
-      make_pair_pull(wx, wy, zw, s, g, pp);
-      pull_fs(pp, fo);
-      R u[3];
-      pair_velocity(fo, Fown, u);
-      if (s == 0) {
-        ring[rs][0][oslot] = u[0];
-        ring[rs][1][oslot] = u[1];
-        ring[rs][2][oslot] = u[2];
-      }
+  auto ring_slot = [](int zp) { return ((zp % 3) + 3) % 3; };
+  // velocity of plane zp from its pulled f into the ring slots
+  // (the sums run for every lane, so that the loaded f are consumed on every
+  // path; only the ring writes are conditional)
+  auto publish_u = [&](int zp, const R* fo, const R* fr) {
+    const bool ok = plane_ok(zp);
+    const int rs = ring_slot(zp);
+    R u[3], v[3];
+    pair_velocity(fo, Fown, u);
+    pair_velocity(fr, Fring, v);
+    if (ok && vxy && s == 0) {
+      ring[rs][0][oslot] = u[0];
+      ring[rs][1][oslot] = u[1];
+      ring[rs][2][oslot] = u[2];
     }
-    if (vz && hxy) {
-      PairPull pp;
-      make_pair_pull(hx, hy, zw, s, g, pp);
-      R fr[NP], F[3], u[3];
-      pull_fs(pp, fr);
-      force_at<R>(a.F, hx, hy, g.nx, g.ny, F);
-      pair_velocity(fr, F, u);
-      if (s == 0) {
-        ring[rs][0][hslot] = u[0];
-        ring[rs][1][hslot] = u[1];
-        ring[rs][2][hslot] = u[2];
-      }
+    if (ok && hxy && s == 0) {
+      ring[rs][0][hslot] = v[0];
+      ring[rs][1][hslot] = v[1];
+      ring[rs][2][hslot] = v[2];
     }
   };
 
-  R fn[NP];  // pulled f of the own node of the next plane
-  {
-    R fd[NP];
-    plane_u(zs - 1, fd);
+  // Software pipeline over the planes of the chunk.  Per plane z: publish
+  // u(z + 1) from the f pulled one plane ago; read the staged h, rest f and
+  // source state of z (landed during the previous plane); start the LDS-DMA
+  // loads of plane z + 1 and the register loads of the moving f of plane
+  // z + 2; collide and store z.  Every load is waited for at the top of the
+  // next plane, a whole collision after its issue.  The own moving f of z
+  // and z + 1 ride in registers.  FP64 (no LDS stage: it would not fit)
+  // loads plane z straight to registers instead.
+  // (the stage of the first plane is requested before the pulls that start
+  // the velocity ring, whose waits then cover it as well)
+  if constexpr (kDma) {
+    PairPull pq;
+    make_pair_pull(ox, oy, zs, s, g, pq);
+    stage_issue<S, TY, WALLS>(st, pin, aux, pq, s, N, a.first != 0, ty);
   }
-  plane_u(zs, fn);
+  R fz[NP], fn[NP], frn[NP];
+  {
+    R fa[NP];
+    pull_plane(zs - 1, fa, frn);
+    publish_u(zs - 1, fa, frn);
+    pull_plane(zs, fz, frn);
+    publish_u(zs, fz, frn);
+  }
+  pull_plane(zs + 1, fn, frn);
 
 #pragma unroll 1
   for (int z = zs; z < ze; ++z) {
-    // ---- pull this plane's populations (moving f carried from the look-ahead)
+    // everything issued during the previous plane has landed: LDS-DMA loads
+    // need not retire in order with other memory operations
+    if constexpr (kDma) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    publish_u(z + 1, fn, frn);
     PairPull pl;
-    make_pair_pull(x, y, z, s, g, pl);
+    make_pair_pull(ox, oy, z, s, g, pl);
     const uint32_t n = pl.self;
     R f[NP], h[NC][NP];
     R chip[NC] = {0, 0, 0, 0, 0, 0}, up[3] = {0, 0, 0};
-    if (in_xy) {
-      // rest population: both lanes read it (one address), the even lane keeps it
-      R f0, h0[NC];
-      f0 = PA::load_f(pin, 0, n, N, a.inv_sf);
-      PA::load_h(pin, 0, n, N, a.inv_sh, h0);
+    if constexpr (kDma) {
+      {
+        R h0[NC];
+        stage_read_h<S, TY>(st, 0, ty, tx, a.inv_sh, h0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) h[c][0] = s ? (R)0 : h0[c];
+      }
+      for_pairs<1>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        R hv[NC];
+        stage_read_h<S, TY>(st, k, ty, tx, a.inv_sh, hv);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) h[c][k] = hv[c];
+      });
+      if (!a.first) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) chip[c] = st.aux[c][ty][tx];
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) up[bb] = st.aux[NC + bb][ty][tx];
+      }
+      f[0] = s ? (R)0 : stage_read_f0<S, TY>(st, n, ty, tx, a.inv_sf);
+      // every stage slot of this lane has been read before it is refilled
+      __builtin_amdgcn_s_waitcnt(waitcnt_lgkm(0));
+      if (z + 1 < ze) {
+        PairPull pq;
+        make_pair_pull(ox, oy, z + 1, s, g, pq);
+        stage_issue<S, TY, WALLS>(st, pin, aux, pq, s, N, a.first != 0, ty);
+      }
+    } else {
+      R h0[NC];
+      const R f0 = PA::load_f(pin, 0, n, N, a.inv_sf);
       f[0] = s ? (R)0 : f0;
+      PA::load_h(pin, 0, n, N, a.inv_sh, h0);
 #pragma unroll
       for (int c = 0; c < NC; ++c) h[c][0] = s ? (R)0 : h0[c];
-#pragma unroll
-      for (int k = 1; k < NP; ++k) f[k] = fn[k];
       for_pairs<1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         R hv[NC];
@@ -307,14 +505,19 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
       });
       if (!a.first) Aux<3, R>::load(aux, n, N, chip, up);
     }
-    // ---- look ahead: u(z + 1)
-    plane_u(z + 1, fn);
-    __syncthreads();
-    if (in_xy) {
+#pragma unroll
+    for (int k = 1; k < NP; ++k) {
+      f[k] = fz[k];
+      fz[k] = fn[k];
+    }
+    pull_plane(z + 2, fn, frn);
+    lds_barrier();  // u(z + 1) published
+
+    {
       // the collision may fuse multiply-adds (this node's own arithmetic
       // only; velocities shared through LDS are formed without contraction)
 #pragma clang fp contract(fast)
-      const int rc = ((z % 3) + 3) % 3, rm = (((z - 1) % 3) + 3) % 3, rp = ((z + 1) % 3 + 3) % 3;
+      const int rc = ring_slot(z), rm = ring_slot(z - 1), rp = ring_slot(z + 1);
       const R u[3] = {ring[rc][0][oslot], ring[rc][1][oslot], ring[rc][2][oslot]};
       const R* F = Fown;
       // moments of the pulled state
@@ -346,7 +549,8 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
       //   f* = (1 - w_f) f + w_f f^eq + f^B_i + F_i, written as
       //   (1 - w_f) f + a0 + f^B_i + a1 cu (3 + 9/2 cu) + a2 cF (1 + 3 cu)
       // with the weight-class constants a0 = w (w_f (3 p - 3/2 u.u) - 3 k_f F.u),
-      // a1 = w w_f, a2 = 3 w k_f (w_f = 1/tau_f; the same sum, reordered)
+      // a1 = w w_f, a2 = 3 w k_f (w_f = 1/tau_f; the same sum, reordered).
+      // Both lanes of the pair carry the rest f and update it alike.
       const R omf = a.P.inv_tau_f, keepf = (R)1 - omf;
       {
         const R feq = (R)(3.0 * (L::w(0) - 1.0)) * p - w0 * (R)1.5 * uu;
@@ -435,27 +639,28 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
         h[c][0] = target - pair_sum(hs);
       }
 
-      // ---- stores
-      if (s == 0) {
-        const R hv[NC] = {h[0][0], h[1][0], h[2][0], h[3][0], h[4][0], h[5][0]};
-        PA::store(pout, 0, n, N, a.sf, a.sh, f[0], hv);
-      }
+      // ---- stores (the even lane holds the rest populations); chi (6
+      // planes) then u (3 planes) split over the pair
+      if (in_xy) {
+        if (s == 0)
+          PA::store(pout, 0, n, N, a.sf, a.sh, f[0], h[0][0], h[1][0], h[2][0], h[3][0], h[4][0],
+                    h[5][0]);
 #pragma unroll
-      for (int k = 1; k < NP; ++k) {
-        const R hv[NC] = {h[0][k], h[1][k], h[2][k], h[3][k], h[4][k], h[5][k]};
-        PA::store(pout, k, (s ? N32 : 0u) + n, N, a.sf, a.sh, f[k], hv);
-      }
-      // chi (6 planes) then u (3 planes): the pair splits the nine stores
-      const R item[9] = {chi[0], chi[1], chi[2], chi[3], chi[4], chi[5], u[0], u[1], u[2]};
+        for (int k = 1; k < NP; ++k)
+          PA::store(pout, k, (s ? N32 : 0u) + n, N, a.sf, a.sh, f[k], h[0][k], h[1][k], h[2][k],
+                    h[3][k], h[4][k], h[5][k]);
+        const R item[9] = {chi[0], chi[1], chi[2], chi[3], chi[4], chi[5], u[0], u[1], u[2]};
 #pragma unroll
-      for (int j = 0; j < 5; ++j) {
-        const int q = 2 * j + s;
-        const R v = s ? item[2 * j + 1 < 9 ? 2 * j + 1 : 8] : item[2 * j];
-        if (q < 9) stream_store(aux + (size_t)q * N + n, v);
+        for (int j = 0; j < 5; ++j) {
+          const int q = 2 * j + s;
+          if (q < 9) stream_store(aux + (size_t)q * N + n, item[q]);
+        }
       }
     }
-    __syncthreads();
+    lds_barrier();  // ring slot of z - 1 free
   }
+  // no LDS-DMA may land after the workgroup has ended
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
 }
 
 }  // namespace vflb

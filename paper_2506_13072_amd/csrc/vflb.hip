@@ -98,6 +98,17 @@ void drop_graphs(vflb_sim* s) {
 }
 
 // D3Q19: 32 x tile_y node columns, tile_y 4 (two workgroups per CU) or 8
+template <class S, int TY, int ZC, bool WALLS>
+void launch_step3d(dim3 grid, hipStream_t st, const StepArgs<S>& a, int ntx, int nty, bool any_full,
+                   bool any_ragged) {
+  if (any_full)
+    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, true>), grid, dim3(64, TY), 0, st, a, ntx,
+                       nty);
+  if (any_ragged)
+    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, false>), grid, dim3(64, TY), 0, st, a,
+                       ntx, nty);
+}
+
 int tile_y_3d(const vflb_sim* s) { return s->tile_y == 8 ? 8 : 4; }
 
 int default_tile_y(const vflb_sim* s) {
@@ -209,16 +220,19 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
     const int ntx = (s->nx + 31) / 32, nty = (s->ny + ty - 1) / ty;
     const int nzc = (s->nz + ZC - 1) / ZC;
     const dim3 grid((unsigned)(ntx * nty * nzc));
+    // full tiles and ragged tiles run as two launches of one kernel
+    const bool any_full = s->nx >= 32 && s->ny >= ty;
+    const bool any_ragged = s->nx % 32 != 0 || s->ny % ty != 0;
     if (ty == 8) {
       if (s->walls)
-        hipLaunchKernelGGL((step3d_kernel<S, 8, ZC, true>), grid, dim3(64, 8), 0, st, a, ntx, nty);
+        launch_step3d<S, 8, ZC, true>(grid, st, a, ntx, nty, any_full, any_ragged);
       else
-        hipLaunchKernelGGL((step3d_kernel<S, 8, ZC, false>), grid, dim3(64, 8), 0, st, a, ntx, nty);
+        launch_step3d<S, 8, ZC, false>(grid, st, a, ntx, nty, any_full, any_ragged);
     } else {
       if (s->walls)
-        hipLaunchKernelGGL((step3d_kernel<S, 4, ZC, true>), grid, dim3(64, 4), 0, st, a, ntx, nty);
+        launch_step3d<S, 4, ZC, true>(grid, st, a, ntx, nty, any_full, any_ragged);
       else
-        hipLaunchKernelGGL((step3d_kernel<S, 4, ZC, false>), grid, dim3(64, 4), 0, st, a, ntx, nty);
+        launch_step3d<S, 4, ZC, false>(grid, st, a, ntx, nty, any_full, any_ragged);
     }
   }
   HIP_TRY(s, hipGetLastError());
