@@ -21,6 +21,7 @@ _SRC = os.path.join(_HERE, "vflb_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FORCE_NONE, FORCE_CONST, FORCE_FOUR_ROLL, FORCE_COS_T = 0, 1, 2, 3
+SCHEME_FLUCTUATING, SCHEME_STRESS_DIVERGENCE = 0, 1
 
 
 def build() -> str:
@@ -63,6 +64,8 @@ def lib():
         L.or_get_state.argtypes = [P, P, P, P, P]
         L.or_set_state.argtypes = [P, P, P, P, P]
         L.or_force_field.argtypes = [P, LG, dp]
+        L.or_set_scheme.argtypes = [P, I]
+        L.or_stress_divergence.argtypes = [P, dp]
         L.or_pinv_matrix.argtypes = [I, dp]
         L.or_polymer_stress.argtypes = [I, D, D, dp, dp]
         L.or_fB.argtypes = [I, D, dp, dp]
@@ -204,6 +207,20 @@ class OracleSim:
         a = np.zeros(3)
         a[:len(amp)] = amp
         lib().or_set_force(self._h, kind, a, omega)
+
+    def set_scheme(self, scheme):
+        """SCHEME_FLUCTUATING (the paper's method, default) or
+        SCHEME_STRESS_DIVERGENCE (the stress divergence as a body force,
+        f^B = 0; the scheme the paper compares against)."""
+        self.scheme = int(scheme)
+        lib().or_set_scheme(self._h, self.scheme)
+
+    def stress_divergence(self):
+        """div tau_p of the current state, [N, d], with the stencil of the
+        stress-divergence scheme."""
+        div = np.zeros((self.N, self.d))
+        lib().or_stress_divergence(self._h, div)
+        return div
 
     def init(self, u=None, tau=None, p=None):
         u = None if u is None else _f64(u, (self.N, self.d))

@@ -323,6 +323,8 @@ typedef struct {
   double *chi_prev;     /* chi(t-1) [N][nc]                      */
   double *u_prev;       /* u(t-1)   [N][d]                       */
   double *u, *A;        /* per-step scratch: u(t), A(t)          */
+  int scheme;           /* OR_SCHEME_* below                     */
+  double *tp;           /* scratch of the stress-divergence scheme: tau_p(t) [N][nc] */
 } osim;
 
 void *or_create(int d, int nx, int ny, int nz) {
@@ -342,6 +344,7 @@ void *or_create(int d, int nx, int ny, int nz) {
   s->u_prev = (double *)calloc(s->N * d, sizeof(double));
   s->u = (double *)calloc(s->N * d, sizeof(double));
   s->A = (double *)calloc(s->N * nc, sizeof(double));
+  s->tp = (double *)calloc(s->N * nc, sizeof(double));
   return s;
 }
 
@@ -349,7 +352,7 @@ void or_destroy(void *p) {
   osim *s = (osim *)p;
   if (!s) return;
   free(s->f); free(s->fp); free(s->h); free(s->hp);
-  free(s->chi_prev); free(s->u_prev); free(s->u); free(s->A);
+  free(s->chi_prev); free(s->u_prev); free(s->u); free(s->A); free(s->tp);
   free(s);
 }
 
@@ -370,6 +373,23 @@ void or_set_force(void *p, int kind, const double *amp, double omega) {
   for (int a = 0; a < 3; ++a) s->famp[a] = amp[a];
   s->omega = omega;
 }
+
+/* The two schemes compared in Sec. 3 (Tables of the Poiseuille and
+ * Taylor-Green performance tests):
+ *   OR_SCHEME_FLUCTUATING: the paper's method, the polymer stress enters
+ *     the f equation through the fluctuation term f^B (Sec. 2.2);
+ *   OR_SCHEME_STRESS_DIVERGENCE: the "original" scheme the paper describes
+ *     in prose (Introduction), the divergence of the polymer stress is a
+ *     body force, F_tot = F + div tau_p, in the Guo forcing, the velocity
+ *     and the pressure, with f^B = 0.  The conformation equation is the
+ *     same in both.  The paper gives no stencil for the divergence: it is
+ *     taken here with second-order central differences of tau_p(t) at the
+ *     same time level, and one-sided second-order differences
+ *     (-3 t_0 + 4 t_1 - t_2)/2 normal to a wall (no wall value of tau_p is
+ *     known). */
+enum { OR_SCHEME_FLUCTUATING = 0, OR_SCHEME_STRESS_DIVERGENCE = 1 };
+
+void or_set_scheme(void *p, int scheme) { ((osim *)p)->scheme = scheme; }
 
 long or_time(void *p) { return ((osim *)p)->t; }
 void or_set_time(void *p, long t) { ((osim *)p)->t = t; }
@@ -473,6 +493,57 @@ static void velocity_gradient(const osim *s, long n, double *G) {
   }
 }
 
+/* tau_p(t) of every node from the current (pre-collision) h. */
+static void stress_field(osim *s) {
+  const lattice *L = &s->L;
+  int q = L->q, nc = L->nc;
+  for (long n = 0; n < s->N; ++n) {
+    double A[6];
+    for (int c = 0; c < nc; ++c) {
+      double sum = 0.0;
+      for (int i = 0; i < q; ++i) sum += s->h[(n * nc + c) * q + i];
+      A[c] = sum;
+    }
+    or_polymer_stress(L->d, s->eta_p, s->lambda, A, &s->tp[n * nc]);
+  }
+}
+
+/* Derivative along axis a of component c of the field s->tp at node n:
+ * central, or one-sided second order next to a wall. */
+static double stress_derivative(const osim *s, long n, int a, int c) {
+  int x[3], nc = s->L.nc;
+  node_xyz(s, n, x);
+  long np = neighbour(s, x, a, +1), nm = neighbour(s, x, a, -1);
+  if (np >= 0 && nm >= 0) return 0.5 * (s->tp[np * nc + c] - s->tp[nm * nc + c]);
+  if (nm < 0 && np >= 0) {
+    int y[3] = {x[0], x[1], x[2]};
+    y[a] += 1;
+    long np2 = neighbour(s, y, a, +1);
+    if (np2 < 0) return s->tp[np * nc + c] - s->tp[n * nc + c];
+    return 0.5 * (-3.0 * s->tp[n * nc + c] + 4.0 * s->tp[np * nc + c] - s->tp[np2 * nc + c]);
+  }
+  if (np < 0 && nm >= 0) {
+    int y[3] = {x[0], x[1], x[2]};
+    y[a] -= 1;
+    long nm2 = neighbour(s, y, a, -1);
+    if (nm2 < 0) return s->tp[n * nc + c] - s->tp[nm * nc + c];
+    return 0.5 * (3.0 * s->tp[n * nc + c] - 4.0 * s->tp[nm * nc + c] + s->tp[nm2 * nc + c]);
+  }
+  return 0.0;
+}
+
+/* (div tau_p)_b = sum_a d_a tau_ab at node n, added to F. */
+static void add_stress_divergence(const osim *s, long n, double *F) {
+  const lattice *L = &s->L;
+  int d = L->d;
+  for (int c = 0; c < L->nc; ++c) {
+    int a = L->comp[c][0], b = L->comp[c][1];
+    F[b] += stress_derivative(s, n, a, c);
+    if (a != b) F[a] += stress_derivative(s, n, b, c);
+  }
+  for (int b = d; b < 3; ++b) F[b] = 0.0;
+}
+
 /* One time step of the method:
  *  (1) per node: A = sum_i h_i (Sec. 2.3), tau_p (Sec. 2.1), f^B (App. A),
  *      F(x, t), u (Sec. 2.2), F_i, p (App. B), f^eq, then the collision of
@@ -491,6 +562,8 @@ static void one_step(osim *s) {
   const lattice *L = &s->L;
   int d = L->d, q = L->q, nc = L->nc;
   double tf = s->tau_f, th = s->tau_h;
+  const int divergence = s->scheme == OR_SCHEME_STRESS_DIVERGENCE;
+  if (divergence) stress_field(s);
 
   for (long n = 0; n < s->N; ++n) {
     int x[3];
@@ -503,8 +576,13 @@ static void one_step(osim *s) {
       A[c] = sum;
     }
     or_polymer_stress(d, s->eta_p, s->lambda, A, tau);
-    or_fB(d, tf, tau, fB);
     body_force(s, x, s->t, F);
+    if (divergence) {
+      for (int i = 0; i < q; ++i) fB[i] = 0.0;
+      add_stress_divergence(s, n, F);
+    } else {
+      or_fB(d, tf, tau, fB);
+    }
     or_velocity(d, f, F, u);
     or_guo(d, tf, F, u, Fi);
     double pr = or_pressure(d, tf, f, u, Fi[0], fB[0]);
@@ -574,6 +652,8 @@ void or_moments(void *p, double *u, double *pr, double *A, double *tau) {
   osim *s = (osim *)p;
   const lattice *L = &s->L;
   int d = L->d, q = L->q, nc = L->nc;
+  const int divergence = s->scheme == OR_SCHEME_STRESS_DIVERGENCE;
+  if (divergence) stress_field(s);
   for (long n = 0; n < s->N; ++n) {
     int x[3];
     node_xyz(s, n, x);
@@ -584,8 +664,13 @@ void or_moments(void *p, double *u, double *pr, double *A, double *tau) {
       An[c] = sum;
     }
     or_polymer_stress(d, s->eta_p, s->lambda, An, tn);
-    or_fB(d, s->tau_f, tn, fB);
     body_force(s, x, s->t, F);
+    if (divergence) {
+      for (int i = 0; i < q; ++i) fB[i] = 0.0;
+      add_stress_divergence(s, n, F);
+    } else {
+      or_fB(d, s->tau_f, tn, fB);
+    }
     or_velocity(d, &s->f[n * q], F, un);
     or_guo(d, s->tau_f, F, un, Fi);
     if (u) for (int a = 0; a < d; ++a) u[n * d + a] = un[a];
@@ -627,5 +712,18 @@ void or_force_field(void *p, long t, double *F) {
     node_xyz(s, n, x);
     body_force(s, x, t, Fn);
     for (int a = 0; a < d; ++a) F[n * d + a] = Fn[a];
+  }
+}
+
+/* div tau_p of the current state at every node, [N][d], with the stencil
+ * of the stress-divergence scheme. */
+void or_stress_divergence(void *p, double *div) {
+  osim *s = (osim *)p;
+  int d = s->L.d;
+  stress_field(s);
+  for (long n = 0; n < s->N; ++n) {
+    double F[3] = {0, 0, 0};
+    add_stress_divergence(s, n, F);
+    for (int a = 0; a < d; ++a) div[n * d + a] = F[a];
   }
 }
