@@ -45,10 +45,16 @@ def bytes_per_lup(d, storage):
     return 2 * q * (1 + nc) * sb + 2 * (nc + d) * ab + anchor
 
 
-def run_gpu(steps, warmup, storage="f32", tile=0):
+# stress-divergence scheme: per step one extra pass pulls the 9 (f, h)
+# tuples of every node (144 B) and writes tau_p (12 B), one reads tau_p
+# (12 B) and writes div tau_p (8 B), and the step reads div tau_p (8 B)
+STRESS_DIV_EXTRA_BYTES = 144 + 12 + 12 + 8 + 8
+
+
+def run_gpu(steps, warmup, storage="f32", tile=0, scheme="fluctuating"):
     import torch
     from paper_2506_13072_amd import vflb
-    g = vflb.Sim(2, NX, NY, 1, storage)
+    g = vflb.Sim(2, NX, NY, 1, storage, scheme=scheme)
     g.set_params(RE, WI, BETA, U0, L)
     g.set_boundaries((vflb.PERIODIC, vflb.WALLS))
     if tile:
@@ -92,7 +98,8 @@ def run_gpu(steps, warmup, storage="f32", tile=0):
     total_ms = e0.elapsed_time(e1)
     step_ms = (total_ms - red_ms) / steps
     return dict(total_ms=total_ms, step_ms=step_ms, red_ms=red_ms, wall=wall,
-                R=r["R"], nonfinite=r["nonfinite"])
+                R=r["R"], nonfinite=r["nonfinite"],
+                buffer_bytes=sum(int(b.numel()) for b in g.buffers))
 
 
 def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0):
@@ -305,7 +312,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy kernel (counter calibration)")
     ap.add_argument("--workload", default="channel",
-                    choices=["channel", "tgv", "ensemble", "warmstart"],
+                    choices=["channel", "tgv", "ensemble", "warmstart", "schemes"],
                     help="channel: the 8192x1024 D2Q9 headline; tgv: 512^3 D3Q19 "
                          "Taylor-Green vortex; ensemble: 256 four-roll lattices of "
                          "sides 64..512 as one batch (both reported, not the headline)")
@@ -329,6 +336,40 @@ def main():
                           "warm_over_cold": round(r["warm_steps"] / r["cold_steps"], 3),
                           "detail": {k: (round(v, 6) if isinstance(v, float) else v)
                                      for k, v in r.items()}}), flush=True)
+        return
+    if args.workload == "schemes":
+        # the paper's comparison (Sec. 3, performance tables): its method
+        # against the stress-divergence scheme on the same channel
+        nodes = NX * NY
+        rows = {}
+        for scheme in ("fluctuating", "stress_divergence"):
+            r = run_gpu(args.steps, args.warmup, args.storage, args.tile, scheme)
+            bpl = bytes_per_lup(2, args.storage) + (
+                STRESS_DIV_EXTRA_BYTES * (2 if args.storage == "f64" else 1)
+                if scheme == "stress_divergence" else 0)
+            rows[scheme] = dict(MLUPS=round(nodes * args.steps / (r["total_ms"] / 1e3) / 1e6, 1),
+                                ms_per_step=round(r["total_ms"] / args.steps, 4),
+                                bytes_per_lup=bpl,
+                                achieved_GBps=round(bpl * nodes / (r["step_ms"] / 1e3) / 1e9, 1),
+                                buffer_bytes=r["buffer_bytes"])
+        fl, sd = rows["fluctuating"], rows["stress_divergence"]
+        ach = sd["achieved_GBps"]
+        print(json.dumps({"metric": "MLUPS (stress-divergence scheme, D2Q9 channel)",
+                          "value": sd["MLUPS"], "unit": "MLUPS", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": sd["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
+                          "config": {"workload": "Poiseuille channel D2Q9 8192x1024, both schemes",
+                                     "storage": args.storage, "nodes": nodes},
+                          "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                       "traffic": None, "bytes_per_lup": sd["bytes_per_lup"]},
+                          "schemes": rows,
+                          "time_ratio_fluctuating_over_divergence":
+                              round(fl["ms_per_step"] / sd["ms_per_step"], 4),
+                          "memory_ratio_fluctuating_over_divergence":
+                              round(fl["buffer_bytes"] / sd["buffer_bytes"], 4)}), flush=True)
         return
     if args.workload == "ensemble":
         r = run_gpu_ensemble(args.instances, args.steps, args.warmup, args.storage)

@@ -94,6 +94,23 @@ enum {
  * parabola through the wall value 0 and the first two nodes. */
 enum { VFLB_PERIODIC = 0, VFLB_WALLS = 1 };
 
+/* How the polymer stress enters the velocity populations:
+ *   FLUCTUATING        the paper's method: the fluctuation term f^B of the
+ *                      pseudo-inverse closed forms (Sec. 2.2, App. A);
+ *   STRESS_DIVERGENCE  the scheme the paper measures its method against
+ *                      (Sec. 3, performance tables of the Poiseuille and
+ *                      Taylor-Green tests; described in words in the
+ *                      Introduction): no f^B, and div tau_p(t) added to the
+ *                      body force in the forcing term, the velocity moment
+ *                      and the pressure.  Its stencil is not given in the
+ *                      paper; here second-order central differences of
+ *                      tau_p(t), one-sided second order (-3 t0 + 4 t1 -
+ *                      t2)/2 normal to a wall.  D2Q9 with FP32 or FP64
+ *                      storage; tau_p and div tau_p occupy 5 more words per
+ *                      node of the AUX buffer.
+ * The conformation equation (Sec. 2.3) is the same in both. */
+enum { VFLB_SCHEME_FLUCTUATING = 0, VFLB_SCHEME_STRESS_DIVERGENCE = 1 };
+
 /* Device buffers of one simulation (sizes from vflb_query_buffers).  Their
  * internal layout is private to the library (it differs between lattices
  * and storages); read fields through vflb_read and move whole states through
@@ -147,6 +164,12 @@ typedef struct {
  * or size. */
 vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
                         void *hip_stream, vflb_sim **out);
+
+/* vflb_create with the scheme (VFLB_SCHEME_*; vflb_create is
+ * VFLB_SCHEME_FLUCTUATING).  EINVAL for an unknown scheme, or for
+ * STRESS_DIVERGENCE on D3Q19 or with 16-bit storage. */
+vflb_status vflb_create_scheme(int lattice, int nx, int ny, int nz, int storage, int scheme,
+                               void *hip_stream, vflb_sim **out);
 
 /* Sizes in bytes of the VFLB_NBUF device buffers. */
 vflb_status vflb_query_buffers(const vflb_sim *sim, size_t bytes[VFLB_NBUF]);

@@ -30,6 +30,7 @@ template <class R> struct ForceArgs {
   R F0[3];        // uniform force (CONST, COS_T at this time level)
   R amp[2];       // FOUR_ROLL amplitudes
   const R* tab;   // FOUR_ROLL tables: sin(kx x)[nx], cos(kx x)[nx], sin(ky y)[ny], cos(ky y)[ny]
+  const R* div;   // D2Q9 stress-divergence scheme: div tau_p [2][nx ny] added to F; else null
 };
 
 template <class S> struct StepArgs {
@@ -110,6 +111,11 @@ __device__ inline void force_at(const ForceArgs<R>& fa, int x, int y, int nx,
     F[0] = fa.amp[0] * sx[x] * cy[y];
     F[1] = fa.amp[1] * cx[x] * sy[y];
   }
+  if (fa.div) {
+    const size_t n = (size_t)y * nx + x, M = (size_t)nx * ny;
+    F[0] += fa.div[n];
+    F[1] += fa.div[M + n];
+  }
 }
 
 // Wrap a coordinate that may lie outside [0, n) by at most one tile: for a
@@ -183,7 +189,7 @@ __device__ inline void node_moments(const S* pin, const typename StoreT<S>::R* a
     m.tau[c] = P.eta_over_lam * s;
   }
   R fB[Q];
-  fluct_term<R>(m.tau, P.inv_tau_f, fB, (L*)nullptr);
+  fluct_term<R>(m.tau, P.inv_tau_f * P.fluct, fB, (L*)nullptr);
   R uu = 0, Fu = 0, sum = 0;
 #pragma unroll
   for (int b = 0; b < D; ++b) {
@@ -514,6 +520,68 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchInst<S>* _
 
 // plain streaming copy: one 16-byte vector per lane, non-temporal
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+// ------------------------------------------------ stress-divergence scheme
+// The scheme the paper compares its method against (Sec. 3, performance
+// tables; described in words in the Introduction): the divergence of the
+// polymer stress enters the f equation as a body force, F_tot = F +
+// div tau_p, and f^B is absent.  Per step: tau_p(t) of every node from its
+// pulled h (taup_kernel), then div tau_p by second-order central
+// differences, one-sided second order normal to a wall (stress_div_kernel);
+// the step kernels add it to F wherever they evaluate the force.  D2Q9.
+
+template <class S>
+__global__ void __launch_bounds__(256) taup_kernel(const S* __restrict__ pin, Geo g,
+                                                   typename StoreT<S>::R eta_over_lam,
+                                                   typename StoreT<S>::R* __restrict__ taup) {
+  using R = typename StoreT<S>::R;
+  const size_t N = g.N;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
+    R e[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      R f, hv[3];
+      Pops<2, S>::load(pin, pull_index<2>(i, x, y, 0, g), N, (R)1, (R)1, f, hv);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) e[c] += hv[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) taup[(size_t)c * N + n] = eta_over_lam * e[c];
+  }
+}
+
+// derivative along axis a (0: x, 1: y) of the plane t at node (x, y)
+template <class R>
+__device__ inline R stress_derivative(const R* t, int x, int y, int a, const Geo& g) {
+  const int n = a == 0 ? g.nx : g.ny, c = a == 0 ? x : y;
+  auto at = [&](int k) { return a == 0 ? t[(size_t)y * g.nx + k] : t[(size_t)k * g.nx + x]; };
+  if (!(g.walls & (1 << a))) {
+    const int cm = c == 0 ? n - 1 : c - 1, cp = c == n - 1 ? 0 : c + 1;
+    return (R)0.5 * (at(cp) - at(cm));
+  }
+  if (c > 0 && c < n - 1) return (R)0.5 * (at(c + 1) - at(c - 1));
+  if (n == 1) return (R)0;
+  if (n == 2) return at(1) - at(0);
+  if (c == 0) return (R)0.5 * ((R)-3 * at(0) + (R)4 * at(1) - at(2));
+  return (R)0.5 * ((R)3 * at(n - 1) - (R)4 * at(n - 2) + at(n - 3));
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) stress_div_kernel(const R* __restrict__ taup, Geo g,
+                                                         R* __restrict__ div) {
+  const size_t N = g.N;
+  const R* txx = taup;
+  const R* txy = taup + N;
+  const R* tyy = taup + 2 * N;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
+    div[n] = stress_derivative(txx, x, y, 0, g) + stress_derivative(txy, x, y, 1, g);
+    div[N + n] = stress_derivative(txy, x, y, 0, g) + stress_derivative(tyy, x, y, 1, g);
+  }
+}
+
 __global__ void __launch_bounds__(256) stream_copy_kernel(const v4u32* __restrict__ src,
                                                           v4u32* __restrict__ dst,
                                                           size_t n) {

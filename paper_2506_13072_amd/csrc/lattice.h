@@ -143,6 +143,8 @@ template <class R> struct Phys {
   R tau_f, inv_tau_f, k_f;       // k_f = 1 - 1/(2 tau_f)
   R inv_tau_h, k_h3;             // k_h3 = 3 (1 - 1/(2 tau_h))
   R inv_lam, eta_over_lam;
+  R fluct;  // 1: the fluctuation term f^B enters the f collision; 0: it does not
+            // (the stress-divergence scheme carries the stress as a force)
 };
 
 // ----------------------------------------------------- per-node arithmetic
@@ -200,7 +202,7 @@ __device__ inline R collide_f(R* f, const R* e, const R* u, const R* F,
 #pragma unroll
   for (int c = 0; c < NC; ++c) tau[c] = P.eta_over_lam * e[c];
   R fB[Q];
-  fluct_term<R>(tau, P.inv_tau_f, fB, (L*)nullptr);
+  fluct_term<R>(tau, P.inv_tau_f * P.fluct, fB, (L*)nullptr);
   R uu = u[0] * u[0] + u[1] * u[1];
   R Fu = F[0] * u[0] + F[1] * u[1];
   if (D == 3) {

@@ -59,6 +59,7 @@ struct vflb_sim {
   bool is_view = false;  // an instance of a batch: buffers and stepping belong to the batch
   const float* clamp = nullptr;  // settling targets while vflb::internal::sim_settle runs
   int clamp_flags = 0;
+  int scheme = VFLB_SCHEME_FLUCTUATING;
   std::string err;
 
   size_t store_bytes() const {
@@ -129,6 +130,7 @@ Phys<R> phys_of(const vflb_sim* s) {
   P.k_h3 = (R)(3.0 * (1.0 - 0.5 / l.tau_h));
   P.inv_lam = (R)(1.0 / l.lambda);
   P.eta_over_lam = (R)(l.eta_p / l.lambda);
+  P.fluct = s->scheme == VFLB_SCHEME_FLUCTUATING ? (R)1 : (R)0;
   return P;
 }
 
@@ -140,6 +142,10 @@ ForceArgs<R> force_of(const vflb_sim* s, int64_t t) {
   fa.amp[0] = (R)s->famp[0];
   fa.amp[1] = (R)s->famp[1];
   fa.tab = reinterpret_cast<const R*>(static_cast<char*>(s->buf[VFLB_BUF_WORK]) + s->off_tab);
+  // stress-divergence scheme: div tau_p [2][N] after chi, u, tau_p in AUX
+  fa.div = s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE
+               ? static_cast<const R*>(s->buf[VFLB_BUF_AUX]) + (size_t)(5 + 3) * s->N
+               : nullptr;
   if (s->fkind == VFLB_FORCE_CONST) {
     for (int a = 0; a < s->D; ++a) fa.F0[a] = (R)s->famp[a];
   } else if (s->fkind == VFLB_FORCE_COS_T) {
@@ -187,8 +193,34 @@ StepArgs<S> make_step_args(const vflb_sim* s, int64_t t, int parity) {
   return a;
 }
 
+// stress-divergence scheme: tau_p and div tau_p of the populations in the
+// buffer of parity `parity` (the state the next kernels read)
+template <class S>
+vflb_status launch_divergence(vflb_sim* s, hipStream_t st, int parity) {
+  using R = typename StoreT<S>::R;
+  if constexpr (StoreT<S>::kAnchored) {
+    return fail(s, VFLB_EINVAL, "the stress-divergence scheme needs FP32 or FP64 storage");
+  } else {
+    const S* pin = static_cast<const S*>(s->buf[VFLB_BUF_POP0 + parity]);
+    R* taup = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + (size_t)5 * s->N;
+    R* div = taup + (size_t)3 * s->N;
+    const int g = grid1d(s, 256);
+    hipLaunchKernelGGL((taup_kernel<S>), dim3(g), dim3(256), 0, st, pin, geo_of(s),
+                       (R)(s->lp.eta_p / s->lp.lambda), taup);
+    hipLaunchKernelGGL((stress_div_kernel<R>), dim3(g), dim3(256), 0, st, taup, geo_of(s), div);
+    HIP_TRY(s, hipGetLastError());
+    return VFLB_OK;
+  }
+}
+
 template <int D, class S>
 vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
+  if constexpr (D == 2) {
+    if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
+      vflb_status rc = launch_divergence<S>(s, st, parity);
+      if (rc != VFLB_OK) return rc;
+    }
+  }
   StepArgs<S> a = make_step_args<S>(s, t, parity);
   if (D == 2) {
     a.clamp = s->clamp;
@@ -275,6 +307,12 @@ int grid_for(size_t n) {
 template <int D, class S>
 vflb_status launch_moments(vflb_sim* s, int field, double* out, const Box& box) {
   using R = typename StoreT<S>::R;
+  if constexpr (D == 2) {  // the force of the current state includes div tau_p(t)
+    if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
+      vflb_status rc = launch_divergence<S>(s, s->stream, s->cur);
+      if (rc != VFLB_OK) return rc;
+    }
+  }
   R isf = (R)1, ish = (R)1;
   if (s->storage == VFLB_F16S) {
     isf = (R)std::ldexp(1.0, -s->log2_sf);
@@ -291,6 +329,12 @@ vflb_status launch_moments(vflb_sim* s, int field, double* out, const Box& box) 
 template <int D, class S>
 vflb_status launch_reduce(vflb_sim* s, double* dev_res) {
   using R = typename StoreT<S>::R;
+  if constexpr (D == 2) {
+    if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
+      vflb_status rc = launch_divergence<S>(s, s->stream, s->cur);
+      if (rc != VFLB_OK) return rc;
+    }
+  }
   R isf = (R)1, ish = (R)1;
   if (s->storage == VFLB_F16S) {
     isf = (R)std::ldexp(1.0, -s->log2_sf);
@@ -413,7 +457,7 @@ namespace {
 // A lattice and the sizes of its buffers.  A view (an instance of a batch)
 // has no capture stream: it is stepped by its batch.
 vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_t stream,
-                    bool view, vflb_sim** out) {
+                    bool view, vflb_sim** out, int scheme = VFLB_SCHEME_FLUCTUATING) {
   if (!out) return fail(nullptr, VFLB_EINVAL, "out is NULL");
   *out = nullptr;
   if (lattice != VFLB_D2Q9 && lattice != VFLB_D3Q19)
@@ -431,7 +475,14 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
   if (lattice == VFLB_D3Q19 && N > ((size_t)1 << d3_log2_max))
     return fail(nullptr, VFLB_EINVAL, "D3Q19 lattice of %zu nodes exceeds 2^%d for this storage",
                 N, d3_log2_max);
+  if (scheme != VFLB_SCHEME_FLUCTUATING && scheme != VFLB_SCHEME_STRESS_DIVERGENCE)
+    return fail(nullptr, VFLB_EINVAL, "unknown scheme %d", scheme);
+  if (scheme == VFLB_SCHEME_STRESS_DIVERGENCE &&
+      (lattice != VFLB_D2Q9 || (storage != VFLB_F32 && storage != VFLB_F64)))
+    return fail(nullptr, VFLB_EINVAL,
+                "the stress-divergence scheme runs on D2Q9 with FP32 or FP64 storage");
   vflb_sim* s = new vflb_sim();
+  s->scheme = scheme;
   s->D = lattice;
   s->Q = lattice == VFLB_D2Q9 ? 9 : 19;
   s->NC = lattice == VFLB_D2Q9 ? 3 : 6;
@@ -450,7 +501,10 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
   const bool anchored = lattice == VFLB_D2Q9 && (storage == VFLB_F16S || storage == VFLB_BF16S);
   s->bytes[VFLB_BUF_POP0] = s->bytes[VFLB_BUF_POP1] =
       align256(anchored ? Anchor2::bytes(N) : sb * words);
-  s->bytes[VFLB_BUF_AUX] = align256(ab * (s->NC + s->D) * N);
+  // AUX: chi(t-1), u(t-1); the stress-divergence scheme adds tau_p [3][N]
+  // and div tau_p [2][N]
+  s->bytes[VFLB_BUF_AUX] =
+      align256(ab * ((s->NC + s->D) + (scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? 5 : 0)) * N);
   s->bytes[VFLB_BUF_SNAP] = align256(ab * (s->NC + s->D) * N);
   s->off_tab = 0;
   s->off_part = align256(ab * 2 * ((size_t)nx + ny));
@@ -470,6 +524,12 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
 vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
                         void* hip_stream, vflb_sim** out) {
   return sim_new(lattice, nx, ny, nz, storage, static_cast<hipStream_t>(hip_stream), false, out);
+}
+
+vflb_status vflb_create_scheme(int lattice, int nx, int ny, int nz, int storage, int scheme,
+                               void* hip_stream, vflb_sim** out) {
+  return sim_new(lattice, nx, ny, nz, storage, static_cast<hipStream_t>(hip_stream), false, out,
+                 scheme);
 }
 
 vflb_status vflb_query_buffers(const vflb_sim* s, size_t bytes[VFLB_NBUF]) {

@@ -24,6 +24,8 @@ F64, F32, F16S, BF16S = 0, 1, 2, 3
 STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S}
 FORCE_NONE, FORCE_CONST, FORCE_FOUR_ROLL, FORCE_COS_T = 0, 1, 2, 3
 PERIODIC, WALLS = 0, 1
+SCHEME_FLUCTUATING, SCHEME_STRESS_DIVERGENCE = 0, 1
+SCHEMES = {"fluctuating": SCHEME_FLUCTUATING, "stress_divergence": SCHEME_STRESS_DIVERGENCE}
 (FIELD_U, FIELD_P, FIELD_RHO, FIELD_A, FIELD_TAU, FIELD_F, FIELD_H,
  FIELD_CHI_PREV, FIELD_U_PREV) = range(9)
 NBUF = 5
@@ -72,6 +74,7 @@ def lib():
         P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         I64, SZ = ctypes.c_int64, ctypes.c_size_t
         L.vflb_create.argtypes = [I, I, I, I, I, P, ctypes.POINTER(P)]
+        L.vflb_create_scheme.argtypes = [I, I, I, I, I, I, P, ctypes.POINTER(P)]
         L.vflb_query_buffers.argtypes = [P, ctypes.POINTER(SZ)]
         L.vflb_bind_buffers.argtypes = [P, ctypes.POINTER(P)]
         L.vflb_set_params.argtypes = [P, ctypes.POINTER(Params)]
@@ -146,7 +149,7 @@ def lib():
             getattr(L, name).restype = I
         L.vflb_last_error.argtypes = [P]
         L.vflb_last_error.restype = ctypes.c_char_p
-        for name in ("vflb_create", "vflb_query_buffers", "vflb_bind_buffers",
+        for name in ("vflb_create", "vflb_create_scheme", "vflb_query_buffers", "vflb_bind_buffers",
                      "vflb_set_params", "vflb_get_lattice_params", "vflb_set_force",
                      "vflb_set_boundaries", "vflb_set_storage_scale", "vflb_init_fields",
                      "vflb_step", "vflb_reduce", "vflb_read", "vflb_state_size",
@@ -185,14 +188,16 @@ def stream_copy(src, dst, stream):
 
 
 class Sim:
-    """One lattice: ``Sim(lattice, nx, ny, nz, storage)``.
+    """One lattice: ``Sim(lattice, nx, ny, nz, storage, scheme=...)``.
 
     ``stream`` is a ``torch.cuda.Stream`` (a default-priority side stream is
     created when omitted); the library enqueues every kernel on it.
+    ``scheme`` is "fluctuating" (the paper's method, default) or
+    "stress_divergence" (the comparison scheme, D2Q9 FP32/FP64).
     """
 
     def __init__(self, lattice, nx, ny, nz=1, storage="f32", device="cuda:0",
-                 stream=None, _handle=None):
+                 stream=None, _handle=None, scheme="fluctuating"):
         import torch
         self.torch = torch
         self.D = 2 if lattice in (2, "d2q9", "D2Q9") else 3
@@ -208,10 +213,12 @@ class Sim:
             self._h = None
             self._view = ctypes.c_void_p(_handle)
             return
+        self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         h = ctypes.c_void_p()
-        _check(None, lib().vflb_create(self.D, self.nx, self.ny, self.nz, self.storage,
-                                       ctypes.c_void_p(self.stream.cuda_stream),
-                                       ctypes.byref(h)))
+        _check(None, lib().vflb_create_scheme(self.D, self.nx, self.ny, self.nz, self.storage,
+                                              self.scheme,
+                                              ctypes.c_void_p(self.stream.cuda_stream),
+                                              ctypes.byref(h)))
         self._h = h
         sizes = (ctypes.c_size_t * NBUF)()
         _check(self._h, lib().vflb_query_buffers(self._h, sizes))
