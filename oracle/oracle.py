@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 FORCE_NONE, FORCE_CONST, FORCE_FOUR_ROLL, FORCE_COS_T = 0, 1, 2, 3
 SCHEME_FLUCTUATING, SCHEME_STRESS_DIVERGENCE = 0, 1
+MODEL_OLDROYD_B, MODEL_GIESEKUS, MODEL_LPTT, MODEL_EPTT = 0, 1, 2, 3
 
 
 def build() -> str:
@@ -77,6 +78,8 @@ def lib():
         L.or_heq.argtypes = [I, D, dp, dp]
         L.or_chi_i.argtypes = [I, D, D, dp, dp]
         L.or_chi_tensor.argtypes = [I, D, dp, dp, dp]
+        L.or_chi_tensor_model.argtypes = [I, D, I, D, dp, dp, dp]
+        L.or_set_model.argtypes = [P, I, D]
         L.or_lattice_params.argtypes = [D, D, D, D, D, D, dp]
         _lib = L
     return _lib
@@ -148,9 +151,14 @@ def chi_i(d, tau_h, chi, u):
     return out
 
 
-def chi_tensor(d, lam, A, G):
+def chi_tensor(d, lam, A, G, model=None, param=0.0):
+    """Source tensor chi (components as A) for the symmetric A and the full
+    gradient G[a*d+b] = d_a u_b; model None is Oldroyd-B, else MODEL_*."""
     out = np.zeros(NC(d))
-    lib().or_chi_tensor(d, lam, _f64(A), _f64(G), out)
+    if model is None:
+        lib().or_chi_tensor(d, lam, _f64(A), _f64(G), out)
+    else:
+        lib().or_chi_tensor_model(d, lam, int(model), float(param), _f64(A), _f64(G), out)
     return out
 
 
@@ -207,6 +215,11 @@ class OracleSim:
         a = np.zeros(3)
         a[:len(amp)] = amp
         lib().or_set_force(self._h, kind, a, omega)
+
+    def set_model(self, model, param=0.0):
+        """Constitutive model MODEL_* (Oldroyd-B default) with its parameter
+        (Giesekus mobility alpha, PTT eps)."""
+        lib().or_set_model(self._h, int(model), float(param))
 
     def set_scheme(self, scheme):
         """SCHEME_FLUCTUATING (the paper's method, default) or

@@ -265,25 +265,51 @@ void or_chi_i(int d, double tau_h, double chi, const double *u, double *chii) {
               (1.0 + (1.0 - 1.0 / (2.0 * tau_h)) * cdot(&L, i, u) / CS2);
 }
 
-/* Oldroyd-B source tensor (Sec. 2.3):
- * chi = -(A - I)/lambda + A . grad(u) + grad(u)^T . A,
+/* Source tensor of the conformation equation (Sec. 2.3):
+ * chi = -R(E)/lambda + A . grad(u) + grad(u)^T . A,  E = A - I,
  * with (grad u)_ab = d_a u_b, the convention under which the constitutive
- * equation of Sec. 2.1 is the upper-convected derivative.  G is the full
- * d x d gradient, G[a*d+b] = d_a u_b. */
-void or_chi_tensor(int d, double lambda, const double *A, const double *G,
-                   double *chi) {
+ * equation of Sec. 2.1 is the upper-convected derivative.  R(E) = E is the
+ * Oldroyd-B model of the paper.  The paper names the Giesekus and
+ * Phan-Thien-Tanner models as the next constitutive models for the method
+ * (Introduction, Conclusion); in conformation form their relaxation terms
+ * are (standard forms; the polymer stress stays tau_p = (eta_p/lambda) E):
+ *   Giesekus, mobility alpha:        R(E) = E + alpha E.E
+ *   linear PTT, parameter eps:        R(E) = (1 + eps tr E) E
+ *   exponential PTT, parameter eps:   R(E) = exp(eps tr E) E
+ * G is the full d x d gradient, G[a*d+b] = d_a u_b. */
+enum { OR_MODEL_OLDROYD_B = 0, OR_MODEL_GIESEKUS = 1, OR_MODEL_LPTT = 2, OR_MODEL_EPTT = 3 };
+
+void or_chi_tensor_model(int d, double lambda, int model, double param, const double *A,
+                         const double *G, double *chi) {
   lattice L = lat_of(d);
-  double At[3][3], Gt[3][3];
+  double At[3][3], Gt[3][3], E[3][3];
   sym_to_full(&L, A, At);
   memset(Gt, 0, sizeof Gt);
   for (int a = 0; a < d; ++a)
     for (int b = 0; b < d; ++b) Gt[a][b] = G[a * d + b];
+  double trE = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) E[a][b] = At[a][b] - (a == b && a < d ? 1.0 : 0.0);
+  for (int a = 0; a < d; ++a) trE += E[a][a];
+  double scale = 1.0;
+  if (model == OR_MODEL_LPTT) scale = 1.0 + param * trE;
+  if (model == OR_MODEL_EPTT) scale = exp(param * trE);
   for (int c = 0; c < L.nc; ++c) {
     int a = L.comp[c][0], b = L.comp[c][1];
-    double s = -(At[a][b] - (a == b ? 1.0 : 0.0)) / lambda;
+    double relax = scale * E[a][b];
+    if (model == OR_MODEL_GIESEKUS) {
+      double ee = 0.0;
+      for (int g = 0; g < d; ++g) ee += E[a][g] * E[g][b];
+      relax += param * ee;
+    }
+    double s = -relax / lambda;
     for (int g = 0; g < d; ++g) s += At[a][g] * Gt[g][b] + Gt[g][a] * At[g][b];
     chi[c] = s;
   }
+}
+
+void or_chi_tensor(int d, double lambda, const double *A, const double *G, double *chi) {
+  or_chi_tensor_model(d, lambda, OR_MODEL_OLDROYD_B, 0.0, A, G, chi);
 }
 
 /* Map the dimensionless groups of Sec. 3 to lattice units (dx = dt = 1):
@@ -324,6 +350,8 @@ typedef struct {
   double *u_prev;       /* u(t-1)   [N][d]                       */
   double *u, *A;        /* per-step scratch: u(t), A(t)          */
   int scheme;           /* OR_SCHEME_* below                     */
+  int model;            /* OR_MODEL_*: constitutive model        */
+  double mparam;        /* its parameter (alpha or eps)          */
   double *tp;           /* scratch of the stress-divergence scheme: tau_p(t) [N][nc] */
 } osim;
 
@@ -390,6 +418,12 @@ void or_set_force(void *p, int kind, const double *amp, double omega) {
 enum { OR_SCHEME_FLUCTUATING = 0, OR_SCHEME_STRESS_DIVERGENCE = 1 };
 
 void or_set_scheme(void *p, int scheme) { ((osim *)p)->scheme = scheme; }
+
+void or_set_model(void *p, int model, double param) {
+  osim *s = (osim *)p;
+  s->model = model;
+  s->mparam = param;
+}
 
 long or_time(void *p) { return ((osim *)p)->t; }
 void or_set_time(void *p, long t) { ((osim *)p)->t = t; }
@@ -596,7 +630,7 @@ static void one_step(osim *s) {
   for (long n = 0; n < s->N; ++n) {
     double G[9], chi[6], un[3] = {0, 0, 0}, up[3] = {0, 0, 0};
     velocity_gradient(s, n, G);
-    or_chi_tensor(d, s->lambda, &s->A[n * nc], G, chi);
+    or_chi_tensor_model(d, s->lambda, s->model, s->mparam, &s->A[n * nc], G, chi);
     for (int a = 0; a < d; ++a) {
       un[a] = s->u[n * d + a];
       up[a] = s->u_prev[n * d + a];
