@@ -111,6 +111,23 @@ enum { VFLB_PERIODIC = 0, VFLB_WALLS = 1 };
  * The conformation equation (Sec. 2.3) is the same in both. */
 enum { VFLB_SCHEME_FLUCTUATING = 0, VFLB_SCHEME_STRESS_DIVERGENCE = 1 };
 
+/* Constitutive model of the polymer: the relaxation term R(E), E = A - I,
+ * of the conformation equation chi = -R(E)/lambda + A.grad u + grad u^T.A
+ * (Sec. 2.1, 2.3; the paper's method is built on Oldroyd-B and names the
+ * Giesekus and Phan-Thien-Tanner models as the next ones):
+ *   OLDROYD_B  R = E                               (default; param ignored)
+ *   GIESEKUS   R = E + alpha E.E,  alpha = param in [0, 1/2]
+ *   LPTT       R = (1 + eps tr E) E,   eps = param >= 0
+ *   EPTT       R = exp(eps tr E) E,    eps = param >= 0
+ * The polymer stress stays tau_p = (eta_p/lambda) E, so f^B and the
+ * stress-divergence force are unchanged. */
+enum {
+  VFLB_MODEL_OLDROYD_B = 0,
+  VFLB_MODEL_GIESEKUS = 1,
+  VFLB_MODEL_LPTT = 2,
+  VFLB_MODEL_EPTT = 3
+};
+
 /* Device buffers of one simulation (sizes from vflb_query_buffers).  Their
  * internal layout is private to the library (it differs between lattices
  * and storages); read fields through vflb_read and move whole states through
@@ -170,6 +187,10 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
  * STRESS_DIVERGENCE on D3Q19 or with 16-bit storage. */
 vflb_status vflb_create_scheme(int lattice, int nx, int ny, int nz, int storage, int scheme,
                                void *hip_stream, vflb_sim **out);
+
+/* Constitutive model (VFLB_MODEL_*) and its parameter; takes effect from the
+ * next step.  EINVAL for an unknown model or a parameter out of range. */
+vflb_status vflb_set_model(vflb_sim *sim, int model, double param);
 
 /* Sizes in bytes of the VFLB_NBUF device buffers. */
 vflb_status vflb_query_buffers(const vflb_sim *sim, size_t bytes[VFLB_NBUF]);

@@ -145,7 +145,15 @@ template <class R> struct Phys {
   R inv_lam, eta_over_lam;
   R fluct;  // 1: the fluctuation term f^B enters the f collision; 0: it does not
             // (the stress-divergence scheme carries the stress as a force)
+  int model;  // constitutive model (MODEL_* below) and its parameter
+  R mparam;
 };
+
+// Constitutive models: the relaxation term R(E) of the conformation
+// equation, E = A - I (Oldroyd-B of the paper: R = E; the Giesekus and
+// Phan-Thien-Tanner models the paper names as next: R = E + alpha E.E,
+// (1 + eps tr E) E, exp(eps tr E) E).
+enum { MODEL_OLDROYD_B = 0, MODEL_GIESEKUS = 1, MODEL_LPTT = 2, MODEL_EPTT = 3 };
 
 // ----------------------------------------------------- per-node arithmetic
 // Polymer-stress fluctuation term from the pseudo-inverse closed forms
@@ -250,7 +258,7 @@ __device__ inline R collide_f(R* f, const R* e, const R* u, const R* F,
 // Oldroyd-B source tensor chi = -(A - I)/lambda + A.G + G^T.A with
 // G[a][b] = d_a u_b (upper-convected form of the constitutive equation).
 template <int D, class R>
-__device__ inline void source_tensor(const R* e, const R (*G)[3], R inv_lam,
+__device__ inline void source_tensor(const R* e, const R (*G)[3], const Phys<R>& P,
                                      R* chi) {
   using L = Lat<D>;
   R A[3][3];
@@ -261,10 +269,33 @@ __device__ inline void source_tensor(const R* e, const R (*G)[3], R inv_lam,
     A[a][b] = v;
     A[b][a] = v;
   }
+  // relaxation term R(E) of the constitutive model
+  R rel[L::NC];
+#pragma unroll
+  for (int c = 0; c < L::NC; ++c) rel[c] = e[c];
+  if (P.model == MODEL_GIESEKUS) {
+#pragma unroll
+    for (int c = 0; c < L::NC; ++c) {
+      const int a = L::ca(c), b = L::cb(c);
+      R ee = 0;
+#pragma unroll
+      for (int g = 0; g < D; ++g)
+        ee += (A[a][g] - (a == g ? (R)1 : (R)0)) * (A[g][b] - (g == b ? (R)1 : (R)0));
+      rel[c] = e[c] + P.mparam * ee;
+    }
+  } else if (P.model == MODEL_LPTT || P.model == MODEL_EPTT) {
+    R tr = 0;
+#pragma unroll
+    for (int c = 0; c < L::NC; ++c)
+      if (L::ca(c) == L::cb(c)) tr += e[c];
+    const R f = P.model == MODEL_LPTT ? (R)1 + P.mparam * tr : exp(P.mparam * tr);
+#pragma unroll
+    for (int c = 0; c < L::NC; ++c) rel[c] = f * e[c];
+  }
 #pragma unroll
   for (int c = 0; c < L::NC; ++c) {
     const int a = L::ca(c), b = L::cb(c);
-    R s = -e[c] * inv_lam;
+    R s = -rel[c] * P.inv_lam;
 #pragma unroll
     for (int g = 0; g < D; ++g) s += A[a][g] * G[g][b] + G[g][a] * A[g][b];
     chi[c] = s;

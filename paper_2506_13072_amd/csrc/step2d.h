@@ -261,7 +261,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
                      : (R)0.5 * (ub[SX] - ub[-SX]);
   }
   R chi[NC];
-  source_tensor<2, R>(e, G, a.P.inv_lam, chi);
+  source_tensor<2, R>(e, G, a.P, chi);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const R Ac = e[c] + ((c != 1) ? (R)1 : (R)0);

@@ -605,7 +605,7 @@ __global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int n
         }
       }
       R chi[NC];
-      source_tensor<3, R>(e, G, a.P.inv_lam, chi);
+      source_tensor<3, R>(e, G, a.P, chi);
 
       // ---- h collision (Sec. 2.3); the rest population closes
       // sum_i h*_i = A - I + chi + (chi - chi(t-1))/2.  Per direction

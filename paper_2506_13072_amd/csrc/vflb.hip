@@ -60,6 +60,8 @@ struct vflb_sim {
   const float* clamp = nullptr;  // settling targets while vflb::internal::sim_settle runs
   int clamp_flags = 0;
   int scheme = VFLB_SCHEME_FLUCTUATING;
+  int model = VFLB_MODEL_OLDROYD_B;
+  double mparam = 0.0;
   std::string err;
 
   size_t store_bytes() const {
@@ -131,6 +133,8 @@ Phys<R> phys_of(const vflb_sim* s) {
   P.inv_lam = (R)(1.0 / l.lambda);
   P.eta_over_lam = (R)(l.eta_p / l.lambda);
   P.fluct = s->scheme == VFLB_SCHEME_FLUCTUATING ? (R)1 : (R)0;
+  P.model = s->model;
+  P.mparam = (R)s->mparam;
   return P;
 }
 
@@ -647,6 +651,21 @@ vflb_status vflb_set_boundaries(vflb_sim* s, const int kind_per_axis[3]) {
     }
   }
   s->walls = w;
+  drop_graphs(s);
+  return VFLB_OK;
+}
+
+vflb_status vflb_set_model(vflb_sim* s, int model, double param) {
+  if (!s) return VFLB_EINVAL;
+  if (model != VFLB_MODEL_OLDROYD_B && model != VFLB_MODEL_GIESEKUS && model != VFLB_MODEL_LPTT &&
+      model != VFLB_MODEL_EPTT)
+    return fail(s, VFLB_EINVAL, "unknown constitutive model %d", model);
+  if (!std::isfinite(param) || param < 0)
+    return fail(s, VFLB_EINVAL, "the model parameter must be finite and non-negative");
+  if (model == VFLB_MODEL_GIESEKUS && param > 0.5)
+    return fail(s, VFLB_EINVAL, "the Giesekus mobility must lie in [0, 1/2]");
+  s->model = model;
+  s->mparam = model == VFLB_MODEL_OLDROYD_B ? 0.0 : param;
   drop_graphs(s);
   return VFLB_OK;
 }

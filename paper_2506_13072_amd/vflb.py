@@ -26,6 +26,7 @@ FORCE_NONE, FORCE_CONST, FORCE_FOUR_ROLL, FORCE_COS_T = 0, 1, 2, 3
 PERIODIC, WALLS = 0, 1
 SCHEME_FLUCTUATING, SCHEME_STRESS_DIVERGENCE = 0, 1
 SCHEMES = {"fluctuating": SCHEME_FLUCTUATING, "stress_divergence": SCHEME_STRESS_DIVERGENCE}
+MODEL_OLDROYD_B, MODEL_GIESEKUS, MODEL_LPTT, MODEL_EPTT = 0, 1, 2, 3
 (FIELD_U, FIELD_P, FIELD_RHO, FIELD_A, FIELD_TAU, FIELD_F, FIELD_H,
  FIELD_CHI_PREV, FIELD_U_PREV) = range(9)
 NBUF = 5
@@ -75,6 +76,7 @@ def lib():
         I64, SZ = ctypes.c_int64, ctypes.c_size_t
         L.vflb_create.argtypes = [I, I, I, I, I, P, ctypes.POINTER(P)]
         L.vflb_create_scheme.argtypes = [I, I, I, I, I, I, P, ctypes.POINTER(P)]
+        L.vflb_set_model.argtypes = [P, I, ctypes.c_double]
         L.vflb_query_buffers.argtypes = [P, ctypes.POINTER(SZ)]
         L.vflb_bind_buffers.argtypes = [P, ctypes.POINTER(P)]
         L.vflb_set_params.argtypes = [P, ctypes.POINTER(Params)]
@@ -149,7 +151,8 @@ def lib():
             getattr(L, name).restype = I
         L.vflb_last_error.argtypes = [P]
         L.vflb_last_error.restype = ctypes.c_char_p
-        for name in ("vflb_create", "vflb_create_scheme", "vflb_query_buffers", "vflb_bind_buffers",
+        for name in ("vflb_create", "vflb_create_scheme", "vflb_set_model", "vflb_query_buffers",
+                     "vflb_bind_buffers",
                      "vflb_set_params", "vflb_get_lattice_params", "vflb_set_force",
                      "vflb_set_boundaries", "vflb_set_storage_scale", "vflb_init_fields",
                      "vflb_step", "vflb_reduce", "vflb_read", "vflb_state_size",
@@ -256,6 +259,11 @@ class Sim:
         w = list(walls) + [0] * (3 - len(walls))
         k = (ctypes.c_int * 3)(*[int(x) for x in w])
         _check(self.handle, lib().vflb_set_boundaries(self.handle, k))
+
+    def set_model(self, model, param=0.0):
+        """Constitutive model MODEL_* with its parameter (Giesekus alpha,
+        PTT eps); Oldroyd-B by default."""
+        _check(self.handle, lib().vflb_set_model(self.handle, int(model), float(param)))
 
     def set_storage_scale(self, log2_f, log2_h):
         _check(self.handle, lib().vflb_set_storage_scale(self.handle, int(log2_f), int(log2_h)))

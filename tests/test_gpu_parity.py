@@ -31,7 +31,7 @@ FORCES = {"none": 0, "const": 1, "four_roll": 2, "cos_t": 3}
 
 def setup_pair(V, d, shape, storage, walls=(0, 0, 0), force="none", Re=1.0, Wi=1.0,
                beta=0.5, U0=0.01, L=10.0, tau_h=0.501, init=None, seed=0,
-               scheme="fluctuating"):
+               scheme="fluctuating", model=None, mparam=0.0):
     nx, ny = shape[-1], shape[-2]
     nz = shape[0] if d == 3 else 1
     p = O.lattice_params(Re, Wi, beta, U0, L)
@@ -41,6 +41,9 @@ def setup_pair(V, d, shape, storage, walls=(0, 0, 0), force="none", Re=1.0, Wi=1
     o.set_scheme({"fluctuating": O.SCHEME_FLUCTUATING,
                   "stress_divergence": O.SCHEME_STRESS_DIVERGENCE}[scheme])
     g = V.Sim(d, nx, ny, nz, storage, scheme=scheme)
+    if model is not None:
+        o.set_model(model, mparam)
+        g.set_model(model, mparam)
     g.set_params(Re, Wi, beta, U0, L, 0.0, tau_h)
     g.set_boundaries(walls[:d])
     lp = g.lattice_params()
@@ -286,3 +289,66 @@ def test_stress_divergence_rejected_where_not_built(V):
     for args in ((3, 8, 8, 8, "f32"), (2, 8, 8, 1, "f16s"), (2, 8, 8, 1, "bf16s")):
         with pytest.raises(V.VflbError):
             V.Sim(*args, scheme="stress_divergence")
+
+
+# ------------------------------------------------- constitutive models
+# Giesekus and Phan-Thien-Tanner relaxation terms against the oracle's; a
+# stretched smooth start (A - I of order 1/2) makes the nonlinear terms
+# matter.
+MODEL_CASES = [
+    (2, (37, 70), (0, 1, 0), "const", O.MODEL_GIESEKUS, 0.3),
+    (2, (8, 8), (0, 0, 0), "four_roll", O.MODEL_LPTT, 0.25),
+    (2, (8, 8), (1, 1, 0), "const", O.MODEL_EPTT, 0.25),
+    (3, (5, 9, 36), (0, 0, 1), "const", O.MODEL_GIESEKUS, 0.2),
+    (3, (6, 6, 6), (1, 1, 0), "none", O.MODEL_LPTT, 0.1),
+    (3, (40, 6, 70), (0, 1, 0), "four_roll", O.MODEL_EPTT, 0.1),
+]
+
+
+def stretched_pair(V, d, shape, storage, walls, force, model, mparam, scheme="fluctuating"):
+    o, g = setup_pair(V, d, shape, storage, walls, force, model=model, mparam=mparam,
+                      scheme=scheme)
+    p = O.lattice_params(1.0, 1.0, 0.5, 0.01, 10.0)
+    # A - I of order 0.5: tau_p = (eta_p/lambda) (A - I)
+    u, tau, pr = smooth_fields(d, shape, 21, amp_u=0.01, amp_tau=0.5 * p["eta_p"] / p["lam"],
+                               amp_p=1e-4)
+    o.init(u, tau, pr)
+    g.init_fields(u, tau, pr)
+    return o, g
+
+
+@pytest.mark.parametrize("d,shape,walls,force,model,mparam", MODEL_CASES)
+def test_model_fp64_parity_100_steps(V, d, shape, walls, force, model, mparam):
+    o, g = stretched_pair(V, d, shape, "f64", walls, force, model, mparam)
+    o.step(100)
+    g.step(100)
+    compare(o, g, 1e-12)
+
+
+def test_model_fp32_parity(V):
+    o, g = stretched_pair(V, 2, (64, 64), "f32", (0, 1, 0), "const", O.MODEL_GIESEKUS, 0.3)
+    o.step(200)
+    g.step(200)
+    compare(o, g, 1e-5, fields=("u", "tau", "Ae"))
+
+
+def test_model_with_stress_divergence_scheme(V):
+    o, g = stretched_pair(V, 2, (37, 70), "f64", (0, 1, 0), "const", O.MODEL_LPTT, 0.2,
+                          scheme="stress_divergence")
+    o.step(60)
+    g.step(60)
+    compare(o, g, 1e-12)
+
+
+def test_model_changes_the_flow_and_validates(V):
+    res = []
+    for model, mparam in ((None, 0.0), (O.MODEL_GIESEKUS, 0.4)):
+        o, g = stretched_pair(V, 2, (16, 16), "f64", (0, 0, 0), "none", model, mparam)
+        g.step(40)
+        res.append(g.moments()["A"])
+    assert AN.rel_l2(res[1], res[0]) > 1e-6
+    g = V.Sim(2, 8, 8, 1, "f32")
+    for bad in ((7, 0.1), (O.MODEL_GIESEKUS, 0.7), (O.MODEL_LPTT, -1.0),
+                (O.MODEL_EPTT, float("nan"))):
+        with pytest.raises(V.VflbError):
+            g.set_model(*bad)
