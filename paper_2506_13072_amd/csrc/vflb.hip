@@ -251,7 +251,7 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
       }
     }
   } else {
-    constexpr int ZC = 32;
+    constexpr int ZC = kStep3dChunk;
     const int ty = tile_y_3d(s);
     const int ntx = (s->nx + 31) / 32, nty = (s->ny + ty - 1) / ty;
     const int nzc = (s->nz + ZC - 1) / ZC;
