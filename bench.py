@@ -51,10 +51,15 @@ def bytes_per_lup(d, storage):
 STRESS_DIV_EXTRA_BYTES = 144 + 12 + 12 + 8 + 8
 
 
-def run_gpu(steps, warmup, storage="f32", tile=0, scheme="fluctuating"):
+# in-place (AA) streaming: a velocity pass reads the 8 moving f of every
+# node (32 B in FP32) and writes u (8 B); the step reads u (8 B)
+INPLACE_EXTRA_BYTES = 8 * 4 + 8 + 8
+
+
+def run_gpu(steps, warmup, storage="f32", tile=0, scheme="fluctuating", inplace=False):
     import torch
     from paper_2506_13072_amd import vflb
-    g = vflb.Sim(2, NX, NY, 1, storage, scheme=scheme)
+    g = vflb.Sim(2, NX, NY, 1, storage, scheme=scheme, inplace=inplace)
     g.set_params(RE, WI, BETA, U0, L)
     g.set_boundaries((vflb.PERIODIC, vflb.WALLS))
     if tile:
@@ -312,7 +317,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy kernel (counter calibration)")
     ap.add_argument("--workload", default="channel",
-                    choices=["channel", "tgv", "ensemble", "warmstart", "schemes"],
+                    choices=["channel", "tgv", "ensemble", "warmstart", "schemes", "inplace"],
                     help="channel: the 8192x1024 D2Q9 headline; tgv: 512^3 D3Q19 "
                          "Taylor-Green vortex; ensemble: 256 four-roll lattices of "
                          "sides 64..512 as one batch (both reported, not the headline)")
@@ -370,6 +375,39 @@ def main():
                               round(fl["ms_per_step"] / sd["ms_per_step"], 4),
                           "memory_ratio_fluctuating_over_divergence":
                               round(fl["buffer_bytes"] / sd["buffer_bytes"], 4)}), flush=True)
+        return
+    if args.workload == "inplace":
+        # one population buffer (AA streaming) against the two-buffer step
+        nodes = NX * NY
+        rows = {}
+        for name, inplace in (("two_buffers", False), ("in_place", True)):
+            r = run_gpu(args.steps, args.warmup, args.storage, args.tile, inplace=inplace)
+            bpl = bytes_per_lup(2, args.storage) + (
+                INPLACE_EXTRA_BYTES * (2 if args.storage == "f64" else 1) if inplace else 0)
+            rows[name] = dict(MLUPS=round(nodes * args.steps / (r["total_ms"] / 1e3) / 1e6, 1),
+                              ms_per_step=round(r["total_ms"] / args.steps, 4),
+                              bytes_per_lup=bpl,
+                              achieved_GBps=round(bpl * nodes / (r["step_ms"] / 1e3) / 1e9, 1),
+                              buffer_bytes=r["buffer_bytes"])
+        tb, ip = rows["two_buffers"], rows["in_place"]
+        ach = ip["achieved_GBps"]
+        print(json.dumps({"metric": "MLUPS (in-place AA streaming, D2Q9 channel)",
+                          "value": ip["MLUPS"], "unit": "MLUPS", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": ip["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
+                          "config": {"workload": "Poiseuille channel D2Q9 8192x1024, one "
+                                                 "population buffer vs two",
+                                     "storage": args.storage, "nodes": nodes},
+                          "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                       "traffic": None, "bytes_per_lup": ip["bytes_per_lup"]},
+                          "layouts": rows,
+                          "time_ratio_in_place_over_two_buffers":
+                              round(ip["ms_per_step"] / tb["ms_per_step"], 4),
+                          "memory_ratio_in_place_over_two_buffers":
+                              round(ip["buffer_bytes"] / tb["buffer_bytes"], 4)}), flush=True)
         return
     if args.workload == "ensemble":
         r = run_gpu_ensemble(args.instances, args.steps, args.warmup, args.storage)

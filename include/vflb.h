@@ -134,7 +134,7 @@ enum {
  * vflb_save / vflb_load. */
 enum {
   VFLB_BUF_POP0 = 0, /* all populations, ping                              */
-  VFLB_BUF_POP1 = 1, /* all populations, pong                              */
+  VFLB_BUF_POP1 = 1, /* all populations, pong (256 bytes, unused, in place)*/
   VFLB_BUF_AUX = 2,  /* chi(t-1) and u(t-1), arithmetic type               */
   VFLB_BUF_SNAP = 3, /* residual snapshot of u and tau, arithmetic type    */
   VFLB_BUF_WORK = 4, /* force tables, reduction partials                   */
@@ -187,6 +187,26 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
  * STRESS_DIVERGENCE on D3Q19 or with 16-bit storage. */
 vflb_status vflb_create_scheme(int lattice, int nx, int ny, int nz, int storage, int scheme,
                                void *hip_stream, vflb_sim **out);
+
+/* Options of vflb_create_ex.
+ *   VFLB_OPT_INPLACE  one population buffer instead of two (AA streaming):
+ *     a step at even t reads a node's pre-collision populations from its
+ *     own slots and writes the post-collision ones back into them under the
+ *     opposite directions; a step at odd t reads them where their writers
+ *     left them and writes into the slots of the readers of the next step.
+ *     The same-time velocity gradient then needs u of the neighbours before
+ *     they are overwritten: a velocity pass per step writes u(t) (2 more
+ *     words per node of AUX).  Results equal the two-buffer step's bit for
+ *     bit.  D2Q9, FP32 or FP64 storage, single lattices; no settling.  The
+ *     population layout alternates with the parity of t; checkpoints record
+ *     it (vflb_load refuses a checkpoint of the other layout). */
+enum { VFLB_OPT_INPLACE = 1 };
+
+/* vflb_create_scheme with options (VFLB_OPT_* bits; 0 is vflb_create_scheme).
+ * EINVAL for unknown bits or an option on a lattice or storage that does
+ * not support it. */
+vflb_status vflb_create_ex(int lattice, int nx, int ny, int nz, int storage, int scheme,
+                           int options, void *hip_stream, vflb_sim **out);
 
 /* Constitutive model (VFLB_MODEL_*) and its parameter; takes effect from the
  * next step.  EINVAL for an unknown model or a parameter out of range. */

@@ -23,6 +23,14 @@ struct Geo {
   int nx, ny, nz;
   int walls;  // bit a: halfway bounce-back walls on axis a
   size_t N;
+  // how the population buffer holds the state at time t:
+  //   0  two buffers: post-collision values of the last step at their
+  //      writer's node (the reader pulls them);
+  //   1  one buffer, in place (AA), t even: pre-collision values at their
+  //      own node and direction;
+  //   2  one buffer, in place, t odd: post-collision values at their
+  //      writer's node under the opposite direction.
+  int aa;
 };
 
 template <class R> struct ForceArgs {
@@ -79,6 +87,8 @@ __host__ __device__ inline size_t tuple_of(int i, size_t n, size_t N) {
 // bounce-back).  The returned value is a tuple index (tuple_of).
 template <int D>
 __device__ inline size_t pull_index(int i, int x, int y, int z, const Geo& g) {
+  // index of the value that is f_i (or h_i) of node (x, y, z) at time t
+  if (g.aa == 1) return tuple_of<D>(i, node_of(x, y, z, g), g.N);
   int s[3] = {x - cdir<D>(i, 0), y - cdir<D>(i, 1), z - cdir<D>(i, 2)};
   const int n[3] = {g.nx, g.ny, g.nz};
   bool bounce = false;
@@ -91,8 +101,11 @@ __device__ inline size_t pull_index(int i, int x, int y, int z, const Geo& g) {
         s[a] = s[a] < 0 ? n[a] - 1 : 0;
     }
   }
-  if (bounce) return tuple_of<D>(Lat<D>::opp(i), node_of(x, y, z, g), g.N);
-  return tuple_of<D>(i, node_of(s[0], s[1], s[2], g), g.N);
+  // two buffers: the writer x - c_i keeps it under i, or the node itself
+  // under opp(i) behind a wall; in place and t odd the directions swap
+  const int j = g.aa == 2 ? Lat<D>::opp(i) : i;
+  if (bounce) return tuple_of<D>(Lat<D>::opp(j), node_of(x, y, z, g), g.N);
+  return tuple_of<D>(j, node_of(s[0], s[1], s[2], g), g.N);
 }
 
 template <class R>

@@ -309,6 +309,122 @@ __global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx,
   step2d_tile<S, TY, CLAMP>(a, (blockIdx.x % ntx) * 64, (blockIdx.x / ntx) * TY, lds);
 }
 
+// ------------------------------------------- in-place (AA) streaming
+// One population buffer instead of two.  A step at even t reads the
+// pre-collision values of a node from its own slots and writes the
+// post-collision values back into the same node's slots under the opposite
+// directions; a step at odd t reads each value from the slot its writer left
+// it in (x - c_i, opposite direction) and writes the post-collision values
+// into the slots their readers of the next step own (x + c_i, same
+// direction; behind a wall the node itself, opposite direction).  Every slot
+// is read and written by one node within a step, so the buffer needs no
+// copy.  Neighbours' slots are overwritten during the step, so the same-time
+// velocity comes from a separate pass (aa_velocity_kernel) into u [2][N].
+// The arithmetic is step2d_tile's, operation for operation, so a lattice
+// stepped in place takes bitwise the values it takes with two buffers.
+
+// index of the slot that the reader of the next step expects f*_i of
+// node (x, y) in (g.aa: the layout of the state being read, 1 or 2)
+__device__ inline size_t aa_write_index(int i, int x, int y, const Geo& g) {
+  const size_t n = (size_t)y * g.nx + x;
+  const int opp = Lat<2>::opp(i);
+  if (g.aa == 1) return (size_t)opp * g.N + n;  // next state swapped: own node
+  int tx = x + Lat<2>::cx(i), ty = y + Lat<2>::cy(i);
+  if ((g.walls & 1) && (tx < 0 || tx >= g.nx)) return (size_t)opp * g.N + n;
+  if ((g.walls & 2) && (ty < 0 || ty >= g.ny)) return (size_t)opp * g.N + n;
+  tx = tx < 0 ? g.nx - 1 : (tx >= g.nx ? 0 : tx);
+  ty = ty < 0 ? g.ny - 1 : (ty >= g.ny ? 0 : ty);
+  return (size_t)i * g.N + (size_t)ty * g.nx + tx;
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) aa_velocity_kernel(const S* __restrict__ pop, Geo g,
+                                                          ForceArgs<typename StoreT<S>::R> fa,
+                                                          typename StoreT<S>::R inv_sf,
+                                                          typename StoreT<S>::R* __restrict__ U) {
+  using R = typename StoreT<S>::R;
+  const size_t N = g.N;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
+    R f[9], F[3], u[3];
+    f[0] = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) f[i] = Pops<2, S>::load_f(pop, pull_index<2>(i, x, y, 0, g), N, inv_sf);
+    force_at<R>(fa, x, y, g.nx, g.ny, F);
+    velocity2(f, F, u);
+    U[n] = u[0];
+    U[N + n] = u[1];
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) aa_step_kernel(StepArgs<S> a,
+                                                      const typename StoreT<S>::R* __restrict__ U) {
+  using R = typename StoreT<S>::R;
+  constexpr int Q = 9, NC = 3;
+  using P2 = Pops<2, S>;
+  const Geo g = a.g;
+  S* __restrict__ pop = a.pout;
+  R* __restrict__ aux = a.aux;
+  const size_t N = g.N;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
+    Pull2 p;
+    make_pull2(x, y, g, p);
+    R f[Q], h[NC][Q];
+    R chip[NC] = {0, 0, 0}, up[2] = {0, 0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R hv[NC];
+      P2::load(pop, pull_index<2>(i, x, y, 0, g), N, a.inv_sf, a.inv_sh, f[i], hv);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) h[c][i] = hv[c];
+    }
+    if (!a.first) Aux<2, R>::load(aux, n, N, chip, up);
+    R F[3] = {0, 0, 0};
+    force_at<R>(a.F, x, y, g.nx, g.ny, F);
+    const R u[3] = {U[n], U[N + n], (R)0};
+    R e[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      R s = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s += h[c][i];
+      e[c] = s;
+    }
+    collide_f<2, R>(f, e, u, F, a.P);
+    // same-time velocity gradient G[a][b] = d_a u_b (as in step2d_tile)
+    R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const R* Ub = U + (size_t)b * N;
+      const R uxm = Ub[p.row[1] + p.col[0]], uxp = Ub[p.row[1] + p.col[2]];
+      const R uym = Ub[p.row[0] + p.col[1]], uyp = Ub[p.row[2] + p.col[1]];
+      G[0][b] = p.lo_x ? u[b] + uxp * (R)(1.0 / 3.0)
+              : p.hi_x ? -(u[b] + uxm * (R)(1.0 / 3.0))
+                       : (R)0.5 * (uxp - uxm);
+      G[1][b] = p.lo_y ? u[b] + uyp * (R)(1.0 / 3.0)
+              : p.hi_y ? -(u[b] + uym * (R)(1.0 / 3.0))
+                       : (R)0.5 * (uyp - uym);
+    }
+    R chi[NC];
+    source_tensor<2, R>(e, G, a.P, chi);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const R Ac = e[c] + ((c != 1) ? (R)1 : (R)0);
+      collide_h<2, R>(h[c], e[c], Ac, chi[c], chip[c], u, up, a.first != 0, a.P);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R hv[NC] = {h[0][i], h[1][i], h[2][i]};
+      P2::store(pop, aa_write_index(i, x, y, g), N, a.sf, a.sh, f[i], hv);
+    }
+    Aux<2, R>::store(aux, n, N, chi, u);
+  }
+}
+
 // Batched step over many lattices: a persistent launch whose workgroups walk
 // a flattened table of (instance, tile) entries.  desc[inst] holds the
 // instance's step arguments with pin in the buffer of parity 0; for parity 1

@@ -60,6 +60,7 @@ struct vflb_sim {
   const float* clamp = nullptr;  // settling targets while vflb::internal::sim_settle runs
   int clamp_flags = 0;
   int scheme = VFLB_SCHEME_FLUCTUATING;
+  bool inplace = false;  // one population buffer, AA streaming (D2Q9)
   int model = VFLB_MODEL_OLDROYD_B;
   double mparam = 0.0;
   std::string err;
@@ -149,7 +150,7 @@ ForceArgs<R> force_of(const vflb_sim* s, int64_t t) {
   // stress-divergence scheme: div tau_p [2][N] after chi, u, tau_p in AUX
   fa.div = s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE
                ? static_cast<const R*>(s->buf[VFLB_BUF_AUX]) + (size_t)(5 + 3) * s->N
-               : nullptr;
+               : nullptr;  // D2Q9 only: chi, u are 5 words per node
   if (s->fkind == VFLB_FORCE_CONST) {
     for (int a = 0; a < s->D; ++a) fa.F0[a] = (R)s->famp[a];
   } else if (s->fkind == VFLB_FORCE_COS_T) {
@@ -158,14 +159,25 @@ ForceArgs<R> force_of(const vflb_sim* s, int64_t t) {
   return fa;
 }
 
-Geo geo_of(const vflb_sim* s) {
+// geometry of the state at time level t (the in-place layout alternates)
+Geo geo_of(const vflb_sim* s, int64_t t) {
   Geo g;
   g.nx = s->nx;
   g.ny = s->ny;
   g.nz = s->nz;
   g.walls = s->walls;
   g.N = s->N;
+  g.aa = s->inplace ? ((t & 1) ? 2 : 1) : 0;
   return g;
+}
+
+Geo geo_of(const vflb_sim* s) { return geo_of(s, s->t); }
+
+// AUX layout: chi(t-1) [NC][N], u(t-1) [D][N]; stress-divergence scheme:
+// tau_p [3][N], div tau_p [2][N]; in-place streaming: u(t) [2][N]
+size_t aux_taup_words(const vflb_sim* s) { return (size_t)(s->NC + s->D) * s->N; }
+size_t aux_u_words(const vflb_sim* s) {
+  return aux_taup_words(s) + (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? 5 * s->N : 0);
 }
 
 int grid1d(const vflb_sim* s, int block) {
@@ -180,10 +192,11 @@ template <class S>
 StepArgs<S> make_step_args(const vflb_sim* s, int64_t t, int parity) {
   using R = typename StoreT<S>::R;
   StepArgs<S> a;
+  if (s->inplace) parity = 0;  // one buffer, read and written in place
   a.pin = static_cast<const S*>(s->buf[VFLB_BUF_POP0 + parity]);
-  a.pout = static_cast<S*>(s->buf[VFLB_BUF_POP0 + (parity ^ 1)]);
+  a.pout = static_cast<S*>(s->buf[VFLB_BUF_POP0 + (s->inplace ? 0 : parity ^ 1)]);
   a.aux = static_cast<R*>(s->buf[VFLB_BUF_AUX]);
-  a.g = geo_of(s);
+  a.g = geo_of(s, t);
   a.P = phys_of<R>(s);
   a.F = force_of<R>(s, t);
   a.sf = (R)std::ldexp(1.0, s->log2_sf);
@@ -200,18 +213,19 @@ StepArgs<S> make_step_args(const vflb_sim* s, int64_t t, int parity) {
 // stress-divergence scheme: tau_p and div tau_p of the populations in the
 // buffer of parity `parity` (the state the next kernels read)
 template <class S>
-vflb_status launch_divergence(vflb_sim* s, hipStream_t st, int parity) {
+vflb_status launch_divergence(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
   using R = typename StoreT<S>::R;
   if constexpr (StoreT<S>::kAnchored) {
     return fail(s, VFLB_EINVAL, "the stress-divergence scheme needs FP32 or FP64 storage");
   } else {
-    const S* pin = static_cast<const S*>(s->buf[VFLB_BUF_POP0 + parity]);
-    R* taup = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + (size_t)5 * s->N;
+    const S* pin = static_cast<const S*>(s->buf[VFLB_BUF_POP0 + (s->inplace ? 0 : parity)]);
+    R* taup = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + aux_taup_words(s);
     R* div = taup + (size_t)3 * s->N;
     const int g = grid1d(s, 256);
-    hipLaunchKernelGGL((taup_kernel<S>), dim3(g), dim3(256), 0, st, pin, geo_of(s),
+    hipLaunchKernelGGL((taup_kernel<S>), dim3(g), dim3(256), 0, st, pin, geo_of(s, t),
                        (R)(s->lp.eta_p / s->lp.lambda), taup);
-    hipLaunchKernelGGL((stress_div_kernel<R>), dim3(g), dim3(256), 0, st, taup, geo_of(s), div);
+    hipLaunchKernelGGL((stress_div_kernel<R>), dim3(g), dim3(256), 0, st, taup, geo_of(s, t),
+                       div);
     HIP_TRY(s, hipGetLastError());
     return VFLB_OK;
   }
@@ -221,11 +235,23 @@ template <int D, class S>
 vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
   if constexpr (D == 2) {
     if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
-      vflb_status rc = launch_divergence<S>(s, st, parity);
+      vflb_status rc = launch_divergence<S>(s, t, st, parity);
       if (rc != VFLB_OK) return rc;
     }
   }
   StepArgs<S> a = make_step_args<S>(s, t, parity);
+  if constexpr (D == 2 && !StoreT<S>::kAnchored) {
+    if (s->inplace) {  // same-time velocity, then the in-place step
+      using R = typename StoreT<S>::R;
+      R* U = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + aux_u_words(s);
+      const int g = grid1d(s, 256);
+      hipLaunchKernelGGL((aa_velocity_kernel<S>), dim3(g), dim3(256), 0, st, a.pin, a.g, a.F,
+                         a.inv_sf, U);
+      hipLaunchKernelGGL((aa_step_kernel<S>), dim3(g), dim3(256), 0, st, a, (const R*)U);
+      HIP_TRY(s, hipGetLastError());
+      return VFLB_OK;
+    }
+  }
   if (D == 2) {
     a.clamp = s->clamp;
     a.clamp_flags = s->clamp_flags;
@@ -286,7 +312,7 @@ vflb_status launch_init(vflb_sim* s, const T* u, const T* tau, const T* p) {
   }
   hipLaunchKernelGGL((init_kernel<D, S, T>), dim3(grid1d(s, 256)), dim3(256), 0,
                      s->stream, static_cast<S*>(s->buf[VFLB_BUF_POP0]),
-                     static_cast<R*>(s->buf[VFLB_BUF_AUX]), geo_of(s), u, tau, p,
+                     static_cast<R*>(s->buf[VFLB_BUF_AUX]), geo_of(s, 0), u, tau, p,
                      loe, sf, sh);
   HIP_TRY(s, hipGetLastError());
   return VFLB_OK;
@@ -313,7 +339,7 @@ vflb_status launch_moments(vflb_sim* s, int field, double* out, const Box& box) 
   using R = typename StoreT<S>::R;
   if constexpr (D == 2) {  // the force of the current state includes div tau_p(t)
     if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
-      vflb_status rc = launch_divergence<S>(s, s->stream, s->cur);
+      vflb_status rc = launch_divergence<S>(s, s->t, s->stream, s->cur);
       if (rc != VFLB_OK) return rc;
     }
   }
@@ -335,7 +361,7 @@ vflb_status launch_reduce(vflb_sim* s, double* dev_res) {
   using R = typename StoreT<S>::R;
   if constexpr (D == 2) {
     if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
-      vflb_status rc = launch_divergence<S>(s, s->stream, s->cur);
+      vflb_status rc = launch_divergence<S>(s, s->t, s->stream, s->cur);
       if (rc != VFLB_OK) return rc;
     }
   }
@@ -433,8 +459,11 @@ vflb_status need_ready(vflb_sim* s) {
 vflb_status build_graph(vflb_sim* s, int parity) {
   HIP_TRY(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
   vflb_status rc = VFLB_OK;
+  // the steps depend on t only through t == 0, the COS_T force (both
+  // excluded) and, in place, the parity of t, which `parity` then holds
+  const int64_t t0 = s->inplace ? 2 + parity : 1;
   for (int k = 0; k < kGraphSteps && rc == VFLB_OK; ++k)
-    rc = dispatch<StepOp>(s, (int64_t)1 + k, s->cap_stream, parity ^ (k & 1));
+    rc = dispatch<StepOp>(s, t0 + k, s->cap_stream, parity ^ (k & 1));
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
   if (rc != VFLB_OK) {
@@ -461,7 +490,8 @@ namespace {
 // A lattice and the sizes of its buffers.  A view (an instance of a batch)
 // has no capture stream: it is stepped by its batch.
 vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_t stream,
-                    bool view, vflb_sim** out, int scheme = VFLB_SCHEME_FLUCTUATING) {
+                    bool view, vflb_sim** out, int scheme = VFLB_SCHEME_FLUCTUATING,
+                    int options = 0) {
   if (!out) return fail(nullptr, VFLB_EINVAL, "out is NULL");
   *out = nullptr;
   if (lattice != VFLB_D2Q9 && lattice != VFLB_D3Q19)
@@ -485,8 +515,14 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
       (lattice != VFLB_D2Q9 || (storage != VFLB_F32 && storage != VFLB_F64)))
     return fail(nullptr, VFLB_EINVAL,
                 "the stress-divergence scheme runs on D2Q9 with FP32 or FP64 storage");
+  if (options & ~VFLB_OPT_INPLACE) return fail(nullptr, VFLB_EINVAL, "unknown options %#x", options);
+  const bool inplace = (options & VFLB_OPT_INPLACE) != 0;
+  if (inplace && (lattice != VFLB_D2Q9 || (storage != VFLB_F32 && storage != VFLB_F64) || view))
+    return fail(nullptr, VFLB_EINVAL,
+                "in-place streaming runs on single D2Q9 lattices with FP32 or FP64 storage");
   vflb_sim* s = new vflb_sim();
   s->scheme = scheme;
+  s->inplace = inplace;
   s->D = lattice;
   s->Q = lattice == VFLB_D2Q9 ? 9 : 19;
   s->NC = lattice == VFLB_D2Q9 ? 3 : 6;
@@ -505,10 +541,12 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
   const bool anchored = lattice == VFLB_D2Q9 && (storage == VFLB_F16S || storage == VFLB_BF16S);
   s->bytes[VFLB_BUF_POP0] = s->bytes[VFLB_BUF_POP1] =
       align256(anchored ? Anchor2::bytes(N) : sb * words);
+  if (inplace) s->bytes[VFLB_BUF_POP1] = 256;  // unused
   // AUX: chi(t-1), u(t-1); the stress-divergence scheme adds tau_p [3][N]
   // and div tau_p [2][N]
-  s->bytes[VFLB_BUF_AUX] =
-      align256(ab * ((s->NC + s->D) + (scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? 5 : 0)) * N);
+  s->bytes[VFLB_BUF_AUX] = align256(
+      ab * ((s->NC + s->D) + (scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? 5 : 0) + (inplace ? 2 : 0)) *
+      N);
   s->bytes[VFLB_BUF_SNAP] = align256(ab * (s->NC + s->D) * N);
   s->off_tab = 0;
   s->off_part = align256(ab * 2 * ((size_t)nx + ny));
@@ -534,6 +572,12 @@ vflb_status vflb_create_scheme(int lattice, int nx, int ny, int nz, int storage,
                                void* hip_stream, vflb_sim** out) {
   return sim_new(lattice, nx, ny, nz, storage, static_cast<hipStream_t>(hip_stream), false, out,
                  scheme);
+}
+
+vflb_status vflb_create_ex(int lattice, int nx, int ny, int nz, int storage, int scheme,
+                           int options, void* hip_stream, vflb_sim** out) {
+  return sim_new(lattice, nx, ny, nz, storage, static_cast<hipStream_t>(hip_stream), false, out,
+                 scheme, options);
 }
 
 vflb_status vflb_query_buffers(const vflb_sim* s, size_t bytes[VFLB_NBUF]) {
@@ -695,9 +739,9 @@ vflb_status vflb_init_fields(vflb_sim* s, const double* u, const double* tau,
   vflb_status rc = need_ready(s);
   if (rc != VFLB_OK) return rc;
   s->cur = 0;
+  s->t = 0;
   rc = dispatch<InitOp>(s, u, tau, p);
   if (rc != VFLB_OK) return rc;
-  s->t = 0;
   s->inited = true;
   s->snap_valid = false;
   return VFLB_OK;
@@ -712,19 +756,21 @@ vflb_status vflb_step(vflb_sim* s, int64_t nsteps) {
   while (nsteps > 0) {
     const bool graphable = s->t > 0 && s->fkind != VFLB_FORCE_COS_T &&
                            nsteps >= kGraphSteps && s->stream != nullptr;
+    // graphs are kept per parity: of the buffer pair, or in place of t
+    const int par = s->inplace ? (int)(s->t & 1) : s->cur;
     if (graphable) {
-      if (!s->gexec[s->cur]) {
-        rc = build_graph(s, s->cur);
+      if (!s->gexec[par]) {
+        rc = build_graph(s, par);
         if (rc != VFLB_OK) return rc;
       }
-      HIP_TRY(s, hipGraphLaunch(s->gexec[s->cur], s->stream));
+      HIP_TRY(s, hipGraphLaunch(s->gexec[par], s->stream));
       s->t += kGraphSteps;  // even: parity unchanged
       nsteps -= kGraphSteps;
       continue;
     }
     rc = dispatch<StepOp>(s, s->t, s->stream, s->cur);
     if (rc != VFLB_OK) return rc;
-    s->cur ^= 1;
+    if (!s->inplace) s->cur ^= 1;
     s->t += 1;
     nsteps -= 1;
   }
@@ -854,6 +900,7 @@ vflb_status vflb_save(vflb_sim* s, void* blob, size_t n) {
   CkptHeader h{};
   h.magic = kCkptMagic;
   h.D = s->D; h.nx = s->nx; h.ny = s->ny; h.nz = s->nz; h.storage = s->storage;
+  h.pad = s->inplace ? 1 : 0;  // in place the layout follows the parity of t
   h.t = s->t;
   char* b = static_cast<char*>(blob);
   HIP_TRY(s, hipMemcpyAsync(b, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
@@ -878,7 +925,7 @@ vflb_status vflb_load(vflb_sim* s, const void* blob, size_t n) {
   HIP_TRY(s, hipMemcpyAsync(&h, b, sizeof h, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(s, hipStreamSynchronize(s->stream));
   if (h.magic != kCkptMagic || h.D != s->D || h.nx != s->nx || h.ny != s->ny ||
-      h.nz != s->nz || h.storage != s->storage)
+      h.nz != s->nz || h.storage != s->storage || h.pad != (s->inplace ? 1 : 0))
     return fail(s, VFLB_EINVAL, "checkpoint does not match this simulation");
   size_t off = 256;
   HIP_TRY(s, hipMemcpyAsync(s->buf[VFLB_BUF_POP0], b + off, s->bytes[VFLB_BUF_POP0],
@@ -1515,9 +1562,9 @@ vflb_status sim_init_f32(vflb_sim* s, const float* u, const float* tau) {
   vflb_status rc = need_ready(s);
   if (rc != VFLB_OK) return rc;
   s->cur = 0;
+  s->t = 0;
   rc = dispatch<InitOp>(s, u, tau, (const float*)nullptr);
   if (rc != VFLB_OK) return rc;
-  s->t = 0;
   s->inited = true;
   s->snap_valid = false;  // the snapshot buffer held the fields
   return VFLB_OK;
@@ -1528,6 +1575,7 @@ vflb_status sim_settle_f32(vflb_sim* s, const float* targets, int64_t nsteps, in
   if (rc != VFLB_OK) return rc;
   if (!s->inited) return fail(s, VFLB_ESTATE, "initialise the fields first");
   if (s->D != 2) return fail(s, VFLB_EINVAL, "settling is implemented for D2Q9");
+  if (s->inplace) return fail(s, VFLB_EINVAL, "settling needs two population buffers");
   if (flags < 1 || flags > 3) return fail(s, VFLB_EINVAL, "settle flags must be 1, 2 or 3");
   s->clamp = targets;
   s->clamp_flags = flags;

@@ -27,9 +27,11 @@ PERIODIC, WALLS = 0, 1
 SCHEME_FLUCTUATING, SCHEME_STRESS_DIVERGENCE = 0, 1
 SCHEMES = {"fluctuating": SCHEME_FLUCTUATING, "stress_divergence": SCHEME_STRESS_DIVERGENCE}
 MODEL_OLDROYD_B, MODEL_GIESEKUS, MODEL_LPTT, MODEL_EPTT = 0, 1, 2, 3
+OPT_INPLACE = 1
 (FIELD_U, FIELD_P, FIELD_RHO, FIELD_A, FIELD_TAU, FIELD_F, FIELD_H,
  FIELD_CHI_PREV, FIELD_U_PREV) = range(9)
 NBUF = 5
+BUF_POP0, BUF_POP1, BUF_AUX, BUF_SNAP, BUF_WORK = range(NBUF)
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = range(6)
 RUN_ACTIVE, RUN_CONVERGED, RUN_CAPPED, RUN_UNSTABLE, RUN_SKIPPED = range(5)
 SETTLE_U, SETTLE_A = 1, 2
@@ -76,6 +78,7 @@ def lib():
         I64, SZ = ctypes.c_int64, ctypes.c_size_t
         L.vflb_create.argtypes = [I, I, I, I, I, P, ctypes.POINTER(P)]
         L.vflb_create_scheme.argtypes = [I, I, I, I, I, I, P, ctypes.POINTER(P)]
+        L.vflb_create_ex.argtypes = [I, I, I, I, I, I, I, P, ctypes.POINTER(P)]
         L.vflb_set_model.argtypes = [P, I, ctypes.c_double]
         L.vflb_query_buffers.argtypes = [P, ctypes.POINTER(SZ)]
         L.vflb_bind_buffers.argtypes = [P, ctypes.POINTER(P)]
@@ -151,7 +154,8 @@ def lib():
             getattr(L, name).restype = I
         L.vflb_last_error.argtypes = [P]
         L.vflb_last_error.restype = ctypes.c_char_p
-        for name in ("vflb_create", "vflb_create_scheme", "vflb_set_model", "vflb_query_buffers",
+        for name in ("vflb_create", "vflb_create_scheme", "vflb_create_ex", "vflb_set_model",
+                     "vflb_query_buffers",
                      "vflb_bind_buffers",
                      "vflb_set_params", "vflb_get_lattice_params", "vflb_set_force",
                      "vflb_set_boundaries", "vflb_set_storage_scale", "vflb_init_fields",
@@ -196,11 +200,13 @@ class Sim:
     ``stream`` is a ``torch.cuda.Stream`` (a default-priority side stream is
     created when omitted); the library enqueues every kernel on it.
     ``scheme`` is "fluctuating" (the paper's method, default) or
-    "stress_divergence" (the comparison scheme, D2Q9 FP32/FP64).
+    "stress_divergence" (the comparison scheme, D2Q9 FP32/FP64);
+    ``inplace=True`` keeps one population buffer (AA streaming, D2Q9
+    FP32/FP64).
     """
 
     def __init__(self, lattice, nx, ny, nz=1, storage="f32", device="cuda:0",
-                 stream=None, _handle=None, scheme="fluctuating"):
+                 stream=None, _handle=None, scheme="fluctuating", inplace=False):
         import torch
         self.torch = torch
         self.D = 2 if lattice in (2, "d2q9", "D2Q9") else 3
@@ -218,10 +224,11 @@ class Sim:
             return
         self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         h = ctypes.c_void_p()
-        _check(None, lib().vflb_create_scheme(self.D, self.nx, self.ny, self.nz, self.storage,
-                                              self.scheme,
-                                              ctypes.c_void_p(self.stream.cuda_stream),
-                                              ctypes.byref(h)))
+        self.inplace = bool(inplace)
+        _check(None, lib().vflb_create_ex(self.D, self.nx, self.ny, self.nz, self.storage,
+                                          self.scheme, OPT_INPLACE if self.inplace else 0,
+                                          ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(h)))
         self._h = h
         sizes = (ctypes.c_size_t * NBUF)()
         _check(self._h, lib().vflb_query_buffers(self._h, sizes))

@@ -31,7 +31,7 @@ FORCES = {"none": 0, "const": 1, "four_roll": 2, "cos_t": 3}
 
 def setup_pair(V, d, shape, storage, walls=(0, 0, 0), force="none", Re=1.0, Wi=1.0,
                beta=0.5, U0=0.01, L=10.0, tau_h=0.501, init=None, seed=0,
-               scheme="fluctuating", model=None, mparam=0.0):
+               scheme="fluctuating", model=None, mparam=0.0, inplace=False):
     nx, ny = shape[-1], shape[-2]
     nz = shape[0] if d == 3 else 1
     p = O.lattice_params(Re, Wi, beta, U0, L)
@@ -40,7 +40,7 @@ def setup_pair(V, d, shape, storage, walls=(0, 0, 0), force="none", Re=1.0, Wi=1
     o.set_walls(walls)
     o.set_scheme({"fluctuating": O.SCHEME_FLUCTUATING,
                   "stress_divergence": O.SCHEME_STRESS_DIVERGENCE}[scheme])
-    g = V.Sim(d, nx, ny, nz, storage, scheme=scheme)
+    g = V.Sim(d, nx, ny, nz, storage, scheme=scheme, inplace=inplace)
     if model is not None:
         o.set_model(model, mparam)
         g.set_model(model, mparam)
@@ -305,9 +305,10 @@ MODEL_CASES = [
 ]
 
 
-def stretched_pair(V, d, shape, storage, walls, force, model, mparam, scheme="fluctuating"):
+def stretched_pair(V, d, shape, storage, walls, force, model, mparam, scheme="fluctuating",
+                   inplace=False):
     o, g = setup_pair(V, d, shape, storage, walls, force, model=model, mparam=mparam,
-                      scheme=scheme)
+                      scheme=scheme, inplace=inplace)
     p = O.lattice_params(1.0, 1.0, 0.5, 0.01, 10.0)
     # A - I of order 0.5: tau_p = (eta_p/lambda) (A - I)
     u, tau, pr = smooth_fields(d, shape, 21, amp_u=0.01, amp_tau=0.5 * p["eta_p"] / p["lam"],
@@ -352,3 +353,104 @@ def test_model_changes_the_flow_and_validates(V):
                 (O.MODEL_EPTT, float("nan"))):
         with pytest.raises(V.VflbError):
             g.set_model(*bad)
+
+
+# ------------------------------------------------- in-place (AA) streaming
+# One population buffer read and written in place, the layout alternating
+# with the parity of t.  Every node does step2d_tile's arithmetic in the same
+# order, so the state equals the two-buffer state bitwise at every t
+# (pre-collision populations, chi(t-1) and u(t-1)), through graph replays
+# (64 steps) and odd step counts.
+INPLACE_CASES = [
+    ("f32", (8, 8), (0, 0, 0), "four_roll"),
+    ("f32", (37, 70), (0, 1, 0), "const"),
+    ("f32", (37, 70), (1, 1, 0), "const"),
+    ("f64", (37, 70), (0, 1, 0), "cos_t"),
+    ("f64", (5, 3), (1, 0, 0), "const"),
+    ("f64", (2, 2), (1, 1, 0), "none"),
+]
+
+
+def state_of(V, g):
+    return [g.read(k) for k in (V.FIELD_F, V.FIELD_H, V.FIELD_CHI_PREV, V.FIELD_U_PREV)]
+
+
+def assert_same_state(V, a, b, what):
+    for k, (x, y) in enumerate(zip(state_of(V, a), state_of(V, b))):
+        assert np.array_equal(x, y), (what, k, np.abs(x - y).max())
+
+
+@pytest.mark.parametrize("storage,shape,walls,force", INPLACE_CASES)
+def test_inplace_bitwise_equals_two_buffers(V, storage, shape, walls, force):
+    a = setup_pair(V, 2, shape, storage, walls, force, init="smooth", seed=4)[1]
+    b = setup_pair(V, 2, shape, storage, walls, force, init="smooth", seed=4, inplace=True)[1]
+    assert b.inplace and not a.inplace
+    for n in (1, 1, 5, 64, 3, 70):  # t = 1, 2, 7, 71, 74, 144
+        a.step(n)
+        b.step(n)
+        assert a.t == b.t
+        assert_same_state(V, a, b, a.t)
+    ma, mb = a.moments(), b.moments()
+    for k in ma:
+        assert np.array_equal(ma[k], mb[k]), k
+
+
+def test_inplace_fp64_parity_with_the_oracle(V):
+    o, g = setup_pair(V, 2, (37, 70), "f64", (0, 1, 0), "four_roll", init="smooth", seed=3,
+                      inplace=True)
+    o.step(101)
+    g.step(101)
+    compare(o, g, 1e-12)
+    so, sg = o.get_state(), g.state()
+    assert AN.rel_l2(sg["f"], so["f"]) < 1e-12
+    assert AN.rel_l2(sg["h"], so["h"]) < 1e-12
+
+
+def test_inplace_with_stress_divergence_and_models(V):
+    for scheme, model, mparam in (("stress_divergence", None, 0.0),
+                                  ("fluctuating", O.MODEL_GIESEKUS, 0.3),
+                                  ("stress_divergence", O.MODEL_EPTT, 0.2)):
+        a = stretched_pair(V, 2, (37, 70), "f64", (0, 1, 0), "const", model, mparam,
+                           scheme=scheme)[1]
+        b = stretched_pair(V, 2, (37, 70), "f64", (0, 1, 0), "const", model, mparam,
+                           scheme=scheme, inplace=True)[1]
+        a.step(67)
+        b.step(67)
+        assert_same_state(V, a, b, (scheme, model))
+
+
+def test_inplace_reduce_and_checkpoint_at_odd_t(V):
+    a = setup_pair(V, 2, (16, 24), "f32", (0, 1, 0), "cos_t", init="smooth", seed=8)[1]
+    b = setup_pair(V, 2, (16, 24), "f32", (0, 1, 0), "cos_t", init="smooth", seed=8,
+                   inplace=True)[1]
+    a.step(41)
+    b.step(41)
+    assert a.reduce() == b.reduce()
+    blob = b.save()
+    b.step(23)
+    c = setup_pair(V, 2, (16, 24), "f32", (0, 1, 0), "cos_t", init="smooth", seed=1,
+                   inplace=True)[1]
+    c.step(2)
+    c.load(blob)
+    assert c.t == 41
+    c.step(23)
+    a.step(23)
+    assert_same_state(V, b, c, "resumed")
+    assert_same_state(V, a, c, "two buffers")
+    # a checkpoint holds its layout: the other kind of lattice refuses it
+    with pytest.raises(V.VflbError):
+        a.load(blob)
+    with pytest.raises(V.VflbError):
+        c.load(a.save())
+
+
+def test_inplace_keeps_one_population_buffer_and_is_rejected_where_not_built(V):
+    a = V.Sim(2, 64, 32, 1, "f32")
+    b = V.Sim(2, 64, 32, 1, "f32", inplace=True)
+    pa = [x.numel() for x in a.buffers]
+    pb = [x.numel() for x in b.buffers]
+    assert pb[V.BUF_POP1] <= 256 and pb[V.BUF_POP0] == pa[V.BUF_POP0]
+    assert pb[V.BUF_AUX] == pa[V.BUF_AUX] + 2 * 4 * 64 * 32
+    for args in ((3, 8, 8, 8, "f32"), (2, 8, 8, 1, "f16s"), (2, 8, 8, 1, "bf16s")):
+        with pytest.raises(V.VflbError):
+            V.Sim(*args, inplace=True)
