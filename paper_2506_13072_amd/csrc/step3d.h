@@ -301,8 +301,11 @@ __device__ inline R stage_read_f0(const Stage3<S, TY>& st, uint32_t n, int ty, i
 // Tiles are walked by full tiles (FULL: every lane owns a lattice node, so
 // no load or store is lane-conditional) and ragged tiles (the rest) in two
 // launches of the same code; a block whose tile is of the other kind returns.
+// FP64 state does not fit 256 VGPRs: it runs one wave per SIMD, which opens
+// the accumulation registers to the allocator instead of scratch memory.
 template <class S, int TY, int ZC, bool WALLS, bool FULL>
-__global__ void __launch_bounds__(64 * TY, 2) step3d_kernel(StepArgs<S> a, int ntx, int nty) {
+__global__ void __launch_bounds__(64 * TY, sizeof(S) == 8 ? 1 : 2)
+    step3d_kernel(StepArgs<S> a, int ntx, int nty) {
   using R = typename StoreT<S>::R;
   using PA = Pair3<S>;
   using L = Lat<3>;
