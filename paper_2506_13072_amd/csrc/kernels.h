@@ -415,6 +415,7 @@ __device__ inline void reduce_node(const S* pin, const typename StoreT<S>::R* au
   NodeMoments<D, S> m;
   node_moments<D, S>(pin, aux, x, y, z, g, P, fa, inv_sf, inv_sh, m);
   bool finite = true;
+#pragma unroll
   for (int b = 0; b < D; ++b) {
     const double ub = (double)m.u[b];
     finite = finite && isfinite(ub);
@@ -426,6 +427,7 @@ __device__ inline void reduce_node(const S* pin, const typename StoreT<S>::R* au
     snap[(size_t)b * g.N + n] = m.u[b];
   }
   double tr = 0.0;
+#pragma unroll
   for (int c = 0; c < NC; ++c) {
     const double tc = (double)m.tau[c];
     finite = finite && isfinite(tc);
@@ -440,9 +442,11 @@ __device__ inline void reduce_node(const S* pin, const typename StoreT<S>::R* au
     snap[(size_t)(D + c) * g.N + n] = m.tau[c];
   }
   double M = 0.0, Pm[3] = {0, 0, 0};
+#pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double fi = (double)m.f[i];
     M += fi;
+#pragma unroll
     for (int b = 0; b < D; ++b) Pm[b] += cdir<D>(i, b) * fi;
   }
   finite = finite && isfinite(M) && isfinite((double)m.p);

@@ -322,6 +322,8 @@ __global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx,
 // velocity comes from a separate pass (aa_velocity_kernel) into u [2][N].
 // The arithmetic is step2d_tile's, operation for operation, so a lattice
 // stepped in place takes bitwise the values it takes with two buffers.
+// Both kernels give a lane one node: blockIdx.x a run of x, blockIdx.y (and
+// its strides) the rows.
 
 // index of the slot that the reader of the next step expects f*_i of
 // node (x, y) in (g.aa: the layout of the state being read, 1 or 2)
@@ -344,9 +346,10 @@ __global__ void __launch_bounds__(256) aa_velocity_kernel(const S* __restrict__ 
                                                           typename StoreT<S>::R* __restrict__ U) {
   using R = typename StoreT<S>::R;
   const size_t N = g.N;
-  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
-       n += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  for (int y = blockIdx.y; y < g.ny; y += gridDim.y) {
+    const size_t n = (size_t)y * g.nx + x;
     R f[9], F[3], u[3];
     f[0] = 0;
 #pragma unroll
@@ -368,9 +371,10 @@ __global__ void __launch_bounds__(256) aa_step_kernel(StepArgs<S> a,
   S* __restrict__ pop = a.pout;
   R* __restrict__ aux = a.aux;
   const size_t N = g.N;
-  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
-       n += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  for (int y = blockIdx.y; y < g.ny; y += gridDim.y) {
+    const size_t n = (size_t)y * g.nx + x;
     Pull2 p;
     make_pull2(x, y, g, p);
     R f[Q], h[NC][Q];

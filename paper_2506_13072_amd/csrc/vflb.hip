@@ -245,10 +245,10 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
     if (s->inplace) {  // same-time velocity, then the in-place step
       using R = typename StoreT<S>::R;
       R* U = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + aux_u_words(s);
-      const int g = grid1d(s, 256);
-      hipLaunchKernelGGL((aa_velocity_kernel<S>), dim3(g), dim3(256), 0, st, a.pin, a.g, a.F,
+      const dim3 grid((s->nx + 255) / 256, s->ny < 65535 ? s->ny : 65535);
+      hipLaunchKernelGGL((aa_velocity_kernel<S>), grid, dim3(256), 0, st, a.pin, a.g, a.F,
                          a.inv_sf, U);
-      hipLaunchKernelGGL((aa_step_kernel<S>), dim3(g), dim3(256), 0, st, a, (const R*)U);
+      hipLaunchKernelGGL((aa_step_kernel<S>), grid, dim3(256), 0, st, a, (const R*)U);
       HIP_TRY(s, hipGetLastError());
       return VFLB_OK;
     }
