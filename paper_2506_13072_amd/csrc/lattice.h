@@ -98,18 +98,21 @@ template <class S> struct StoreT;
 template <> struct StoreT<double> {
   using R = double;
   static constexpr bool kAnchored = false;
+  static constexpr bool kPlanar = false;
   __device__ static R ld(const double* p, size_t i, R) { return p[i]; }
   __device__ static void st(double* p, size_t i, R v, R) { stream_store(p + i, v); }
 };
 template <> struct StoreT<float> {
   using R = float;
   static constexpr bool kAnchored = false;
+  static constexpr bool kPlanar = false;
   __device__ static R ld(const float* p, size_t i, R) { return p[i]; }
   __device__ static void st(float* p, size_t i, R v, R) { stream_store(p + i, v); }
 };
 template <> struct StoreT<_Float16> {
   using R = float;
   static constexpr bool kAnchored = true;
+  static constexpr bool kPlanar = false;
   // v = stored * 2^-k ; stored = RNE(v * 2^k)  (the scale is exact)
   __device__ static R ld(const _Float16* p, size_t i, R inv_scale) {
     return (float)p[i] * inv_scale;
@@ -121,6 +124,7 @@ template <> struct StoreT<_Float16> {
 template <> struct StoreT<bf16_t> {
   using R = float;
   static constexpr bool kAnchored = true;
+  static constexpr bool kPlanar = false;
   __device__ static R ld(const bf16_t* p, size_t i, R) {
     uint32_t b = (uint32_t)p[i].bits << 16;
     return __uint_as_float(b);
@@ -136,6 +140,21 @@ template <> struct StoreT<bf16_t> {
     }
     stream_store(reinterpret_cast<uint16_t*>(p) + i, out);
   }
+};
+
+// In-place (AA) storage of D2Q9 FP32 and FP64 states: the same numbers as
+// float and double, kept in planes (f, then each h component; layout.h)
+// rather than in (f, h) tuples, so that a pass which needs f alone reads f
+// alone.
+template <class T> struct Planar {
+  T v;
+};
+template <class T> struct StoreT<Planar<T>> {
+  using R = T;
+  static constexpr bool kAnchored = false;
+  static constexpr bool kPlanar = true;
+  __device__ static R ld(const Planar<T>* p, size_t i, R) { return p[i].v; }
+  __device__ static void st(Planar<T>* p, size_t i, R v, R) { stream_store(&p[i].v, v); }
 };
 
 // ---------------------------------------------------------------- params

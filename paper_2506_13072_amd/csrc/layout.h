@@ -111,6 +111,29 @@ template <class S> struct Pops<2, S> {
   }
 };
 
+// D2Q9 in place (Planar storage): f [Q N], then h_xx, h_xy, h_yy, each
+// [Q N].  Value t of a plane is direction t / N of node t % N, as in the
+// tuple layout; the velocity pass of in-place streaming reads the f plane
+// only.
+template <class T> struct Pops<2, Planar<T>> {
+  using S = Planar<T>;
+  using St = StoreT<S>;
+  using R = T;
+  static constexpr int Q = 9, NC = 3;
+  __host__ __device__ static size_t words(size_t N) { return (size_t)4 * Q * N; }
+  __device__ static void load(const S* p, size_t t, size_t N, R, R, R& f, R* h) {
+    f = St::ld(p, t, (R)1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) h[c] = St::ld(p, (size_t)(c + 1) * Q * N + t, (R)1);
+  }
+  __device__ static R load_f(const S* p, size_t t, size_t, R) { return St::ld(p, t, (R)1); }
+  __device__ static void store(S* p, size_t t, size_t N, R, R, R f, const R* h) {
+    St::st(p, t, f, (R)1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) St::st(p, (size_t)(c + 1) * Q * N + t, h[c], (R)1);
+  }
+};
+
 // D3Q19: f [Q N], then tuples (h_xx, h_yy, h_zz, h_xy) [Q N], then tuples
 // (h_xz, h_yz) [Q N].  f sits alone so that forming u ahead of a plane
 // touches only f cache lines; per pulled direction the step issues one

@@ -322,8 +322,9 @@ __global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx,
 // velocity comes from a separate pass (aa_velocity_kernel) into u [2][N].
 // The arithmetic is step2d_tile's, operation for operation, so a lattice
 // stepped in place takes bitwise the values it takes with two buffers.
-// Both kernels give a lane one node: blockIdx.x a run of x, blockIdx.y (and
-// its strides) the rows.
+// The buffer holds Planar storage (f and each h component in planes), so
+// the velocity pass reads the f plane alone.  Both kernels give a lane one
+// node: blockIdx.x a run of x, blockIdx.y (and its strides) the rows.
 
 // index of the slot that the reader of the next step expects f*_i of
 // node (x, y) in (g.aa: the layout of the state being read, 1 or 2)

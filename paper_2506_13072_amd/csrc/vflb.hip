@@ -232,27 +232,9 @@ vflb_status launch_divergence(vflb_sim* s, int64_t t, hipStream_t st, int parity
   }
 }
 
+// the two-buffer step: tiled kernels over the whole lattice
 template <int D, class S>
-vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
-  if constexpr (D == 2) {
-    if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
-      vflb_status rc = launch_divergence<S>(s, t, st, parity);
-      if (rc != VFLB_OK) return rc;
-    }
-  }
-  StepArgs<S> a = make_step_args<S>(s, t, parity);
-  if constexpr (D == 2 && !StoreT<S>::kAnchored) {
-    if (s->inplace) {  // same-time velocity, then the in-place step
-      using R = typename StoreT<S>::R;
-      R* U = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + aux_u_words(s);
-      const dim3 grid((s->nx + 255) / 256, s->ny < 65535 ? s->ny : 65535);
-      hipLaunchKernelGGL((aa_velocity_kernel<S>), grid, dim3(256), 0, st, a.pin, a.g, a.F,
-                         a.inv_sf, U);
-      hipLaunchKernelGGL((aa_step_kernel<S>), grid, dim3(256), 0, st, a, (const R*)U);
-      HIP_TRY(s, hipGetLastError());
-      return VFLB_OK;
-    }
-  }
+vflb_status launch_tiled(vflb_sim* s, hipStream_t st, StepArgs<S> a) {
   if (D == 2) {
     a.clamp = s->clamp;
     a.clamp_flags = s->clamp_flags;
@@ -300,6 +282,29 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
   }
   HIP_TRY(s, hipGetLastError());
   return VFLB_OK;
+}
+
+template <int D, class S>
+vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
+  if constexpr (D == 2) {
+    if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
+      vflb_status rc = launch_divergence<S>(s, t, st, parity);
+      if (rc != VFLB_OK) return rc;
+    }
+  }
+  StepArgs<S> a = make_step_args<S>(s, t, parity);
+  if constexpr (!StoreT<S>::kPlanar) {
+    return launch_tiled<D, S>(s, st, a);
+  } else {  // in place: same-time velocity, then the step
+    using R = typename StoreT<S>::R;
+    R* U = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + aux_u_words(s);
+    const dim3 grid((s->nx + 255) / 256, s->ny < 65535 ? s->ny : 65535);
+    hipLaunchKernelGGL((aa_velocity_kernel<S>), grid, dim3(256), 0, st, a.pin, a.g, a.F, a.inv_sf,
+                       U);
+    hipLaunchKernelGGL((aa_step_kernel<S>), grid, dim3(256), 0, st, a, (const R*)U);
+    HIP_TRY(s, hipGetLastError());
+    return VFLB_OK;
+  }
 }
 
 template <int D, class S, class T>
@@ -390,8 +395,10 @@ template <template <int, class> class Op, class... A>
 vflb_status dispatch(vflb_sim* s, A... args) {
   if (s->D == 2) {
     switch (s->storage) {
-      case VFLB_F64: return Op<2, double>::run(s, args...);
-      case VFLB_F32: return Op<2, float>::run(s, args...);
+      case VFLB_F64:
+        return s->inplace ? Op<2, Planar<double>>::run(s, args...) : Op<2, double>::run(s, args...);
+      case VFLB_F32:
+        return s->inplace ? Op<2, Planar<float>>::run(s, args...) : Op<2, float>::run(s, args...);
       case VFLB_F16S: return Op<2, _Float16>::run(s, args...);
       default: return Op<2, bf16_t>::run(s, args...);
     }
