@@ -1,0 +1,95 @@
+"""In-place (AA) streaming index maps, checked on the CPU.
+
+A model of the two maps the in-place D2Q9 step uses: where the value f_i of
+node x at time t sits (the read map, by parity of t) and where a node puts
+its post-collision f*_i for the next step's reader (the write map).  On
+small lattices with every wall combination the maps must (i) give each slot
+exactly one reader and one writer per step, that writer being its reader
+(no ordering between nodes is needed), and (ii) reproduce two-buffer pull
+streaming with halfway bounce-back exactly, for an arbitrary node- and
+time-dependent collision.  The GPU tests check the kernels themselves
+(bitwise against the two-buffer path).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+C = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+
+
+def read_slot(i, x, y, nx, ny, walls, mode):
+    """Slot holding f_i(x, y): mode 0 two buffers (post-collision values at
+    their writer), 1 in place at even t, 2 in place at odd t."""
+    N = nx * ny
+    if mode == 1:
+        return i * N + y * nx + x
+    s, n, bounce = [x - C[i][0], y - C[i][1]], [nx, ny], False
+    for a in range(2):
+        if C[i][a] != 0 and not 0 <= s[a] < n[a]:
+            if walls & (1 << a):
+                bounce = True
+            else:
+                s[a] = n[a] - 1 if s[a] < 0 else 0
+    j = OPP[i] if mode == 2 else i
+    if bounce:
+        return OPP[j] * N + y * nx + x
+    return j * N + s[1] * nx + s[0]
+
+
+def write_slot(i, x, y, nx, ny, walls, mode):
+    """Slot that receives f*_i of (x, y) in an in-place step of `mode`."""
+    N, n, o = nx * ny, y * nx + x, OPP[i]
+    if mode == 1:
+        return o * N + n
+    tx, ty = x + C[i][0], y + C[i][1]
+    if (walls & 1 and not 0 <= tx < nx) or (walls & 2 and not 0 <= ty < ny):
+        return o * N + n
+    return i * N + (ty % ny) * nx + (tx % nx)
+
+
+def collide(f, x, y, t):
+    return [v * 1.0001 + 0.37 * ((7 * x + 3 * y + i + t) % 5) for i, v in enumerate(f)]
+
+
+CASES = [(nx, ny, w) for nx, ny, w in itertools.product([1, 2, 3, 5], [1, 2, 4], range(4))
+         if not (w & 1 and nx < 2) and not (w & 2 and ny < 2)]
+
+
+@pytest.mark.parametrize("nx,ny,walls", CASES)
+def test_in_place_maps_are_race_free_and_equal_two_buffer_streaming(nx, ny, walls):
+    N = nx * ny
+    f0 = np.random.default_rng(100 * nx + 10 * ny + walls).normal(size=(9, N))
+    two = np.full(9 * N, np.nan)
+    one = np.full(9 * N, np.nan)
+    for y, x, i in itertools.product(range(ny), range(nx), range(9)):
+        two[read_slot(i, x, y, nx, ny, walls, 0)] = f0[i, y * nx + x]
+        one[read_slot(i, x, y, nx, ny, walls, 1)] = f0[i, y * nx + x]
+    assert not np.isnan(two).any() and not np.isnan(one).any()
+    for t in range(6):
+        nxt = np.full(9 * N, np.nan)
+        for y, x in itertools.product(range(ny), range(nx)):
+            fs = collide([two[read_slot(i, x, y, nx, ny, walls, 0)] for i in range(9)], x, y, t)
+            for i in range(9):
+                nxt[i * N + y * nx + x] = fs[i]
+        two = nxt
+        mode = 1 if t % 2 == 0 else 2
+        reader, writer, new = {}, {}, one.copy()
+        for y, x in itertools.product(range(ny), range(nx)):
+            n, f = y * nx + x, []
+            for i in range(9):
+                k = read_slot(i, x, y, nx, ny, walls, mode)
+                assert reader.setdefault(k, n) == n
+                f.append(one[k])
+            for i, v in enumerate(collide(f, x, y, t)):
+                k = write_slot(i, x, y, nx, ny, walls, mode)
+                assert writer.setdefault(k, n) == n
+                new[k] = v
+        assert len(reader) == len(writer) == 9 * N
+        assert all(reader[k] == writer[k] for k in writer)
+        one = new
+        nm = 1 if (t + 1) % 2 == 0 else 2
+        for y, x, i in itertools.product(range(ny), range(nx), range(9)):
+            assert two[read_slot(i, x, y, nx, ny, walls, 0)] == \
+                one[read_slot(i, x, y, nx, ny, walls, nm)], (t, x, y, i)
