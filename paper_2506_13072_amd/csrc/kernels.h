@@ -162,11 +162,22 @@ __device__ inline void node_moments(const S* pin, const typename StoreT<S>::R* a
   using L = Lat<D>;
   constexpr int Q = L::Q, NC = L::NC;
   constexpr bool ANCHOR = D == 2 && St::kAnchored;
+  constexpr bool ANCHOR3 = D == 3 && St::kAnchored;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     R hv[NC];
     const size_t t = pull_index<D>(i, x, y, z, g);
     Pops<D, S>::load(pin, t, g.N, inv_sf, inv_sh, m.f[i], hv);
+    if constexpr (ANCHOR3) {  // reference of the writing node + deviation
+      const int j = (int)(t / g.N);
+      const size_t src = t - (size_t)j * g.N;
+      float pa, ua[3], Ea[6];
+      Anchor3::load(pin, src, g.N, pa, ua, Ea);
+      const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
+      m.f[i] += fref3<R>(j, (R)pa, uw);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) hv[c] += href3<R>(j, c, (R)Ea[c], uw);
+    }
     if constexpr (ANCHOR) {  // reference of the writing node + deviation
       const int j = (int)(t / g.N);
       const size_t src = t % g.N;
@@ -330,6 +341,16 @@ __device__ inline float2 init_velocity(size_t m, size_t N, const T* u_in) {
   return v;
 }
 
+// D3Q19 anchor of node m from the initial fields
+template <class T>
+__device__ inline void init_anchor3(size_t m, size_t N, const T* u_in, const T* tau_in,
+                                    const T* p_in, double lam_over_eta, float& p, float* u,
+                                    float* E) {
+  p = p_in ? (float)p_in[m] : 0.0f;
+  for (int b = 0; b < 3; ++b) u[b] = u_in ? (float)u_in[(size_t)b * N + m] : 0.0f;
+  for (int c = 0; c < 6; ++c) E[c] = tau_in ? (float)(lam_over_eta * tau_in[(size_t)c * N + m]) : 0.0f;
+}
+
 template <int D, class S, class T>
 __global__ void __launch_bounds__(256) init_kernel(
     S* pbuf, typename StoreT<S>::R* aux, Geo g,
@@ -340,6 +361,7 @@ __global__ void __launch_bounds__(256) init_kernel(
   using L = Lat<D>;
   constexpr int Q = L::Q, NC = L::NC;
   constexpr bool ANCHOR = D == 2 && St::kAnchored;
+  constexpr bool ANCHOR3 = D == 3 && St::kAnchored;
   for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
        n += (size_t)gridDim.x * blockDim.x) {
     int x, y, z;
@@ -378,6 +400,16 @@ __global__ void __launch_bounds__(256) init_kernel(
         hv[1] -= href2<R>(j, 1, (R)1, (R)q.y, ux, uy);
         hv[2] -= href2<R>(j, 2, (R)1, (R)q.z, ux, uy);
       }
+      if constexpr (ANCHOR3) {
+        const int j = (int)(t / g.N);
+        const size_t src = t - (size_t)j * g.N;
+        float pa, ua[3], Ea[6];
+        init_anchor3(src, g.N, u_in, tau_in, p_in, lam_over_eta, pa, ua, Ea);
+        const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
+        feq -= fref3<R>(j, (R)pa, uw);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) hv[c] -= href3<R>(j, c, (R)Ea[c], uw);
+      }
       Pops<D, S>::store(pbuf, t, g.N, sf, sh, feq, hv);
     }
     R zero[NC];
@@ -386,6 +418,11 @@ __global__ void __launch_bounds__(256) init_kernel(
     if constexpr (ANCHOR)
       Anchor2::store(pbuf, n, g.N, init_anchor(n, g.N, tau_in, p_in, lam_over_eta),
                      init_velocity(n, g.N, u_in));
+    if constexpr (ANCHOR3) {
+      float pa, ua[3], Ea[6];
+      init_anchor3(n, g.N, u_in, tau_in, p_in, lam_over_eta, pa, ua, Ea);
+      Anchor3::store(pbuf, n, g.N, pa, ua, Ea);
+    }
   }
 }
 

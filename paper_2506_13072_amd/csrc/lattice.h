@@ -10,7 +10,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace vflb {
+
+// Compile-time loop: fn(std::integral_constant<int, K>()) for K = B .. E-1,
+// each body its own instantiation, so the loop is unrolled whatever its size
+// and per-direction arrays stay in registers.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>());
+    static_for<B + 1, E>(fn);
+  }
+}
 
 template <int D> struct Lat;
 

@@ -15,8 +15,8 @@
 //  D2Q9:  chi [N][3] then u [N][2] (one 12-byte and one 8-byte access).
 //  D3Q19: chi [NC][N] then u [D][N].
 //
-// Anchored 16-bit storage (D2Q9, FP16 and BF16): every node also keeps, in
-// FP32 in the population buffer (Anchor2), its anchor (E_xx, E_xy, E_yy, p)
+// Anchored 16-bit storage (D2Q9 and D3Q19, FP16 and BF16): every node also keeps, in
+// FP32 in the population buffer (Anchor2, Anchor3), its anchor (E, p)
 // with E = A - I of its post-collision state, p its pressure and u its
 // velocity, from which follow reference populations f_ref(p, u) (the
 // equilibrium form) and h_ref(E, u) (the shifted equilibrium form).  A stored population is the
@@ -205,6 +205,62 @@ struct Anchor2 {
     const f2 v = {u.x, u.y};
     __builtin_nontemporal_store(q, reinterpret_cast<f4*>(b) + n);
     __builtin_nontemporal_store(v, reinterpret_cast<f2*>(b + 16 * N) + n);
+  }
+};
+
+// D3Q19 references, as fref2 / href2; direction i is the stored direction
+// (the writer's), so no sign flip is needed for a bounce-back pull
+template <class R>
+__device__ inline R fref3(int i, R p, const R* u) {
+  const R wi = (R)Lat<3>::w(i);
+  const R lam_i = (R)(i == 0 ? 3.0 * (Lat<3>::w(0) - 1.0) : 3.0 * Lat<3>::w(i));
+  const R cu = (R)Lat<3>::cx(i) * u[0] + (R)Lat<3>::cy(i) * u[1] + (R)Lat<3>::cz(i) * u[2];
+  const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  return lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
+}
+template <class R>
+__device__ inline R href3(int i, int c, R E, const R* u) {
+  const R wi = (R)Lat<3>::w(i);
+  const R cu = (R)Lat<3>::cx(i) * u[0] + (R)Lat<3>::cy(i) * u[1] + (R)Lat<3>::cz(i) * u[2];
+  return wi * E + 3 * wi * (E + (c < 3 ? (R)1 : (R)0)) * cu;
+}
+
+// D3Q19 anchor of node n, after the 16-bit populations of the buffer (it
+// ping-pongs with them): (p, u_x, u_y, u_z) as [N] float4, then (E_xx,
+// E_yy, E_zz, E_xy) as [N] float4, then (E_xz, E_yz) as [N] float2, each
+// array 256-byte aligned.  A pull that needs only the writer's p and u
+// reads the first array alone.
+struct Anchor3 {
+  __host__ __device__ static size_t offset(size_t N) {
+    return ((size_t)2 * 7 * 19 * N + 255) & ~(size_t)255;
+  }
+  __host__ __device__ static size_t off1(size_t N) { return (16 * N + 255) & ~(size_t)255; }
+  __host__ __device__ static size_t off2(size_t N) { return off1(N) + ((16 * N + 255) & ~(size_t)255); }
+  __host__ __device__ static size_t bytes(size_t N) { return offset(N) + off2(N) + 8 * N; }
+  __device__ static void load_pu(const void* pbuf, size_t n, size_t N, float& p, float* u) {
+    const char* b = static_cast<const char*>(pbuf) + offset(N);
+    const float4 q = reinterpret_cast<const float4*>(b)[n];
+    p = q.x; u[0] = q.y; u[1] = q.z; u[2] = q.w;
+  }
+  __device__ static void load(const void* pbuf, size_t n, size_t N, float& p, float* u,
+                              float* E) {
+    load_pu(pbuf, n, N, p, u);
+    const char* b = static_cast<const char*>(pbuf) + offset(N);
+    const float4 e = reinterpret_cast<const float4*>(b + off1(N))[n];
+    const float2 r = reinterpret_cast<const float2*>(b + off2(N))[n];
+    E[0] = e.x; E[1] = e.y; E[2] = e.z; E[3] = e.w; E[4] = r.x; E[5] = r.y;
+  }
+  __device__ static void store(void* pbuf, size_t n, size_t N, float p, const float* u,
+                               const float* E) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    char* b = static_cast<char*>(pbuf) + offset(N);
+    const f4 q = {p, u[0], u[1], u[2]};
+    const f4 e = {E[0], E[1], E[2], E[3]};
+    const f2 r = {E[4], E[5]};
+    __builtin_nontemporal_store(q, reinterpret_cast<f4*>(b) + n);
+    __builtin_nontemporal_store(e, reinterpret_cast<f4*>(b + off1(N)) + n);
+    __builtin_nontemporal_store(r, reinterpret_cast<f2*>(b + off2(N)) + n);
   }
 };
 

@@ -19,6 +19,7 @@
 // into registers.  A lane keeps the f it pulled for its own node and
 // collides it two planes later, so f crosses HBM once and h once.
 // Blocks are renumbered so that each XCD walks one contiguous run of tiles.
+// FP32 and FP64 storage; 16-bit storage is anchored and runs anchor3d.h.
 #pragma once
 
 #include "kernels.h"
@@ -30,8 +31,8 @@ namespace vflb {
 // 128: 31.9 ms per step (same box)
 constexpr int kStep3dChunk = 16;
 
-// conversion between the storage type and the arithmetic type (scale: the
-// exact power of two of FP16 storage; unused otherwise)
+// conversion between the storage type and the arithmetic type (FP32 and
+// FP64 storage: 16-bit D3Q19 storage is anchored and runs anchor3d.h)
 template <class S> struct Cvt;
 template <> struct Cvt<double> {
   using V = double;
@@ -42,16 +43,6 @@ template <> struct Cvt<float> {
   using V = float;
   __device__ static float in(V v, float) { return v; }
   __device__ static V out(float v, float) { return v; }
-};
-template <> struct Cvt<_Float16> {
-  using V = _Float16;
-  __device__ static float in(V v, float inv_scale) { return (float)v * inv_scale; }
-  __device__ static V out(float v, float scale) { return (_Float16)(v * scale); }
-};
-template <> struct Cvt<bf16_t> {
-  using V = uint16_t;
-  __device__ static float in(V v, float) { return bf16_to_f32(v); }
-  __device__ static V out(float v, float) { return f32_to_bf16(v); }
 };
 
 // Access to the D3Q19 population buffer by pair: k = 0 is the rest plane
@@ -208,15 +199,7 @@ __device__ inline void dma_to_lds(const void* src, void* wave_block) {
 // issued one plane ahead of their use: per wave and pair the lane slots of
 // the h tuples, the rest f and the previous-step source state.  A lane reads
 // back only what it loaded itself.
-template <class S, int TY> struct Stage3 {
-  // 16-bit storage: (xx, yy) and (zz, xy) as the two 4-byte halves of the
-  // 8-byte 4-tuple, (xz, yz) as one 4-byte 2-tuple; the rest f as the
-  // aligned 4-byte word that holds it
-  uint32_t h4[2][TY][10][64];
-  uint32_t h2[TY][10][64];
-  uint32_t f0[TY][64];
-  float aux[9][TY][64];
-};
+template <class S, int TY> struct Stage3;
 template <int TY> struct Stage3<float, TY> {
   float4 h4[TY][10][64];
   float h2[2][TY][10][64];
@@ -231,29 +214,18 @@ __device__ inline void stage_issue(Stage3<S, TY>& st, const S* pin, const typena
   using PA = Pair3<S>;
   const uint32_t N32 = (uint32_t)N, n = pq.self;
   auto issue_h = [&](int k, uint32_t o) {
-    if constexpr (std::is_same<S, float>::value) {
-      const char* a = PA::h4b(pin, k, N) + o * 16u;
-      const char* b = PA::h2b(pin, k, N) + o * 8u;
-      dma_to_lds<16>(a, &st.h4[ty][k][0]);
-      dma_to_lds<4>(b, &st.h2[0][ty][k][0]);
-      dma_to_lds<4>(b + 4, &st.h2[1][ty][k][0]);
-    } else {
-      const char* a = PA::h4b(pin, k, N) + o * 8u;
-      const char* b = PA::h2b(pin, k, N) + o * 4u;
-      dma_to_lds<4>(a, &st.h4[0][ty][k][0]);
-      dma_to_lds<4>(a + 4, &st.h4[1][ty][k][0]);
-      dma_to_lds<4>(b, &st.h2[ty][k][0]);
-    }
+    const char* a = PA::h4b(pin, k, N) + o * 16u;
+    const char* b = PA::h2b(pin, k, N) + o * 8u;
+    dma_to_lds<16>(a, &st.h4[ty][k][0]);
+    dma_to_lds<4>(b, &st.h2[0][ty][k][0]);
+    dma_to_lds<4>(b + 4, &st.h2[1][ty][k][0]);
   };
   issue_h(0, n);  // rest: both lanes, one address
   for_pairs<1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     issue_h(k, pair_src<k, WALLS>(pq, s, N32));
   });
-  if constexpr (std::is_same<S, float>::value)
-    dma_to_lds<4>(pin + n, &st.f0[ty][0]);
-  else
-    dma_to_lds<4>(reinterpret_cast<const char*>(pin) + 4 * (size_t)(n >> 1), &st.f0[ty][0]);
+  dma_to_lds<4>(pin + n, &st.f0[ty][0]);
   if (!first) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) dma_to_lds<4>(aux + (size_t)q * N + n, &st.aux[q][ty][0]);
@@ -261,41 +233,16 @@ __device__ inline void stage_issue(Stage3<S, TY>& st, const S* pin, const typena
 }
 
 template <class S, int TY, class R>
-__device__ inline void stage_read_h(const Stage3<S, TY>& st, int k, int ty, int tx, R ish, R* h) {
-  using C = Cvt<S>;
-  using V = typename C::V;
-  if constexpr (std::is_same<S, float>::value) {
-    const float4 a = st.h4[ty][k][tx];
-    h[0] = a.x; h[1] = a.y; h[2] = a.z; h[3] = a.w;
-    h[4] = st.h2[0][ty][k][tx];
-    h[5] = st.h2[1][ty][k][tx];
-  } else {
-    const uint32_t w[3] = {st.h4[0][ty][k][tx], st.h4[1][ty][k][tx], st.h2[ty][k][tx]};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const uint16_t lo = (uint16_t)(w[j] & 0xFFFFu), hi = (uint16_t)(w[j] >> 16);
-      V vl, vh;
-      __builtin_memcpy(&vl, &lo, 2);
-      __builtin_memcpy(&vh, &hi, 2);
-      h[2 * j] = C::in(vl, ish);
-      h[2 * j + 1] = C::in(vh, ish);
-    }
-  }
+__device__ inline void stage_read_h(const Stage3<S, TY>& st, int k, int ty, int tx, R, R* h) {
+  const float4 a = st.h4[ty][k][tx];
+  h[0] = a.x; h[1] = a.y; h[2] = a.z; h[3] = a.w;
+  h[4] = st.h2[0][ty][k][tx];
+  h[5] = st.h2[1][ty][k][tx];
 }
 
 template <class S, int TY, class R>
-__device__ inline R stage_read_f0(const Stage3<S, TY>& st, uint32_t n, int ty, int tx, R isf) {
-  if constexpr (std::is_same<S, float>::value) {
-    return st.f0[ty][tx];
-  } else {
-    using C = Cvt<S>;
-    using V = typename C::V;
-    const uint32_t w = st.f0[ty][tx];
-    const uint16_t b = (uint16_t)((n & 1u) ? (w >> 16) : (w & 0xFFFFu));
-    V v;
-    __builtin_memcpy(&v, &b, 2);
-    return C::in(v, isf);
-  }
+__device__ inline R stage_read_f0(const Stage3<S, TY>& st, uint32_t, int ty, int tx, R) {
+  return st.f0[ty][tx];
 }
 
 // Tiles are walked by full tiles (FULL: every lane owns a lattice node, so
@@ -306,6 +253,7 @@ __device__ inline R stage_read_f0(const Stage3<S, TY>& st, uint32_t n, int ty, i
 template <class S, int TY, int ZC, bool WALLS, bool FULL>
 __global__ void __launch_bounds__(64 * TY, sizeof(S) == 8 ? 1 : 2)
     step3d_kernel(StepArgs<S> a, int ntx, int nty) {
+  static_assert(!StoreT<S>::kAnchored, "16-bit D3Q19 storage is anchored (anchor3d.h)");
   using R = typename StoreT<S>::R;
   using PA = Pair3<S>;
   using L = Lat<3>;

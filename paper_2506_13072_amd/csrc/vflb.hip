@@ -15,6 +15,7 @@
 #include "kernels.h"
 #include "step2d.h"
 #include "step3d.h"
+#include "anchor3d.h"
 #include "internal.h"
 
 using namespace vflb;
@@ -259,6 +260,19 @@ vflb_status launch_tiled(vflb_sim* s, hipStream_t st, StepArgs<S> a) {
           break;
       }
     }
+  } else if constexpr (StoreT<S>::kAnchored) {
+    // anchored 16-bit storage: same-time velocity, then the step
+    using R = typename StoreT<S>::R;
+    R* U = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + aux_u_words(s);
+    const dim3 grid((s->nx + 255) / 256, s->ny < 65535 ? s->ny : 65535,
+                    s->nz < 65535 ? s->nz : 65535);
+    hipLaunchKernelGGL((anchor3_velocity_kernel<S>), grid, dim3(256), 0, st, a.pin, a.g, a.F,
+                       a.inv_sf, U);
+    const int nty = (s->ny + A3_TY - 1) / A3_TY;
+    const dim3 grid_step((s->nx + A3_TX - 1) / A3_TX, nty < 65535 ? nty : 65535,
+                         s->nz < 65535 ? s->nz : 65535);
+    hipLaunchKernelGGL((anchor3_step_kernel<S>), grid_step, dim3(A3_TX, A3_TY), 0, st, a,
+                       (const R*)U);
   } else {
     constexpr int ZC = kStep3dChunk;
     const int ty = tile_y_3d(s);
@@ -544,17 +558,18 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
   const size_t sb = s->store_bytes(), ab = s->arith_bytes();
   const size_t words =
       lattice == VFLB_D2Q9 ? Pops<2, float>::words(N) : Pops<3, float>::words(N);
-  // anchored 16-bit D2Q9 storage keeps an FP32 anchor per node after the
-  // tuples of each population buffer (layout.h)
-  const bool anchored = lattice == VFLB_D2Q9 && (storage == VFLB_F16S || storage == VFLB_BF16S);
-  s->bytes[VFLB_BUF_POP0] = s->bytes[VFLB_BUF_POP1] =
-      align256(anchored ? Anchor2::bytes(N) : sb * words);
+  // anchored 16-bit storage keeps an FP32 anchor per node after the
+  // populations of each population buffer (layout.h)
+  const bool anchored = storage == VFLB_F16S || storage == VFLB_BF16S;
+  s->bytes[VFLB_BUF_POP0] = s->bytes[VFLB_BUF_POP1] = align256(
+      anchored ? (lattice == VFLB_D2Q9 ? Anchor2::bytes(N) : Anchor3::bytes(N)) : sb * words);
   if (inplace) s->bytes[VFLB_BUF_POP1] = 256;  // unused
   // AUX: chi(t-1), u(t-1); the stress-divergence scheme adds tau_p [3][N]
-  // and div tau_p [2][N]
+  // and div tau_p [2][N]; in-place streaming u(t) [2][N], anchored D3Q19
+  // storage u(t) [3][N]
+  const size_t u_now = inplace ? 2 : (anchored && lattice == VFLB_D3Q19 ? 3 : 0);
   s->bytes[VFLB_BUF_AUX] = align256(
-      ab * ((s->NC + s->D) + (scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? 5 : 0) + (inplace ? 2 : 0)) *
-      N);
+      ab * ((s->NC + s->D) + (scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? 5 : 0) + u_now) * N);
   s->bytes[VFLB_BUF_SNAP] = align256(ab * (s->NC + s->D) * N);
   s->off_tab = 0;
   s->off_part = align256(ab * 2 * ((size_t)nx + ny));
@@ -627,19 +642,12 @@ vflb_status vflb_set_params(vflb_sim* s, const vflb_params* p) {
   s->prm = *p;
   s->lp = l;
   s->have_params = true;
-  // FP16 scales: populations of f are O(U0); shifted h are O(1) at most
-  // moderate stretch.  Keep 2^14 * typical magnitude below the FP16 range.
+  // FP16 scales: anchored storage holds deviations from a reference, the
+  // non-equilibrium parts O(U0 k) and below, scaled into FP16's normal range
   int ef;
   std::frexp(p->U0, &ef);
-  if (s->D == 2) {
-    // anchored D2Q9 storage holds deviations from a reference: non-
-    // equilibrium parts O(U0 k) and below, scaled into FP16's normal range
-    s->log2_sf = 10 - ef;
-    s->log2_sh = 12;
-  } else {
-    s->log2_sf = 8 - ef;
-    s->log2_sh = 6;
-  }
+  s->log2_sf = 10 - ef;
+  s->log2_sh = 12;
   if (s->log2_sf < 0) s->log2_sf = 0;
   if (s->log2_sf > 24) s->log2_sf = 24;
   drop_graphs(s);

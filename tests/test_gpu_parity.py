@@ -11,7 +11,7 @@ import pytest
 
 from oracle import analytic as AN
 from oracle import oracle as O
-from paper_2506_13072_amd.workloads import smooth_fields
+from paper_2506_13072_amd.workloads import smooth_fields, taylor_green_3d_velocity
 
 pytestmark = pytest.mark.gpu
 
@@ -64,6 +64,14 @@ def setup_pair(V, d, shape, storage, walls=(0, 0, 0), force="none", Re=1.0, Wi=1
                                    amp_p=U0 ** 2)
         o.init(u, tau, pr)
         g.init_fields(u, tau, pr)
+    elif init == "tgv":  # 3D Taylor-Green vortex (theta = 0) with its pressure
+        n = shape[0]
+        u = taylor_green_3d_velocity(n, U0)
+        x = 2 * np.pi * np.arange(n) / n
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        pr = ((U0 ** 2 / 16) * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2)).ravel()
+        o.init(u, None, pr)
+        g.init_fields(u, None, pr)
     else:
         o.init()
         g.init_fields()
@@ -454,3 +462,57 @@ def test_inplace_keeps_one_population_buffer_and_is_rejected_where_not_built(V):
     for args in ((3, 8, 8, 8, "f32"), (2, 8, 8, 1, "f16s"), (2, 8, 8, 1, "bf16s")):
         with pytest.raises(V.VflbError):
             V.Sim(*args, inplace=True)
+
+
+# ------------------------------------------------- anchored 16-bit D3Q19
+# FP16 / BF16 deviations from the writer's FP32 anchor.  The 3D Taylor-Green
+# copy uses the benchmark's parameters (U0 = 0.02, Re = 100); Wi = 2,
+# beta = 0.1 is the strongly polymeric case.  FP16 meets the 1e-3 bar of
+# 16-bit storage in every case.  BF16 does not in D3Q19: its 8-bit mantissa
+# leaves each deviation with a 2e-3 relative rounding, and these coarse
+# lattices carry large non-equilibrium parts; its bounds below are the
+# measured errors (u 2.1e-3 / 2.7e-3, tau 1.5e-3 / 1.0e-3 / 6.5e-3) with
+# margin, and the mass bound is four times FP16's.
+ANCHOR3_CASES = [
+    ("f16s", (16, 16, 16), (0, 0, 0), "tgv", 0.5, 0.9, 300, 1e-3),
+    ("bf16s", (16, 16, 16), (0, 0, 0), "tgv", 0.5, 0.9, 300, 3e-3),
+    ("f16s", (16, 16, 16), (0, 0, 0), "tgv", 2.0, 0.1, 200, 1e-3),
+    ("bf16s", (16, 16, 16), (0, 0, 0), "tgv", 2.0, 0.1, 200, 4e-3),
+    ("f16s", (36, 9, 5), (0, 0, 1), "smooth", 1.0, 0.5, 200, 1e-3),
+    ("bf16s", (36, 9, 5), (0, 0, 1), "smooth", 1.0, 0.5, 200, 1e-2),
+]
+
+
+@pytest.mark.parametrize("storage,shape,walls,init,Wi,beta,steps,tol", ANCHOR3_CASES)
+def test_anchored_16bit_d3q19_against_the_oracle(V, storage, shape, walls, init, Wi, beta,
+                                                  steps, tol):
+    n = shape[-1]
+    o, g = setup_pair(V, 3, shape, storage, walls, "const" if init == "smooth" else "none",
+                      Re=100.0 if init == "tgv" else 1.0, Wi=Wi, beta=beta,
+                      U0=0.02 if init == "tgv" else 0.01, L=n / (2 * np.pi), init=init, seed=12)
+    o.step(steps)
+    g.step(steps)
+    out = compare(o, g, tol, fields=("u", "tau", "Ae"))
+    r = g.reduce()
+    assert r["nonfinite"] == 0
+    mass_tol = (1e-3 if storage == "f16s" else 4e-3) * n ** 3 * 0.02 ** 2
+    assert abs(r["M"] - float(o.get_state()["f"].sum())) < mass_tol, (r, out)
+
+
+def test_anchored_16bit_d3q19_graphs_and_checkpoints_bitwise(V):
+    mk = lambda: setup_pair(V, 3, (20, 12, 18), "f16s", (0, 1, 0), "const", init="smooth",
+                            seed=5)[1]
+    a, b, c = mk(), mk(), mk()
+    a.step(1)
+    a.step(70)  # single launches and a 64-step graph
+    for _ in range(71):
+        b.step(1)
+    for k in (V.FIELD_F, V.FIELD_H, V.FIELD_CHI_PREV, V.FIELD_U_PREV):
+        assert np.array_equal(a.read(k), b.read(k)), k
+    blob = b.save()
+    b.step(9)
+    c.step(4)
+    c.load(blob)
+    c.step(9)
+    for k in (V.FIELD_F, V.FIELD_H):
+        assert np.array_equal(b.read(k), c.read(k)), k
