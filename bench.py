@@ -37,16 +37,12 @@ def bytes_per_lup(d, storage):
     """Algorithmic HBM bytes per lattice update: every f and h population
     read once and written once, plus chi(t-1) and u(t-1) read and written;
     16-bit storage also reads and writes each node's FP32 anchor (A - I, p,
-    u: 24 bytes in D2Q9, 40 in D3Q19), and in D3Q19 its velocity pass reads
-    the 18 moving f and the writers' (p, u) and writes u (3 words), which the
-    step reads."""
+    u: 24 bytes in D2Q9, 40 in D3Q19)."""
     q, nc = (9, 3) if d == 2 else (19, 6)
     sb = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[storage]
     ab = 8 if storage == "f64" else 4
-    extra = 0
-    if sb == 2:
-        extra = 2 * 24 if d == 2 else 2 * 40 + (18 * 2 + 16 + 12) + 12
-    return 2 * q * (1 + nc) * sb + 2 * (nc + d) * ab + extra
+    anchor = 2 * (24 if d == 2 else 40) if sb == 2 else 0
+    return 2 * q * (1 + nc) * sb + 2 * (nc + d) * ab + anchor
 
 
 # stress-divergence scheme: per step one extra pass pulls the 9 (f, h)

@@ -28,7 +28,6 @@ HIPCC_FLAGS = [
 KERNEL_FILES = {
     "step2d": ("step2d.h", "kernels.h", "layout.h", "lattice.h"),
     "step3d": ("step3d.h", "kernels.h", "layout.h", "lattice.h"),
-    "anchor3d": ("anchor3d.h", "kernels.h", "layout.h", "lattice.h"),
 }
 
 

@@ -225,6 +225,27 @@ __device__ inline R href3(int i, int c, R E, const R* u) {
   return wi * E + 3 * wi * (E + (c < 3 ? (R)1 : (R)0)) * cu;
 }
 
+// The same references for the member of opposite pair K (K >= 1) with
+// velocity sgn c_{2K-1} (sgn = 1: direction 2K - 1, -1: direction 2K), for
+// code that holds a pair's member by sign rather than by index; equal
+// bitwise to fref3 / href3 of that direction (c_{2K} = -c_{2K-1}).
+template <int K, class R>
+__device__ inline R fref3_pair(R sgn, R p, const R* u) {
+  constexpr int i = 2 * K - 1;
+  const R wi = (R)Lat<3>::w(i);
+  const R lam_i = (R)(3.0 * Lat<3>::w(i));
+  const R cu = sgn * ((R)Lat<3>::cx(i) * u[0] + (R)Lat<3>::cy(i) * u[1] + (R)Lat<3>::cz(i) * u[2]);
+  const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  return lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
+}
+template <int K, class R>
+__device__ inline R href3_pair(R sgn, int c, R E, const R* u) {
+  constexpr int i = 2 * K - 1;
+  const R wi = (R)Lat<3>::w(i);
+  const R cu = sgn * ((R)Lat<3>::cx(i) * u[0] + (R)Lat<3>::cy(i) * u[1] + (R)Lat<3>::cz(i) * u[2]);
+  return wi * E + 3 * wi * (E + (c < 3 ? (R)1 : (R)0)) * cu;
+}
+
 // D3Q19 anchor of node n, after the 16-bit populations of the buffer (it
 // ping-pongs with them): (p, u_x, u_y, u_z) as [N] float4, then (E_xx,
 // E_yy, E_zz, E_xy) as [N] float4, then (E_xz, E_yz) as [N] float2, each

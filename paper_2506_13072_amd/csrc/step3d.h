@@ -19,7 +19,11 @@
 // into registers.  A lane keeps the f it pulled for its own node and
 // collides it two planes later, so f crosses HBM once and h once.
 // Blocks are renumbered so that each XCD walks one contiguous run of tiles.
-// FP32 and FP64 storage; 16-bit storage is anchored and runs anchor3d.h.
+// 16-bit storage is anchored (layout.h): each pulled value is rebuilt from
+// its 16-bit deviation and the reference of its writer's FP32 anchor (a
+// global load, mostly from L2), and the stored values are deviations from
+// the node's new anchor (E = the conformation moment the h collision
+// produces, the pressure, u), which the even lane stores.
 #pragma once
 
 #include "kernels.h"
@@ -31,8 +35,8 @@ namespace vflb {
 // 128: 31.9 ms per step (same box)
 constexpr int kStep3dChunk = 16;
 
-// conversion between the storage type and the arithmetic type (FP32 and
-// FP64 storage: 16-bit D3Q19 storage is anchored and runs anchor3d.h)
+// conversion between the storage type and the arithmetic type (scale: the
+// exact power of two of FP16 storage; unused otherwise)
 template <class S> struct Cvt;
 template <> struct Cvt<double> {
   using V = double;
@@ -43,6 +47,16 @@ template <> struct Cvt<float> {
   using V = float;
   __device__ static float in(V v, float) { return v; }
   __device__ static V out(float v, float) { return v; }
+};
+template <> struct Cvt<_Float16> {
+  using V = _Float16;
+  __device__ static float in(V v, float inv_scale) { return (float)v * inv_scale; }
+  __device__ static V out(float v, float scale) { return (_Float16)(v * scale); }
+};
+template <> struct Cvt<bf16_t> {
+  using V = uint16_t;
+  __device__ static float in(V v, float) { return bf16_to_f32(v); }
+  __device__ static V out(float v, float) { return f32_to_bf16(v); }
 };
 
 // Access to the D3Q19 population buffer by pair: k = 0 is the rest plane
@@ -199,14 +213,13 @@ __device__ inline void dma_to_lds(const void* src, void* wave_block) {
 // issued one plane ahead of their use: per wave and pair the lane slots of
 // the h tuples, the rest f and the previous-step source state.  A lane reads
 // back only what it loaded itself.
-template <class S, int TY> struct Stage3;
+template <class S, int TY> struct Stage3 {};  // FP64, 16-bit: loads straight to registers
 template <int TY> struct Stage3<float, TY> {
   float4 h4[TY][10][64];
   float h2[2][TY][10][64];
   float f0[TY][64];
   float aux[9][TY][64];
 };
-template <int TY> struct Stage3<double, TY> {};  // FP64 loads straight to registers
 
 template <class S, int TY, bool WALLS>
 __device__ inline void stage_issue(Stage3<S, TY>& st, const S* pin, const typename StoreT<S>::R* aux,
@@ -248,16 +261,17 @@ __device__ inline R stage_read_f0(const Stage3<S, TY>& st, uint32_t, int ty, int
 // Tiles are walked by full tiles (FULL: every lane owns a lattice node, so
 // no load or store is lane-conditional) and ragged tiles (the rest) in two
 // launches of the same code; a block whose tile is of the other kind returns.
-// FP64 state does not fit 256 VGPRs: it runs one wave per SIMD, which opens
-// the accumulation registers to the allocator instead of scratch memory.
+// FP64 state and the anchored 16-bit step do not fit 256 VGPRs: they run one
+// wave per SIMD, which opens the accumulation registers to the allocator
+// instead of scratch memory.
 template <class S, int TY, int ZC, bool WALLS, bool FULL>
-__global__ void __launch_bounds__(64 * TY, sizeof(S) == 8 ? 1 : 2)
+__global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchored) ? 1 : 2)
     step3d_kernel(StepArgs<S> a, int ntx, int nty) {
-  static_assert(!StoreT<S>::kAnchored, "16-bit D3Q19 storage is anchored (anchor3d.h)");
   using R = typename StoreT<S>::R;
   using PA = Pair3<S>;
   using L = Lat<3>;
-  constexpr bool kDma = !std::is_same<S, double>::value;
+  constexpr bool kDma = std::is_same<S, float>::value;
+  constexpr bool ANCH = StoreT<S>::kAnchored;
   constexpr int NP = 10, NC = 6, TXN = 32, SX = TXN + 2, SY = TY + 2, NS = SX * SY;
   constexpr int H = 2 * SX + 2 * TY;  // ring nodes
   static_assert(2 * H <= 64 * TY, "ring needs more lanes than the workgroup has");
@@ -337,12 +351,28 @@ __global__ void __launch_bounds__(64 * TY, sizeof(S) == 8 ? 1 : 2)
     make_pair_pull(ox, oy, zw, s, g, pp);
     for_pairs<1>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      fo[k] = PA::load_f(pin, k, pair_src<k, WALLS>(pp, s, N32), N, a.inv_sf);
+      const uint32_t o = pair_src<k, WALLS>(pp, s, N32);
+      fo[k] = PA::load_f(pin, k, o, N, a.inv_sf);
+      if constexpr (ANCH) {  // + the reference of the writer (member o / N)
+        const bool m2 = o >= N32;
+        float pa, ua[3];
+        Anchor3::load_pu(pin, o - (m2 ? N32 : 0u), N, pa, ua);
+        const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
+        fo[k] += fref3_pair<k, R>(m2 ? (R)-1 : (R)1, (R)pa, uw);
+      }
     });
     make_pair_pull(hx, hy, zw, s, g, pp);
     for_pairs<1>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      fr[k] = PA::load_f(pin, k, pair_src<k, WALLS>(pp, s, N32), N, a.inv_sf);
+      const uint32_t o = pair_src<k, WALLS>(pp, s, N32);
+      fr[k] = PA::load_f(pin, k, o, N, a.inv_sf);
+      if constexpr (ANCH) {
+        const bool m2 = o >= N32;
+        float pa, ua[3];
+        Anchor3::load_pu(pin, o - (m2 ? N32 : 0u), N, pa, ua);
+        const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
+        fr[k] += fref3_pair<k, R>(m2 ? (R)-1 : (R)1, (R)pa, uw);
+      }
     });
   };
   // u = sum c f + F/2: each lane sums its members, the pair adds the halves
@@ -447,15 +477,33 @@ __global__ void __launch_bounds__(64 * TY, sizeof(S) == 8 ? 1 : 2)
       }
     } else {
       R h0[NC];
-      const R f0 = PA::load_f(pin, 0, n, N, a.inv_sf);
-      f[0] = s ? (R)0 : f0;
+      R f0 = PA::load_f(pin, 0, n, N, a.inv_sf);
       PA::load_h(pin, 0, n, N, a.inv_sh, h0);
+      if constexpr (ANCH) {  // the rest population's writer is the node itself
+        float pa, ua[3], Ea[6];
+        Anchor3::load(pin, n, N, pa, ua, Ea);
+        const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
+        f0 += fref3<R>(0, (R)pa, uw);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) h0[c] += href3<R>(0, c, (R)Ea[c], uw);
+      }
+      f[0] = s ? (R)0 : f0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) h[c][0] = s ? (R)0 : h0[c];
       for_pairs<1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         R hv[NC];
-        PA::load_h(pin, k, pair_src<k, WALLS>(pl, s, N32), N, a.inv_sh, hv);
+        const uint32_t o = pair_src<k, WALLS>(pl, s, N32);
+        PA::load_h(pin, k, o, N, a.inv_sh, hv);
+        if constexpr (ANCH) {
+          const bool m2 = o >= N32;
+          float pa, ua[3], Ea[6];
+          Anchor3::load(pin, o - (m2 ? N32 : 0u), N, pa, ua, Ea);
+          const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
+          const R sgw = m2 ? (R)-1 : (R)1;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) hv[c] += href3_pair<k, R>(sgw, c, (R)Ea[c], uw);
+        }
 #pragma unroll
         for (int c = 0; c < NC; ++c) h[c][k] = hv[c];
       });
@@ -573,10 +621,12 @@ __global__ void __launch_bounds__(64 * TY, sizeof(S) == 8 ? 1 : 2)
       const bool first = a.first != 0;
       const R omh = a.P.inv_tau_h, keeph = (R)1 - omh;
       const R sc = first ? (R)1 : (R)1.5, rc2 = first ? (R)0 : (R)0.5;
+      R En[NC];  // sum_i h*_i: the new anchor of anchored storage
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const R Ac = e[c] + (c < 3 ? (R)1 : (R)0);
         const R target = e[c] + chi[c] + (first ? (R)0 : (R)0.5 * (chi[c] - chip[c]));
+        En[c] = target;
         R k0[2], k1[2], k2[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -598,13 +648,40 @@ __global__ void __launch_bounds__(64 * TY, sizeof(S) == 8 ? 1 : 2)
       // ---- stores (the even lane holds the rest populations); chi (6
       // planes) then u (3 planes) split over the pair
       if (in_xy) {
-        if (s == 0)
-          PA::store(pout, 0, n, N, a.sf, a.sh, f[0], h[0][0], h[1][0], h[2][0], h[3][0], h[4][0],
-                    h[5][0]);
+        if constexpr (ANCH) {
+          // deviations from this node's new anchor (E, p, u)
+          float Ef[NC], uf[3];
 #pragma unroll
-        for (int k = 1; k < NP; ++k)
-          PA::store(pout, k, (s ? N32 : 0u) + n, N, a.sf, a.sh, f[k], h[0][k], h[1][k], h[2][k],
-                    h[3][k], h[4][k], h[5][k]);
+          for (int c = 0; c < NC; ++c) Ef[c] = (float)En[c];
+#pragma unroll
+          for (int bb = 0; bb < 3; ++bb) uf[bb] = (float)u[bb];
+          const float pf = (float)p;
+          const R ur[3] = {(R)uf[0], (R)uf[1], (R)uf[2]};
+          if (s == 0) {
+            R d[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) d[c] = h[c][0] - href3<R>(0, c, (R)Ef[c], ur);
+            PA::store(pout, 0, n, N, a.sf, a.sh, f[0] - fref3<R>(0, (R)pf, ur), d[0], d[1], d[2],
+                      d[3], d[4], d[5]);
+            Anchor3::store(pout, n, N, pf, uf, Ef);
+          }
+          for_pairs<1>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            R d[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) d[c] = h[c][k] - href3_pair<k, R>(sg, c, (R)Ef[c], ur);
+            PA::store(pout, k, (s ? N32 : 0u) + n, N, a.sf, a.sh,
+                      f[k] - fref3_pair<k, R>(sg, (R)pf, ur), d[0], d[1], d[2], d[3], d[4], d[5]);
+          });
+        } else {
+          if (s == 0)
+            PA::store(pout, 0, n, N, a.sf, a.sh, f[0], h[0][0], h[1][0], h[2][0], h[3][0],
+                      h[4][0], h[5][0]);
+#pragma unroll
+          for (int k = 1; k < NP; ++k)
+            PA::store(pout, k, (s ? N32 : 0u) + n, N, a.sf, a.sh, f[k], h[0][k], h[1][k],
+                      h[2][k], h[3][k], h[4][k], h[5][k]);
+        }
         const R item[9] = {chi[0], chi[1], chi[2], chi[3], chi[4], chi[5], u[0], u[1], u[2]};
 #pragma unroll
         for (int j = 0; j < 5; ++j) {

@@ -15,7 +15,6 @@
 #include "kernels.h"
 #include "step2d.h"
 #include "step3d.h"
-#include "anchor3d.h"
 #include "internal.h"
 
 using namespace vflb;
@@ -260,19 +259,6 @@ vflb_status launch_tiled(vflb_sim* s, hipStream_t st, StepArgs<S> a) {
           break;
       }
     }
-  } else if constexpr (StoreT<S>::kAnchored) {
-    // anchored 16-bit storage: same-time velocity, then the step
-    using R = typename StoreT<S>::R;
-    R* U = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + aux_u_words(s);
-    const dim3 grid((s->nx + 255) / 256, s->ny < 65535 ? s->ny : 65535,
-                    s->nz < 65535 ? s->nz : 65535);
-    hipLaunchKernelGGL((anchor3_velocity_kernel<S>), grid, dim3(256), 0, st, a.pin, a.g, a.F,
-                       a.inv_sf, U);
-    const int nty = (s->ny + A3_TY - 1) / A3_TY;
-    const dim3 grid_step((s->nx + A3_TX - 1) / A3_TX, nty < 65535 ? nty : 65535,
-                         s->nz < 65535 ? s->nz : 65535);
-    hipLaunchKernelGGL((anchor3_step_kernel<S>), grid_step, dim3(A3_TX, A3_TY), 0, st, a,
-                       (const R*)U);
   } else {
     constexpr int ZC = kStep3dChunk;
     const int ty = tile_y_3d(s);
@@ -565,9 +551,8 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
       anchored ? (lattice == VFLB_D2Q9 ? Anchor2::bytes(N) : Anchor3::bytes(N)) : sb * words);
   if (inplace) s->bytes[VFLB_BUF_POP1] = 256;  // unused
   // AUX: chi(t-1), u(t-1); the stress-divergence scheme adds tau_p [3][N]
-  // and div tau_p [2][N]; in-place streaming u(t) [2][N], anchored D3Q19
-  // storage u(t) [3][N]
-  const size_t u_now = inplace ? 2 : (anchored && lattice == VFLB_D3Q19 ? 3 : 0);
+  // and div tau_p [2][N]; in-place streaming u(t) [2][N]
+  const size_t u_now = inplace ? 2 : 0;
   s->bytes[VFLB_BUF_AUX] = align256(
       ab * ((s->NC + s->D) + (scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? 5 : 0) + u_now) * N);
   s->bytes[VFLB_BUF_SNAP] = align256(ab * (s->NC + s->D) * N);

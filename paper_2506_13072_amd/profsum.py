@@ -60,7 +60,7 @@ def kernel_stats(directory, kernel):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--kernel", required=True)
-    ap.add_argument("--sources", required=True, choices=["step2d", "step3d", "anchor3d"],
+    ap.add_argument("--sources", required=True, choices=["step2d", "step3d"],
                     help="which kernel's sources the record describes")
     ap.add_argument("--stats", required=True)
     ap.add_argument("--fetch", required=True)
