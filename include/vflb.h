@@ -291,8 +291,9 @@ vflb_status vflb_load(vflb_sim *sim, const void *dev_blob, size_t n);
 
 /* Block height of the step kernel: D2Q9 tiles of 64 x tile_y nodes,
  * tile_y in {4, 8, 16}; D3Q19 columns of 32 x tile_y nodes, tile_y in
- * {4, 8}.  0 restores the built-in choice.  EINVAL for other values.
- * Results do not depend on it (bitwise for D2Q9). */
+ * {4, 8} (4 only with 16-bit storage).  0 restores the built-in choice.
+ * EINVAL for other values.  Results do not depend on it (bitwise for
+ * D2Q9). */
 vflb_status vflb_set_tile(vflb_sim *sim, int tile_y);
 
 /* Bandwidth probe: copies nbytes (a multiple of 16) from src to dst, both

@@ -20,10 +20,11 @@
 // collides it two planes later, so f crosses HBM once and h once.
 // Blocks are renumbered so that each XCD walks one contiguous run of tiles.
 // 16-bit storage is anchored (layout.h): each pulled value is rebuilt from
-// its 16-bit deviation and the reference of its writer's FP32 anchor (a
-// global load, mostly from L2), and the stored values are deviations from
-// the node's new anchor (E = the conformation moment the h collision
-// produces, the pressure, u), which the even lane stores.
+// its 16-bit deviation and the reference of its writer's FP32 anchor (read
+// from an LDS stage of the anchors around the tile, AnchorStage), and the
+// stored values are deviations from the node's new anchor (E = the
+// conformation moment the h collision produces, the pressure, u), which the
+// even lane stores.
 #pragma once
 
 #include "kernels.h"
@@ -258,6 +259,21 @@ __device__ inline R stage_read_f0(const Stage3<S, TY>& st, uint32_t, int ty, int
   return st.f0[ty][tx];
 }
 
+// Anchored 16-bit storage: the anchors of six consecutive planes of the
+// tile and a two-node ring in x and y (planes z - 2 .. z + 3 while plane z
+// collides: the h pulls of plane z reach z - 1 .. z + 1, the look-ahead f
+// pulls of plane z + 2 reach z + 1 .. z + 3 and, from the ring nodes, two
+// nodes beyond the tile), loaded by LDS-DMA one plane ahead.  Every pulled
+// value takes its writer's reference from here.
+template <bool ANCH, int TY> struct AnchorStage {};
+template <int TY> struct AnchorStage<true, TY> {
+  static constexpr int AX = 32 + 4, AY = TY + 4, NA = AX * AY;
+  float4 pu[6][NA];  // p, u
+  float4 e4[6][NA];  // E_xx, E_yy, E_zz, E_xy
+  float e5[6][NA];   // E_xz
+  float e6[6][NA];   // E_yz
+};
+
 // Tiles are walked by full tiles (FULL: every lane owns a lattice node, so
 // no load or store is lane-conditional) and ragged tiles (the rest) in two
 // launches of the same code; a block whose tile is of the other kind returns.
@@ -277,6 +293,7 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   static_assert(2 * H <= 64 * TY, "ring needs more lanes than the workgroup has");
   __shared__ R ring[3][3][NS];
   __shared__ Stage3<S, TY> st;
+  __shared__ AnchorStage<ANCH, TY> as;
 
   const Geo g = a.g;
   const S* __restrict__ pin = a.pin;
@@ -315,6 +332,9 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   const int ox = clampc(wx, g.nx), oy = clampc(wy, g.ny);
   bool hxy = false;
   int hx = ox, hy = oy, hslot = 0;
+  // positions in the anchor stage (two-node ring): own column, ring node
+  const int alx = (tx >> 1) + 2, aly = ty + 2;
+  int hlx = alx, hly = aly;
   if (tid < 2 * H) {
     const int r = tid >> 1;
     int sxl, syl;
@@ -323,6 +343,8 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
     else if (r < 2 * SX + TY) { sxl = 0; syl = 1 + r - 2 * SX; }
     else { sxl = SX - 1; syl = 1 + r - 2 * SX - TY; }
     hslot = syl * SX + sxl;
+    hlx = sxl + 1;
+    hly = syl + 1;
     hx = x0 - 1 + sxl;
     hy = y0 - 1 + syl;
     hxy = wrap_coord(hx, g.nx, g.walls & 1) && wrap_coord(hy, g.ny, g.walls & 2);
@@ -343,6 +365,42 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
     int zw = zp;
     return wrap_coord(zw, g.nz, g.walls & 4);
   };
+  // anchored storage: the anchors of plane zp (tile and two-node ring) into
+  // its stage slot by LDS-DMA; a lane's slot index follows its lane number,
+  // so each wave fills one contiguous run of slots
+  auto anc_slot = [](int zp) { return ((zp % 6) + 6) % 6; };
+  auto anc_issue = [&](int zp) {
+    if constexpr (ANCH) {
+      using AS = AnchorStage<true, TY>;
+      const int sl = anc_slot(zp), zw = load_z(zp);
+      const char* base = reinterpret_cast<const char*>(pin) + Anchor3::offset(N);
+#pragma unroll
+      for (int r = 0; r * 64 * TY < AS::NA; ++r) {
+        const int k0 = r * 64 * TY + ty * 64, k = k0 + tx;
+        if (k < AS::NA) {
+          int cx = x0 - 2 + k % AS::AX, cy = y0 - 2 + k / AS::AX;
+          wrap_coord(cx, g.nx, g.walls & 1);
+          wrap_coord(cy, g.ny, g.walls & 2);
+          const size_t nd = node_of(clampc(cx, g.nx), clampc(cy, g.ny), zw, g);
+          dma_to_lds<16>(base + 16 * nd, &as.pu[sl][k0]);
+          dma_to_lds<16>(base + Anchor3::off1(N) + 16 * nd, &as.e4[sl][k0]);
+          dma_to_lds<4>(base + Anchor3::off2(N) + 8 * nd, &as.e5[sl][k0]);
+          dma_to_lds<4>(base + Anchor3::off2(N) + 8 * nd + 4, &as.e6[sl][k0]);
+        }
+      }
+    }
+  };
+  // stage index of the writer of this lane's member of pair K, for a node at
+  // stage position (lx, ly) in plane zp: the node itself after a bounce-back
+  // (the pulled offset names the other member), else the node at -c
+  auto anc_at = [&](auto kc, uint32_t o, int lx, int ly, int zp, int& sl) {
+    constexpr int K = decltype(kc)::value, i = 2 * K - 1;
+    const bool bounce = (o >= N32) != (s != 0);
+    const int cx = s ? -L::cx(i) : L::cx(i), cy = s ? -L::cy(i) : L::cy(i),
+              cz = s ? -L::cz(i) : L::cz(i);
+    sl = anc_slot(bounce ? zp : zp - cz);
+    return bounce ? ly * (TXN + 4) + lx : (ly - cy) * (TXN + 4) + lx - cx;
+  };
   // moving f of plane zp streamed into the own column (fo) and the ring
   // node (fr), for every lane
   auto pull_plane = [&](int zp, R* fo, R* fr) {
@@ -354,11 +412,11 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       const uint32_t o = pair_src<k, WALLS>(pp, s, N32);
       fo[k] = PA::load_f(pin, k, o, N, a.inv_sf);
       if constexpr (ANCH) {  // + the reference of the writer (member o / N)
-        const bool m2 = o >= N32;
-        float pa, ua[3];
-        Anchor3::load_pu(pin, o - (m2 ? N32 : 0u), N, pa, ua);
-        const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
-        fo[k] += fref3_pair<k, R>(m2 ? (R)-1 : (R)1, (R)pa, uw);
+        int sl;
+        const int ks = anc_at(kc, o, alx, aly, zp, sl);
+        const float4 q = as.pu[sl][ks];
+        const R uw[3] = {(R)q.y, (R)q.z, (R)q.w};
+        fo[k] += fref3_pair<k, R>(o >= N32 ? (R)-1 : (R)1, (R)q.x, uw);
       }
     });
     make_pair_pull(hx, hy, zw, s, g, pp);
@@ -367,11 +425,11 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       const uint32_t o = pair_src<k, WALLS>(pp, s, N32);
       fr[k] = PA::load_f(pin, k, o, N, a.inv_sf);
       if constexpr (ANCH) {
-        const bool m2 = o >= N32;
-        float pa, ua[3];
-        Anchor3::load_pu(pin, o - (m2 ? N32 : 0u), N, pa, ua);
-        const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
-        fr[k] += fref3_pair<k, R>(m2 ? (R)-1 : (R)1, (R)pa, uw);
+        int sl;
+        const int ks = anc_at(kc, o, hlx, hly, zp, sl);
+        const float4 q = as.pu[sl][ks];
+        const R uw[3] = {(R)q.y, (R)q.z, (R)q.w};
+        fr[k] += fref3_pair<k, R>(o >= N32 ? (R)-1 : (R)1, (R)q.x, uw);
       }
     });
   };
@@ -426,6 +484,11 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
     make_pair_pull(ox, oy, zs, s, g, pq);
     stage_issue<S, TY, WALLS>(st, pin, aux, pq, s, N, a.first != 0, ty);
   }
+  if constexpr (ANCH) {  // anchors of planes zs - 2 .. zs + 3
+    for (int zp = zs - 2; zp <= zs + 3; ++zp) anc_issue(zp);
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    lds_barrier();
+  }
   R fz[NP], fn[NP], frn[NP];
   {
     R fa[NP];
@@ -440,7 +503,12 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   for (int z = zs; z < ze; ++z) {
     // everything issued during the previous plane has landed: LDS-DMA loads
     // need not retire in order with other memory operations
-    if constexpr (kDma) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    if constexpr (kDma || ANCH) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    if constexpr (ANCH) {
+      lds_barrier();  // the anchors of plane z + 3 (issued a plane ago) are in
+      // plane z - 2 is no longer read: its slot takes plane z + 4
+      if (z + 1 < ze) anc_issue(z + 4);
+    }
     publish_u(z + 1, fn, frn);
     PairPull pl;
     make_pair_pull(ox, oy, z, s, g, pl);
@@ -475,17 +543,18 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
         make_pair_pull(ox, oy, z + 1, s, g, pq);
         stage_issue<S, TY, WALLS>(st, pin, aux, pq, s, N, a.first != 0, ty);
       }
-    } else {
+    } else {  // FP64 and 16-bit: plane z straight to registers
       R h0[NC];
       R f0 = PA::load_f(pin, 0, n, N, a.inv_sf);
       PA::load_h(pin, 0, n, N, a.inv_sh, h0);
       if constexpr (ANCH) {  // the rest population's writer is the node itself
-        float pa, ua[3], Ea[6];
-        Anchor3::load(pin, n, N, pa, ua, Ea);
-        const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
-        f0 += fref3<R>(0, (R)pa, uw);
+        const int sl = anc_slot(z), ks = aly * (TXN + 4) + alx;
+        const float4 q = as.pu[sl][ks], e = as.e4[sl][ks];
+        const R uw[3] = {(R)q.y, (R)q.z, (R)q.w};
+        const R Ew[6] = {(R)e.x, (R)e.y, (R)e.z, (R)e.w, (R)as.e5[sl][ks], (R)as.e6[sl][ks]};
+        f0 += fref3<R>(0, (R)q.x, uw);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) h0[c] += href3<R>(0, c, (R)Ea[c], uw);
+        for (int c = 0; c < NC; ++c) h0[c] += href3<R>(0, c, Ew[c], uw);
       }
       f[0] = s ? (R)0 : f0;
 #pragma unroll
@@ -495,14 +564,15 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
         R hv[NC];
         const uint32_t o = pair_src<k, WALLS>(pl, s, N32);
         PA::load_h(pin, k, o, N, a.inv_sh, hv);
-        if constexpr (ANCH) {
-          const bool m2 = o >= N32;
-          float pa, ua[3], Ea[6];
-          Anchor3::load(pin, o - (m2 ? N32 : 0u), N, pa, ua, Ea);
-          const R uw[3] = {(R)ua[0], (R)ua[1], (R)ua[2]};
-          const R sgw = m2 ? (R)-1 : (R)1;
+        if constexpr (ANCH) {  // + the reference of the writer (member o / N)
+          int sl;
+          const int ks = anc_at(kc, o, alx, aly, z, sl);
+          const float4 q = as.pu[sl][ks], e = as.e4[sl][ks];
+          const R uw[3] = {(R)q.y, (R)q.z, (R)q.w};
+          const R Ew[6] = {(R)e.x, (R)e.y, (R)e.z, (R)e.w, (R)as.e5[sl][ks], (R)as.e6[sl][ks]};
+          const R sgw = o >= N32 ? (R)-1 : (R)1;
 #pragma unroll
-          for (int c = 0; c < NC; ++c) hv[c] += href3_pair<k, R>(sgw, c, (R)Ea[c], uw);
+          for (int c = 0; c < NC; ++c) hv[c] += href3_pair<k, R>(sgw, c, Ew[c], uw);
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) h[c][k] = hv[c];

@@ -268,12 +268,18 @@ vflb_status launch_tiled(vflb_sim* s, hipStream_t st, StepArgs<S> a) {
     // full tiles and ragged tiles run as two launches of one kernel
     const bool any_full = s->nx >= 32 && s->ny >= ty;
     const bool any_ragged = s->nx % 32 != 0 || s->ny % ty != 0;
-    if (ty == 8) {
-      if (s->walls)
-        launch_step3d<S, 8, ZC, true>(grid, st, a, ntx, nty, any_full, any_ragged);
-      else
-        launch_step3d<S, 8, ZC, false>(grid, st, a, ntx, nty, any_full, any_ragged);
+    bool eight = ty == 8;
+    if constexpr (!StoreT<S>::kAnchored) {  // anchored 16-bit: 32 x 4 only (LDS)
+      if (eight) {
+        if (s->walls)
+          launch_step3d<S, 8, ZC, true>(grid, st, a, ntx, nty, any_full, any_ragged);
+        else
+          launch_step3d<S, 8, ZC, false>(grid, st, a, ntx, nty, any_full, any_ragged);
+      }
     } else {
+      eight = false;
+    }
+    if (!eight) {
       if (s->walls)
         launch_step3d<S, 4, ZC, true>(grid, st, a, ntx, nty, any_full, any_ragged);
       else
@@ -730,6 +736,9 @@ vflb_status vflb_set_tile(vflb_sim* s, int tile_y) {
   if (s->is_view) return fail(s, VFLB_EINVAL, "set the tile shape on the batch");
   if (tile_y != 0 && tile_y != 4 && tile_y != 8 && (tile_y != 16 || s->D == 3))
     return fail(s, VFLB_EINVAL, "tile_y must be 0, 4, 8 or 16 (D2Q9), 0, 4 or 8 (D3Q19)");
+  if (s->D == 3 && tile_y == 8 && (s->storage == VFLB_F16S || s->storage == VFLB_BF16S))
+    return fail(s, VFLB_EINVAL,
+                "anchored 16-bit D3Q19 storage runs 32 x 4 tiles (its LDS stages would not fit 8 rows)");
   s->tile_y = tile_y;
   drop_graphs(s);
   return VFLB_OK;
