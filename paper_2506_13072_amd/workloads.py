@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs shared by the tests, the benchmark and the drivers.
+"""Seeded synthetic inputs shared by the tests, the benchmark and the workflows.
 
 This module holds no arithmetic of the method: only workload descriptions in
 the paper's dimensionless terms (Sec. 3), seeded random draws and smooth
