@@ -52,6 +52,23 @@ def test_create_validates_arguments_on_host(lib):
     assert not h.value
 
 
+def test_create_rejects_sizes_and_options_not_built(lib):
+    h = ctypes.c_void_p()
+    mk = lambda *a: lib.vflb_create_ex(*a, None, ctypes.byref(h))
+    # D3Q19 node limits of the 32-bit plane offsets: 2^26 FP64, 2^27 FP32,
+    # 2^28 16-bit
+    assert mk(3, 512, 512, 257, 0, 0, 0) == 1
+    assert mk(3, 512, 512, 513, 1, 0, 0) == 1
+    assert mk(3, 1024, 512, 513, 2, 0, 0) == 1
+    assert b"exceeds" in lib.vflb_last_error(None)
+    assert mk(2, 8, 8, 1, 1, 0, 2) == 1              # unknown option bit
+    assert mk(3, 8, 8, 8, 1, 0, 1) == 1              # in place: D2Q9 only
+    assert mk(2, 8, 8, 1, 2, 0, 1) == 1              # in place: not 16-bit
+    assert mk(3, 8, 8, 8, 1, 1, 0) == 1              # comparison scheme: D2Q9 only
+    assert mk(2, 8, 8, 1, 1, 5, 0) == 1              # unknown scheme
+    assert not h.value
+
+
 def test_python_binding_refuses_missing_library(monkeypatch, tmp_path):
     from paper_2506_13072_amd import vflb
     monkeypatch.setattr(vflb, "_lib", None)

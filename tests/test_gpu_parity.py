@@ -516,3 +516,38 @@ def test_anchored_16bit_d3q19_graphs_and_checkpoints_bitwise(V):
     c.step(9)
     for k in (V.FIELD_F, V.FIELD_H):
         assert np.array_equal(b.read(k), c.read(k)), k
+
+
+# ------------------------------------------------- degenerate cases
+# beta = 1: no polymer (eta_p = 0, f^B = 0; the conformation still advects);
+# lattices one node thin along an axis (every pull wraps onto the node).
+@pytest.mark.parametrize("d,shape,walls,force", [
+    (2, (37, 70), (0, 1, 0), "const"),
+    (3, (6, 7, 8), (0, 0, 1), "const"),
+])
+def test_newtonian_limit_fp64_parity(V, d, shape, walls, force):
+    o, g = setup_pair(V, d, shape, "f64", walls, force, beta=1.0, init="smooth", seed=13)
+    assert g.lattice_params()["eta_p"] == 0.0
+    o.step(60)
+    g.step(60)
+    compare(o, g, 1e-12, fields=("u", "p", "Ae"))
+    assert np.abs(g.moments()["tau"]).max() == 0.0
+
+
+THIN = [
+    (2, (8, 1), "f64", False, 1e-12),
+    (2, (1, 9), "f64", False, 1e-12),
+    (2, (1, 9), "f32", True, 1e-5),
+    (3, (8, 1, 1), "f64", False, 1e-12),
+    (3, (1, 5, 1), "f64", False, 1e-12),
+    (3, (1, 1, 6), "f16s", False, 1e-3),
+]
+
+
+@pytest.mark.parametrize("d,shape,storage,inplace,tol", THIN)
+def test_one_node_thin_lattices(V, d, shape, storage, inplace, tol):
+    o, g = setup_pair(V, d, shape, storage, (0, 0, 0), "const", init="smooth", seed=14,
+                      inplace=inplace)
+    o.step(40)
+    g.step(40)
+    compare(o, g, tol, fields=("u", "tau", "Ae"))
