@@ -62,9 +62,14 @@ typedef enum { VFLB_D2Q9 = 2, VFLB_D3Q19 = 3 } vflb_lattice;
 /* Storage of the populations.  Arithmetic is FP64 for VFLB_F64 and FP32
  * otherwise.  The conformation populations are stored shifted by their rest
  * value w_i delta_ab (so A - I is their plain sum); the velocity populations
- * have rest value 0 in this incompressible model.  VFLB_F16S stores the
- * shifted values times a power of two (vflb_set_storage_scale), VFLB_BF16S
- * stores them unscaled; both round to nearest even. */
+ * have rest value 0 in this incompressible model.  The 16-bit storages are
+ * anchored: every node also keeps an FP32 anchor (A - I, pressure and
+ * velocity of its last update), and a stored population is the 16-bit
+ * deviation of the value from the equilibrium-form reference built from
+ * the anchor of the node that wrote it, so that A and u live in FP32.
+ * VFLB_F16S stores the deviations times a power of two
+ * (vflb_set_storage_scale), VFLB_BF16S stores them unscaled; both round to
+ * nearest even.  With 16-bit storage, D3Q19 runs 32 x 4 tiles. */
 typedef enum {
   VFLB_F64 = 0,
   VFLB_F32 = 1,
