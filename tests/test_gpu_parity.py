@@ -140,6 +140,19 @@ def test_fp32_parity_four_roll_64(V, storage, tol):
     compare(o, g, tol, fields=("u", "tau", "Ae"))
 
 
+def test_four_roll_64_fp64_10000_steps(V):
+    # the small reference case: 64^2 four-roll mill from rest, Re = 1,
+    # Wi = 1, beta = 0.5, U0 = 0.01, FP64, 10 000 steps (about 9.8 lambda)
+    o, g = setup_pair(V, 2, (64, 64), "f64", (0, 0, 0), "four_roll", Re=1.0, Wi=1.0,
+                      beta=0.5, U0=0.01, L=64 / (2 * np.pi))
+    o.step(10000)
+    g.step(10000)
+    compare(o, g, 1e-12, fields=("u", "tau", "Ae"))   # measured 1e-13 .. 2e-13
+    # the pressure is O(U0^2), 1e-4 of |u|: its relative error (measured
+    # 1.7e-12) is an absolute error of order 1e-16
+    compare(o, g, 1e-11, fields=("p",))
+
+
 @pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16s", 1e-3), ("bf16s", 1e-3)])
 def test_reduced_storage_smooth_state(V, storage, tol):
     o, g = setup_pair(V, 2, (37, 70), storage, (0, 1, 0), "const", init="smooth", seed=9,
