@@ -147,3 +147,50 @@ def test_channel_8192x1024_holds_the_analytic_poiseuille_state(V):
     # measured: u 1.3e-4, v 7e-6, A_xx and A_xy 1.7e-4 (the equilibrium-only
     # start lacks the non-equilibrium parts of the populations)
     assert du < 5e-4 and dv < 1e-4 and dxx < 1e-3 and dxy < 1e-3, (du, dv, dxx, dxy)
+
+
+def test_tgv_64_kinetic_energy_decay_and_conservation(V):
+    # The 3D Taylor-Green vortex with the benchmark's parameters on a 64^3
+    # copy: the GPU's FP64 reductions of the kinetic energy follow the FP64
+    # oracle's as the vortex decays, for FP32 and anchored FP16 storage,
+    # and mass and momentum stay at their initial values.
+    import math
+    w = WL.TGV_512
+    n = 64
+    L = n / (2 * math.pi)
+    p_or = O.lattice_params(w["Re"], w["Wi"], w["beta"], w["U0"], L)
+    u = WL.taylor_green_3d_velocity(n, w["U0"])
+    x = 2 * np.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    p = ((w["U0"] ** 2 / 16) * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2)).ravel()
+    o = O.OracleSim(3, n, n, n)
+    o.set_params(p_or["tau_f"], 0.501, p_or["lam"], p_or["eta_p"])
+    o.init(u, None, p)
+    sims = {}
+    for storage in ("f32", "f16s"):
+        g = V.Sim(3, n, n, n, storage)
+        g.set_params(w["Re"], w["Wi"], w["beta"], w["U0"], L)
+        g.init_fields(u, None, p)
+        sims[storage] = g
+    C = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1],
+                  [0, 0, -1], [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1],
+                  [-1, 0, -1], [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1],
+                  [0, -1, 1]], float)
+    ke0 = None
+    for k in range(4):
+        o.step(10)
+        ke_o = 0.5 * float((o.moments()["u"] ** 2).sum()) / n ** 3  # per node, as reported
+        f = o.get_state()["f"]
+        m_o, p_o = float(f.sum()), f.sum(0) @ C  # totals, as reported
+        ke0 = ke0 or ke_o
+        for storage, g in sims.items():
+            g.step(10)
+            r = g.reduce()
+            # measured: KE 4.5e-8 (FP32) / 4.2e-7 (FP16) relative; mass and
+            # momentum totals over 262 144 nodes within 5e-6 / 6.3e-4
+            tol, ctol = (1e-6, 2e-5) if storage == "f32" else (1e-5, 2e-3)
+            dm, dp = abs(r["M"] - m_o), np.abs(np.array(r["P"]) - p_o).max()
+            print(storage, k, "KE rel %.2e  dM %.2e  dP %.2e" % (r["KE"] / ke_o - 1, dm, dp))
+            assert abs(r["KE"] / ke_o - 1) < tol, (storage, k, r["KE"], ke_o)
+            assert dm < ctol and dp < ctol, (storage, k, r["M"], m_o, r["P"], p_o)
+    assert ke_o < ke0  # the vortex decays
