@@ -322,6 +322,9 @@ def main():
                          "Taylor-Green vortex; ensemble: 256 four-roll lattices of "
                          "sides 64..512 as one batch (both reported, not the headline)")
     ap.add_argument("--instances", type=int, default=256)
+    ap.add_argument("--ws-side", type=int, default=64, help="warmstart: lattice side")
+    ap.add_argument("--ws-train", type=int, default=96, help="warmstart: training lattices")
+    ap.add_argument("--ws-test", type=int, default=16, help="warmstart: held-out lattices")
     ap.add_argument("--tgv-n", type=int, default=512)
     args = ap.parse_args()
     if args.copy_probe:
@@ -332,9 +335,10 @@ def main():
               "(the multi-GPU slab decomposition is not built)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "warmstart":
-        r = run_gpu_warmstart()
-        print(json.dumps({"metric": "time to steady state (R<1e-6), held-out four-roll 64x64, "
-                                    "steps summed over 16 lattices",
+        r = run_gpu_warmstart(n_train=args.ws_train, n_test=args.ws_test, side=args.ws_side)
+        print(json.dumps({"metric": f"time to steady state (R<1e-6), held-out four-roll "
+                                    f"{args.ws_side}x{args.ws_side}, steps summed over "
+                                    f"{args.ws_test} lattices",
                           "value": r["warm_steps"], "unit": "steps", "n_gpus": 1,
                           "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
                           "data": "synthetic", "cold_steps": r["cold_steps"],
