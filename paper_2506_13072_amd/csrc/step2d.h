@@ -76,7 +76,9 @@ struct Tile2Lds<R, TY, true> {
 template <class S, int TY>
 using Tile2LdsOf = Tile2Lds<typename StoreT<S>::R, TY, StoreT<S>::kAnchored>;
 
-template <class S, int TY, bool CLAMP = false>
+// NT: the tile's own pulls use non-temporal loads (single lattices; the
+// batched ensemble measured faster without)
+template <class S, int TY, bool CLAMP = false, bool NT = false>
 __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
                                    Tile2LdsOf<S, TY>& lds) {
   using R = typename StoreT<S>::R;
@@ -135,7 +137,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       R hv[NC];
-      P2::load(pin, pull2_index(i, p, N), N, a.inv_sf, a.inv_sh, f[i], hv);
+      P2::template load<NT>(pin, pull2_index(i, p, N), N, a.inv_sf, a.inv_sh, f[i], hv);
 #pragma unroll
       for (int c = 0; c < NC; ++c) h[c][i] = hv[c];
     }
@@ -306,7 +308,7 @@ template <class S, int TY, bool CLAMP = false>
 __global__ void __launch_bounds__(64 * TY) step2d_kernel(StepArgs<S> a, int ntx, int nty) {
   __shared__ Tile2LdsOf<S, TY> lds;
   (void)nty;
-  step2d_tile<S, TY, CLAMP>(a, (blockIdx.x % ntx) * 64, (blockIdx.x / ntx) * TY, lds);
+  step2d_tile<S, TY, CLAMP, true>(a, (blockIdx.x % ntx) * 64, (blockIdx.x / ntx) * TY, lds);
 }
 
 // ------------------------------------------- in-place (AA) streaming
