@@ -596,7 +596,10 @@ __global__ void __launch_bounds__(256) taup_kernel(const S* __restrict__ pin, Ge
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       R f, hv[3];
-      Pops<2, S>::load(pin, pull_index<2>(i, x, y, 0, g), N, (R)1, (R)1, f, hv);
+      if constexpr (StoreT<S>::kPlanar)
+        Pops<2, S>::load(pin, pull_index<2>(i, x, y, 0, g), N, (R)1, (R)1, f, hv);
+      else
+        Pops<2, S>::template load<true>(pin, pull_index<2>(i, x, y, 0, g), N, (R)1, (R)1, f, hv);
 #pragma unroll
       for (int c = 0; c < 3; ++c) e[c] += hv[c];
     }
