@@ -395,6 +395,14 @@ def main():
                               buffer_bytes=r["buffer_bytes"])
         tb, ip = rows["two_buffers"], rows["in_place"]
         ach = ip["achieved_GBps"]
+        # one in-place step is two launches (velocity pass, step): their
+        # measured bytes together
+        traffic = None
+        if args.storage == "f32" and not args.tile:
+            parts = [measured_traffic(f"aa_{k}_f32_channel_8192x1024.md", "step2d")
+                     for k in ("velocity", "step")]
+            if None not in parts:
+                traffic = sum(parts)
         print(json.dumps({"metric": "MLUPS (in-place AA streaming, D2Q9 channel)",
                           "value": ip["MLUPS"], "unit": "MLUPS", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup,
@@ -406,7 +414,11 @@ def main():
                                      "storage": args.storage, "nodes": nodes},
                           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                                       "traffic": None, "bytes_per_lup": ip["bytes_per_lup"]},
+                                       "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                                       "traffic_unit": "GB per step (both launches)",
+                                       "algorithmic_GB_per_step":
+                                           round(ip["bytes_per_lup"] * nodes / 1e9, 4),
+                                       "bytes_per_lup": ip["bytes_per_lup"]},
                           "layouts": rows,
                           "time_ratio_in_place_over_two_buffers":
                               round(ip["ms_per_step"] / tb["ms_per_step"], 4),
@@ -417,6 +429,9 @@ def main():
         r = run_gpu_ensemble(args.instances, args.steps, args.warmup, args.storage)
         bpl = bytes_per_lup(2, args.storage)
         ach = bpl * r["nodes"] / (r["step_ms"] / 1e3) / 1e9
+        traffic = None
+        if args.storage == "f32" and args.instances == 256:
+            traffic = measured_traffic("batch2d_f32_ensemble_256.md", "step2d")
         print(json.dumps({"metric": "MLUPS (batched fused stream-collide, D2Q9 ensemble)",
                           "value": round(r["MLUPS"], 1), "unit": "MLUPS", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup,
@@ -429,7 +444,10 @@ def main():
                                      "tile_y": r["tile"]},
                           "roofline": {"bound": "hbm", "achieved": round(ach, 1),
                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                       "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                                       "frac": round(ach / HBM_PEAK_GBS, 4),
+                                       "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                                       "traffic_unit": "GB per launch",
+                                       "algorithmic_GB_per_launch": round(bpl * r["nodes"] / 1e9, 4),
                                        "bytes_per_lup": bpl},
                           "unbatched_MLUPS": round(r.get("unbatched_MLUPS", 0.0), 1),
                           "nonfinite": r["nonfinite"]}), flush=True)
