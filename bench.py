@@ -235,6 +235,10 @@ def run_gpu_warmstart(n_train=96, n_test=16, side=64, tol=1e-6, iters=8000, K0=1
                 t_cold=res["seconds_cold_after_K0"], t_warm=res["seconds_warm_after_K0"])
 
 
+# storage modes with committed rocprofv3 records, and the tag in their names
+RECORD_TAG = {"f32": "f32", "f16s": "f16"}
+
+
 def measured_traffic(record, kernel):
     """HBM bytes per launch of the step kernel (FETCH_SIZE + WRITE_SIZE,
     scaled against the streaming-copy kernel) from a committed rocprofv3
@@ -458,8 +462,8 @@ def main():
         nodes = args.tgv_n ** 3
         ach = bpl * nodes / (r["step_ms"] / 1e3) / 1e9
         traffic = None
-        if args.storage == "f32" and args.tgv_n == 512 and not args.tile:
-            traffic = measured_traffic("step3d_f32_tgv_512.md", "step3d")
+        if args.storage in RECORD_TAG and args.tgv_n == 512 and not args.tile:
+            traffic = measured_traffic(f"step3d_{RECORD_TAG[args.storage]}_tgv_512.md", "step3d")
         print(json.dumps({"metric": "MLUPS (fused stream-collide, D3Q19)", "value": round(r["GLUPS"] * 1e3, 1),
                           "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": round(r["step_ms"], 4), "higher_is_better": True,
@@ -482,8 +486,9 @@ def main():
     bpl = bytes_per_lup(2, args.storage)
     achieved = bpl * nodes / (res["step_ms"] / 1e3) / 1e9
     traffic = None
-    if args.storage == "f32" and not args.tile:
-        traffic = measured_traffic("step2d_f32_channel_8192x1024.md", "step2d")
+    if args.storage in RECORD_TAG and not args.tile:
+        traffic = measured_traffic(f"step2d_{RECORD_TAG[args.storage]}_channel_8192x1024.md",
+                                   "step2d")
     out = {
         "metric": "MLUPS (fused stream-collide, D2Q9 Oldroyd-B fluctuating LB)",
         "value": round(mlups, 1),

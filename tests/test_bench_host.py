@@ -52,6 +52,8 @@ def test_measured_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("record", [
     "step2d_f32_channel_8192x1024.md",
+    "step2d_f16_channel_8192x1024.md",
+    "step3d_f16_tgv_512.md",
     "batch2d_f32_ensemble_256.md",
     "aa_step_f32_channel_8192x1024.md",
     "aa_velocity_f32_channel_8192x1024.md",
