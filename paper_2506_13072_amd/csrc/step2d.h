@@ -375,6 +375,7 @@ __global__ void __launch_bounds__(256) aa_step_kernel(StepArgs<S> a,
                                                       const typename StoreT<S>::R* __restrict__ U) {
   using R = typename StoreT<S>::R;
   constexpr int Q = 9, NC = 3;
+  constexpr bool kF64 = std::is_same<R, double>::value;
   using P2 = Pops<2, S>;
   const Geo g = a.g;
   S* __restrict__ pop = a.pout;
@@ -388,6 +389,9 @@ __global__ void __launch_bounds__(256) aa_step_kernel(StepArgs<S> a,
     make_pull2(x, y, g, p);
     R f[Q], h[NC][Q];
     R chip[NC] = {0, 0, 0}, up[2] = {0, 0};
+    // raised priority while the loads issue (measured on MI355X, 8192 x
+    // 1024 FP32: 0.576 -> 0.568 ms per in-place step; FP64 neutral)
+    if constexpr (!kF64) __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       R hv[NC];
@@ -399,6 +403,7 @@ __global__ void __launch_bounds__(256) aa_step_kernel(StepArgs<S> a,
     R F[3] = {0, 0, 0};
     force_at<R>(a.F, x, y, g.nx, g.ny, F);
     const R u[3] = {U[n], U[N + n], (R)0};
+    if constexpr (!kF64) __builtin_amdgcn_s_setprio(0);
     R e[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
