@@ -69,7 +69,11 @@ typedef enum { VFLB_D2Q9 = 2, VFLB_D3Q19 = 3 } vflb_lattice;
  * the anchor of the node that wrote it, so that A and u live in FP32.
  * VFLB_F16S stores the deviations times a power of two
  * (vflb_set_storage_scale), VFLB_BF16S stores them unscaled; both round to
- * nearest even.  With 16-bit storage, D3Q19 runs 32 x 4 tiles. */
+ * nearest even.  With 16-bit storage, D3Q19 runs 32 x 4 tiles.  D3Q19
+ * takes VFLB_F16S but not VFLB_BF16S: BF16's 8-bit mantissa leaves u and tau
+ * 2e-3 .. 7e-3 (relative L2) away from the FP64 iteration on coarse D3Q19
+ * lattices, above the 1e-3 accuracy of 16-bit storage, so vflb_create
+ * returns VFLB_EINVAL for it. */
 typedef enum {
   VFLB_F64 = 0,
   VFLB_F32 = 1,
@@ -183,7 +187,7 @@ typedef struct {
 /* Create a simulation of nx*ny*nz nodes (nz = 1 for D2Q9) whose work is
  * enqueued on hip_stream (a hipStream_t; NULL is the null stream).
  * *out receives a library-owned handle.  EINVAL for a bad lattice, storage
- * or size. */
+ * (BF16S on D3Q19 included) or size. */
 vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
                         void *hip_stream, vflb_sim **out);
 
@@ -401,14 +405,17 @@ vflb_status vflb_batch_step(vflb_batch *batch, int64_t nsteps);
  * out[14 i + 7], not as an error. */
 vflb_status vflb_batch_reduce(vflb_batch *batch, double *out);
 
-/* Run the active instances towards a steady state: every check_every steps
- * (fewer when a cap is closer) reduce and leave out each instance whose
- * residual R (vflb_reduce out[0]) fell below tol, whose step count reached
- * max_steps[i], or that became non-finite; repeat until none is active.
- * The tile table shrinks as instances leave.  Per instance: steps_out[i]
- * its time level, resid_out[i] its last residual, status_out[i] a
- * VFLB_RUN_* code.  A first reduction takes the residual snapshot when an
- * instance has none. */
+/* Run the active instances towards a steady state: a first reduction takes
+ * a fresh residual snapshot; then every check_every steps (fewer when a cap
+ * is closer) reduce and leave out each instance whose residual R
+ * (vflb_reduce out[0], the relative change of u and tau over the interval)
+ * fell below tol over a full interval of check_every steps, whose step
+ * count reached max_steps[i], or that became non-finite; repeat until none
+ * is active.  An interval shortened to stop another instance at its cap
+ * never counts as convergence.  The tile table shrinks as instances leave.
+ * Per instance: steps_out[i] its time level, resid_out[i] its residual over
+ * the last full interval (+inf when none completed; for a skipped instance
+ * its last reduction), status_out[i] a VFLB_RUN_* code. */
 vflb_status vflb_batch_run_until(vflb_batch *batch, double tol,
                                  int64_t check_every, const int64_t *max_steps,
                                  int64_t *steps_out, double *resid_out,

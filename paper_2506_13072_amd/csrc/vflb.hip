@@ -413,7 +413,7 @@ vflb_status dispatch(vflb_sim* s, A... args) {
     case VFLB_F64: return Op<3, double>::run(s, args...);
     case VFLB_F32: return Op<3, float>::run(s, args...);
     case VFLB_F16S: return Op<3, _Float16>::run(s, args...);
-    default: return Op<3, bf16_t>::run(s, args...);
+    default: return fail(s, VFLB_EINVAL, "no D3Q19 path for storage %d", s->storage);
   }
 }
 
@@ -523,6 +523,13 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
   if (lattice == VFLB_D3Q19 && N > ((size_t)1 << d3_log2_max))
     return fail(nullptr, VFLB_EINVAL, "D3Q19 lattice of %zu nodes exceeds 2^%d for this storage",
                 N, d3_log2_max);
+  // BF16 deviations carry an 8-bit mantissa: on D3Q19 lattices of 16^3
+  // they left u and tau 2e-3 .. 7e-3 away from the FP64 iteration, above
+  // the 1e-3 accuracy of 16-bit storage that FP16 meets
+  if (lattice == VFLB_D3Q19 && storage == VFLB_BF16S)
+    return fail(nullptr, VFLB_EINVAL,
+                "BF16 storage is not offered on D3Q19 (it misses the 1e-3 accuracy of 16-bit "
+                "storage there); use VFLB_F16S");
   if (scheme != VFLB_SCHEME_FLUCTUATING && scheme != VFLB_SCHEME_STRESS_DIVERGENCE)
     return fail(nullptr, VFLB_EINVAL, "unknown scheme %d", scheme);
   if (scheme == VFLB_SCHEME_STRESS_DIVERGENCE &&
@@ -618,6 +625,16 @@ vflb_status vflb_set_params(vflb_sim* s, const vflb_params* p) {
     return fail(s, VFLB_EINVAL, "Re, U0 and L must be positive");
   if (!(p->beta > 0) || !(p->beta <= 1))
     return fail(s, VFLB_EINVAL, "beta must lie in (0, 1]");
+  // FP16 scales: anchored storage holds deviations from a reference, the
+  // non-equilibrium parts O(U0 k) and below, scaled into FP16's normal range
+  int ef;
+  std::frexp(p->U0, &ef);
+  const int log2_sf = std::min(24, std::max(0, 10 - ef)), log2_sh = 12;
+  if (s->storage == VFLB_F16S && s->inited && (log2_sf != s->log2_sf || log2_sh != s->log2_sh))
+    return fail(s, VFLB_ESTATE,
+                "U0 = %g moves the FP16 storage scale (2^%d -> 2^%d) of initialised fields; "
+                "set the parameters before vflb_init_fields",
+                p->U0, s->log2_sf, log2_sf);
   vflb_lattice_params l;
   const double nu = p->U0 * p->L / p->Re;
   l.nu_s = p->beta * nu;
@@ -633,14 +650,8 @@ vflb_status vflb_set_params(vflb_sim* s, const vflb_params* p) {
   s->prm = *p;
   s->lp = l;
   s->have_params = true;
-  // FP16 scales: anchored storage holds deviations from a reference, the
-  // non-equilibrium parts O(U0 k) and below, scaled into FP16's normal range
-  int ef;
-  std::frexp(p->U0, &ef);
-  s->log2_sf = 10 - ef;
-  s->log2_sh = 12;
-  if (s->log2_sf < 0) s->log2_sf = 0;
-  if (s->log2_sf > 24) s->log2_sf = 24;
+  s->log2_sf = log2_sf;
+  s->log2_sh = log2_sh;
   drop_graphs(s);
   return VFLB_OK;
 }
@@ -725,6 +736,10 @@ vflb_status vflb_set_storage_scale(vflb_sim* s, int log2_f, int log2_h) {
   if (!s) return VFLB_EINVAL;
   if (log2_f < -40 || log2_f > 40 || log2_h < -40 || log2_h > 40)
     return fail(s, VFLB_EINVAL, "scale exponent out of range");
+  // the stored FP16 deviations are in the current scale: changing it under
+  // initialised fields would rescale them all by a power of two
+  if (s->storage == VFLB_F16S && s->inited && (log2_f != s->log2_sf || log2_h != s->log2_sh))
+    return fail(s, VFLB_ESTATE, "the FP16 storage scale is fixed once the fields are initialised");
   s->log2_sf = log2_f;
   s->log2_sh = log2_h;
   drop_graphs(s);
@@ -891,6 +906,7 @@ struct CkptHeader {
   uint64_t magic;
   int32_t D, nx, ny, nz, storage, pad;
   int64_t t;
+  int32_t log2_sf, log2_sh;  // FP16 storage scales the populations were written in
 };
 static const uint64_t kCkptMagic = 0x76666c62636b7074ull;
 
@@ -912,6 +928,8 @@ vflb_status vflb_save(vflb_sim* s, void* blob, size_t n) {
   h.D = s->D; h.nx = s->nx; h.ny = s->ny; h.nz = s->nz; h.storage = s->storage;
   h.pad = s->inplace ? 1 : 0;  // in place the layout follows the parity of t
   h.t = s->t;
+  h.log2_sf = s->log2_sf;
+  h.log2_sh = s->log2_sh;
   char* b = static_cast<char*>(blob);
   HIP_TRY(s, hipMemcpyAsync(b, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
   size_t off = 256;
@@ -946,6 +964,13 @@ vflb_status vflb_load(vflb_sim* s, const void* blob, size_t n) {
   HIP_TRY(s, hipStreamSynchronize(s->stream));
   s->cur = 0;
   s->t = h.t;
+  if (s->storage == VFLB_F16S &&
+      (h.log2_sf != s->log2_sf || h.log2_sh != s->log2_sh)) {
+    // the loaded deviations are in the checkpoint's scale: adopt it
+    s->log2_sf = h.log2_sf;
+    s->log2_sh = h.log2_sh;
+    drop_graphs(s);
+  }
   s->inited = true;
   s->snap_valid = false;
   return VFLB_OK;
@@ -1414,11 +1439,14 @@ vflb_status vflb_batch_run_until(vflb_batch* b, double tol, int64_t check_every,
   vflb_status rc = check_active(b, &t, &cur);
   if (rc != VFLB_OK) return rc;
   std::vector<double> red((size_t)14 * b->n);
+  // residual of the last interval of exactly check_every steps per instance
+  std::vector<double> full_R((size_t)b->n, INFINITY);
   for (int i = 0; i < b->n; ++i) status_out[i] = b->active[i] ? VFLB_RUN_ACTIVE : VFLB_RUN_SKIPPED;
-  bool need_snap = false;
-  for (int i = 0; i < b->n; ++i) need_snap = need_snap || (b->active[i] && !b->views[i]->snap_valid);
-  if (need_snap && (rc = vflb_batch_reduce(b, red.data())) != VFLB_OK) return rc;
+  // a fresh snapshot, so that every residual below spans a known interval
+  if ((rc = vflb_batch_reduce(b, red.data())) != VFLB_OK) return rc;
   for (;;) {
+    // the active instances share one time level, so one interval k; it is
+    // shortened only to stop an instance exactly at its cap
     int64_t k = check_every;
     for (int i = 0; i < b->n; ++i) {
       if (!b->active[i]) continue;
@@ -1435,11 +1463,15 @@ vflb_status vflb_batch_run_until(vflb_batch* b, double tol, int64_t check_every,
     if (!any) break;
     if ((rc = vflb_batch_step(b, k)) != VFLB_OK) return rc;
     if ((rc = vflb_batch_reduce(b, red.data())) != VFLB_OK) return rc;
+    // R is the relative change over the k steps just taken: it is held
+    // against tol only when they were a full check_every interval
+    const bool full = k == check_every;
     for (int i = 0; i < b->n; ++i) {
       if (!b->active[i]) continue;
       const double R = red[(size_t)14 * i], bad = red[(size_t)14 * i + 7];
+      if (full) full_R[i] = R;
       if (bad > 0) status_out[i] = VFLB_RUN_UNSTABLE;
-      else if (R < tol) status_out[i] = VFLB_RUN_CONVERGED;
+      else if (full && R < tol) status_out[i] = VFLB_RUN_CONVERGED;
       else if (b->views[i]->t >= max_steps[i]) status_out[i] = VFLB_RUN_CAPPED;
       else continue;
       vflb_batch_set_active(b, i, 0);
@@ -1447,7 +1479,7 @@ vflb_status vflb_batch_run_until(vflb_batch* b, double tol, int64_t check_every,
   }
   for (int i = 0; i < b->n; ++i) {
     steps_out[i] = b->views[i]->t;
-    resid_out[i] = b->last[(size_t)14 * i];
+    resid_out[i] = status_out[i] == VFLB_RUN_SKIPPED ? b->last[(size_t)14 * i] : full_R[i];
   }
   return VFLB_OK;
 }

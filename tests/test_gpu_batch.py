@@ -171,6 +171,43 @@ def test_run_until_compacts_and_freezes(V):
             assert np.array_equal(sb[k], sg[k]), (i, k, steps[i])
 
 
+def test_run_until_short_cap_does_not_shorten_the_residual_interval(V):
+    # R is the relative change over the steps since the last reduction.  A
+    # neighbour's cap at t = 120 forces a check after 20 steps; a residual
+    # over those 20 steps is smaller than over check_every = 100 and must
+    # not count as convergence.  The tolerance is placed between the two.
+    spec = SPECS[0]
+    probe = make_batch(V, specs=[spec])
+    probe.reduce()
+    probe.step(100)
+    probe.reduce()
+    probe.step(20)
+    r20 = probe.reduce()[0, 0]
+    probe.step(80)
+    r100 = probe.reduce()[0, 0]   # the 100 steps from t = 20 .. 120 would do too
+    assert 0 < r20 < r100
+    tol = float(np.sqrt(r20 * r100))
+    b = make_batch(V, specs=[spec, spec])
+    steps, res, status = b.run_until(tol=tol, check_every=100, max_steps=[120, 10_000])
+    assert status[0] == V.RUN_CAPPED and steps[0] == 120
+    # the long-running instance was checked at t = 100 (full), 120 (short),
+    # 220, ... and stops only where a full interval's residual is below tol
+    assert steps[1] > 120
+    assert status[1] in (V.RUN_CONVERGED, V.RUN_CAPPED)
+    if status[1] == V.RUN_CAPPED:
+        assert steps[1] == 10_000
+        return
+    assert res[1] < tol and (steps[1] - 120) % 100 == 0
+    # its residual over its last full interval, recomputed on a lone run
+    # (the batched reduction sums in another order: 1e-9)
+    g = V.Sim(2, spec[0][0], spec[0][1], 1, "f32")
+    configure(V, g, spec, seed=100)
+    g.step(int(steps[1]) - 100)
+    g.reduce()
+    g.step(100)
+    assert g.reduce()["R"] == pytest.approx(res[1], rel=1e-9)
+
+
 def test_batch_state_errors(V):
     b = make_batch(V, specs=SPECS[:2])
     with pytest.raises(V.VflbError):

@@ -196,6 +196,61 @@ def test_tgv_64_kinetic_energy_decay_and_conservation(V):
     assert ke_o < ke0  # the vortex decays
 
 
+TGV64_STEPS = 40
+
+
+@pytest.fixture(scope="module")
+def tgv_64_copy():
+    """The 512^3 Taylor-Green workload's lattice-unit parameters (tau_f,
+    lambda, eta_p of Re = 100, Wi = 0.5, beta = 0.9, U0 = 0.02,
+    L = 512/(2 pi)) on a 64^3 lattice holding the theta = 0 vortex and its
+    pressure; TGV64_STEPS steps of the FP64 oracle."""
+    w = WL.TGV_512
+    n = 64
+    p_or = O.lattice_params(w["Re"], w["Wi"], w["beta"], w["U0"], w["L"])
+    u = WL.taylor_green_3d_velocity(n, w["U0"])
+    x = 2 * np.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    p = ((w["U0"] ** 2 / 16) * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2)).ravel()
+    o = O.OracleSim(3, n, n, n)
+    o.set_params(p_or["tau_f"], 0.501, p_or["lam"], p_or["eta_p"])
+    o.init(u, None, p)
+    o.step(TGV64_STEPS)
+    mo = o.moments()
+    mo["Ae"] = mo["A"] - np.array([1, 1, 1, 0, 0, 0], float)
+    f = o.get_state()["f"]
+    # the pressure is summed from populations of the size of U0, while it is
+    # of the size of U0^2: its bar is the storage bar times that ratio
+    ratio = max(1.0, np.sqrt((np.abs(f[:, 1:]).sum(1) ** 2).mean()) /
+                np.sqrt((mo["p"] ** 2).mean()))
+    return dict(u=u, p=p, mo=mo, ratio=ratio, n=n, w=w)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16s", 1e-3)])
+def test_tgv_64_copy_per_field_parity(V, tgv_64_copy, storage, tol):
+    # per field u, p, tau, A - I against the oracle after TGV64_STEPS steps
+    # (relative L2, and the element-wise max over max for u, tau, A - I)
+    c = tgv_64_copy
+    n, w = c["n"], c["w"]
+    g = V.Sim(3, n, n, n, storage)
+    g.set_params(w["Re"], w["Wi"], w["beta"], w["U0"], w["L"])
+    g.init_fields(c["u"], None, c["p"])
+    g.step(TGV64_STEPS)
+    mg = g.moments()
+    mg["Ae"] = mg["A"] - np.array([1, 1, 1, 0, 0, 0], float)
+    out = {}
+    for k in ("u", "tau", "Ae", "p"):
+        bar = tol * (c["ratio"] if k == "p" else 1.0)
+        out[k] = AN.rel_l2(mg[k], c["mo"][k])
+        em = np.abs(mg[k] - c["mo"][k]).max() / np.abs(c["mo"][k]).max()
+        print(storage, k, "rel L2 %.2e  max %.2e  bar %.1e" % (out[k], em, bar))
+        assert out[k] <= bar, (storage, k, out[k], bar)
+        if k != "p":
+            # a single node may carry a few times the mean rounding error
+            assert em <= 10 * bar, (storage, k, em, bar)
+
+
 def test_channel_8192x1024_follows_the_analytic_womersley_state(V):
     # Oldroyd-B Womersley flow (Sec. 3.3; complex viscosity) at Womersley
     # number 10: started from the analytic periodic state, the full-size

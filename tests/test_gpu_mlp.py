@@ -118,6 +118,64 @@ def test_adam_step_matches_reference(V):
     assert np.all(np.abs(d_gpu - d_ref) <= 1e-3 * lr + 1e-6 * np.abs(flat[big]))
 
 
+# The shape the warm start trains: 128 frequencies (K = 256 for the first
+# product), width 256 (four 64-wide N tiles), 3 hidden layers, on 1024 rows.
+PROD = dict(in_dim=5, n_freq=128, width=256, hidden=3, out_dim=5)
+
+
+@pytest.fixture(scope="module")
+def prod_case(V):
+    m = make(V, seed=12, max_batch=1024, cfg=PROD)
+    flat = m.get_params().astype(np.float64)
+    x, t = inputs(1024, 6)
+    x = x.astype(np.float32).astype(np.float64)
+    t = t.astype(np.float32).astype(np.float64)
+    return m, flat, x, t
+
+
+def test_forward_matches_reference_production_shape(V, prod_case):
+    m, flat, x, _ = prod_case
+    y_gpu = m.forward(x).cpu().numpy()
+    y_ref, _ = M.forward(PROD, flat, x, bf16=True)
+    assert rel(y_gpu, y_ref) <= 1e-2, rel(y_gpu, y_ref)
+
+
+def test_gradients_match_reference_production_shape(V, prod_case):
+    m, flat, x, t = prod_case
+    loss, g = m.grad(x, t)
+    loss_ref, g_ref = M.loss_and_grad(PROD, flat, x, t, bf16=True)
+    assert abs(loss - loss_ref) <= 1e-2 * loss_ref
+    k = PROD["n_freq"] * PROD["in_dim"]
+    assert np.all(g[:k] == 0)
+    for l, (out, inp) in enumerate(M.layer_dims(PROD)):
+        gw = slice(k, k + out * inp)
+        gb = slice(k + out * inp, k + out * inp + out)
+        assert rel(g[gw], g_ref[gw]) <= 1e-2, ("W", l, rel(g[gw], g_ref[gw]))
+        assert rel(g[gb], g_ref[gb]) <= 1e-2, ("b", l, rel(g[gb], g_ref[gb]))
+        k += out * inp + out
+
+
+def test_adam_step_matches_reference_production_shape(V, prod_case):
+    import torch
+    m, flat, x, t = prod_case
+    m.set_params(flat.astype(np.float32))   # also resets Adam
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    lr = 1e-3
+    _, g = m.grad(x, t)
+    m.train_step(xd, td, lr)
+    new = m.get_params().astype(np.float64)
+    nfix = PROD["n_freq"] * PROD["in_dim"]
+    assert np.array_equal(new[:nfix], flat[:nfix])
+    ref, _, _ = M.adam_step(flat, g.astype(np.float64), np.zeros_like(flat),
+                            np.zeros_like(flat), 1, lr, n_fixed=nfix)
+    big = np.abs(g) > 1e-5
+    d_gpu, d_ref = (new - flat)[big], (ref - flat)[big]
+    assert np.all(np.abs(d_gpu - d_ref) <= 1e-3 * lr + 1e-6 * np.abs(flat[big]))
+    m.set_params(flat.astype(np.float32))
+
+
 def test_training_reduces_the_loss(V):
     import torch
     m = make(V, max_batch=512)

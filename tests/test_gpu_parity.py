@@ -78,17 +78,43 @@ def setup_pair(V, d, shape, storage, walls=(0, 0, 0), force="none", Re=1.0, Wi=1
     return o, g
 
 
-def compare(o, g, tol, fields=("u", "p", "tau", "Ae")):
+def max_rel(a, b):
+    """Element-wise bar: max |a - b| over max |b| (per field)."""
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a).max())
+
+
+def compare(o, g, tol, fields=("u", "p", "tau", "Ae"), elementwise=None):
+    """Relative L2 per field <= tol; with FP64 storage (tol <= 1e-12) also
+    the element-wise max-norm bar, so that a few bad nodes cannot hide in
+    the L2 norm of a field."""
     mo, mg = o.moments(), g.moments()
     out = {}
     diag = np.array([1, 0, 1] if o.d == 2 else [1, 1, 1, 0, 0, 0], float)
     mo["Ae"] = mo["A"] - diag
     mg["Ae"] = mg["A"] - diag
+    if elementwise is None:
+        elementwise = tol <= 1e-12
     for k in fields:
         out[k] = AN.rel_l2(mg[k], mo[k])
+        if elementwise:
+            out[k + "_max"] = max_rel(mg[k], mo[k])
     bad = {k: v for k, v in out.items() if not v <= tol}
     assert not bad, (out, tol)
     return out
+
+
+def pressure_bar(o, tol):
+    """Bar for the pressure in reduced-precision storage.  The pressure is
+    not stored: it is recovered from the sum of the moving populations
+    (App. B), which are of the size of U0 while p is of the size of U0^2,
+    so a relative storage error tol of the populations is an error of
+    about tol * |sum_i |f_i|| in p.  The bar is tol scaled by that ratio,
+    from the oracle's own state."""
+    f = o.get_state()["f"]
+    p = o.moments()["p"]
+    mag = np.sqrt((np.abs(f[:, 1:]).sum(1) ** 2).mean())
+    return tol * max(1.0, mag / np.sqrt((p ** 2).mean()))
 
 
 CASES_FP64 = [
@@ -130,14 +156,33 @@ def test_fp64_first_steps_exact_order(V):
         compare(o, g, 1e-13)
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-5)])
-def test_fp32_parity_four_roll_64(V, storage, tol):
-    # the 64x64 four-roll mill from rest (Re = 1, Wi = 1, beta = 0.5)
-    o, g = setup_pair(V, 2, (64, 64), storage, (0, 0, 0), "four_roll", Re=1.0, Wi=1.0,
-                      beta=0.5, U0=0.01, L=64 / (2 * np.pi))
+@pytest.fixture(scope="module")
+def four_roll_64_oracle():
+    # the 64x64 four-roll mill from rest (Re = 1, Wi = 1, beta = 0.5,
+    # U0 = 0.01), 2000 steps of the FP64 oracle, shared by the storages
+    p = O.lattice_params(1.0, 1.0, 0.5, 0.01, 64 / (2 * np.pi))
+    o = O.OracleSim(2, 64, 64)
+    o.set_params(p["tau_f"], 0.501, p["lam"], p["eta_p"])
+    k2 = (2 * np.pi / 64) ** 2
+    a = 2 * p["nu_s"] * 0.01 * k2
+    o.set_force(O.FORCE_FOUR_ROLL, (a, -a, 0.0))
+    o.init()
     o.step(2000)
+    return o
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16s", 1e-3), ("bf16s", 1e-3)])
+def test_four_roll_64_per_field_parity(V, four_roll_64_oracle, storage, tol):
+    # u, tau and A - I at the storage's bar; the pressure at the bar scaled
+    # by the size of the populations it is summed from (pressure_bar)
+    o = four_roll_64_oracle
+    g = setup_pair(V, 2, (64, 64), storage, (0, 0, 0), "four_roll", Re=1.0, Wi=1.0,
+                   beta=0.5, U0=0.01, L=64 / (2 * np.pi))[1]
     g.step(2000)
-    compare(o, g, tol, fields=("u", "tau", "Ae"))
+    out = compare(o, g, tol, fields=("u", "tau", "Ae"))
+    pb = pressure_bar(o, tol)
+    out.update(compare(o, g, pb, fields=("p",)))
+    print(storage, "p bar %.2e" % pb, out)
 
 
 def test_four_roll_64_fp64_10000_steps(V):
@@ -160,6 +205,7 @@ def test_reduced_storage_smooth_state(V, storage, tol):
     o.step(300)
     g.step(300)
     compare(o, g, tol, fields=("u", "tau", "Ae"))
+    compare(o, g, pressure_bar(o, tol), fields=("p",))
 
 
 def test_fp32_parity_3d(V):
@@ -168,6 +214,7 @@ def test_fp32_parity_3d(V):
     o.step(60)
     g.step(60)
     compare(o, g, 1e-5, fields=("u", "tau", "Ae"))
+    compare(o, g, pressure_bar(o, 1e-5), fields=("p",))
 
 
 def test_graph_replay_matches_single_launches(V):
@@ -209,6 +256,35 @@ def test_checkpoint_resume_bitwise(V):
     b.step(40)
     assert np.array_equal(a.read(V.FIELD_F), b.read(V.FIELD_F))
     assert np.array_equal(a.read(V.FIELD_H), b.read(V.FIELD_H))
+
+
+def test_fp16_storage_scale_is_fixed_once_initialised_and_travels_with_checkpoints(V):
+    # FP16 deviations are stored times 2^log2; a scale change under
+    # initialised fields would rescale every stored value
+    mk = lambda: setup_pair(V, 2, (16, 24), "f16s", (0, 1, 0), "const", init="smooth",
+                            seed=8)[1]
+    a = mk()
+    with pytest.raises(V.VflbError) as e:
+        a.set_params(1.0, 1.0, 0.5, 0.04, 10.0)   # U0 in another binade
+    assert e.value.code == V.ESTATE
+    with pytest.raises(V.VflbError) as e:
+        a.set_storage_scale(3, 12)
+    assert e.value.code == V.ESTATE
+    a.set_params(1.0, 1.0, 0.5, 0.01, 10.0)       # same parameters: allowed
+    a.step(30)
+    blob = a.save()
+    a.step(20)
+    # a lattice whose scale differs adopts the checkpoint's on load
+    b = V.Sim(2, 16, 24, 1, "f16s")
+    b.set_params(1.0, 1.0, 0.5, 0.01, 10.0)
+    b.set_boundaries((0, 1))
+    b.set_force(V.FORCE_CONST, (3e-6, -1e-6, 0.0))
+    b.set_storage_scale(4, 9)
+    b.init_fields()
+    b.load(blob)
+    b.step(20)
+    for k in (V.FIELD_F, V.FIELD_H, V.FIELD_CHI_PREV, V.FIELD_U_PREV):
+        assert np.array_equal(a.read(k), b.read(k)), k
 
 
 def test_reductions_match_oracle_and_invariants(V):
@@ -478,22 +554,25 @@ def test_inplace_keeps_one_population_buffer_and_is_rejected_where_not_built(V):
 
 
 # ------------------------------------------------- anchored 16-bit D3Q19
-# FP16 / BF16 deviations from the writer's FP32 anchor.  The 3D Taylor-Green
-# copy uses the benchmark's parameters (U0 = 0.02, Re = 100); Wi = 2,
-# beta = 0.1 is the strongly polymeric case.  FP16 meets the 1e-3 bar of
-# 16-bit storage in every case.  BF16 does not in D3Q19: its 8-bit mantissa
-# leaves each deviation with a 2e-3 relative rounding, and these coarse
-# lattices carry large non-equilibrium parts; its bounds below are the
-# measured errors (u 2.1e-3 / 2.7e-3, tau 1.5e-3 / 1.0e-3 / 6.5e-3) with
-# margin, and the mass bound is four times FP16's.
+# FP16 deviations from the writer's FP32 anchor.  The 3D Taylor-Green copy
+# uses the benchmark's parameters (U0 = 0.02, Re = 100); Wi = 2, beta = 0.1
+# is the strongly polymeric case.  FP16 meets the 1e-3 bar of 16-bit storage
+# in every case.  BF16 is refused on D3Q19 (its 8-bit mantissa missed the
+# bar on these lattices: u 2.1e-3 / 2.7e-3, tau 6.5e-3).
 ANCHOR3_CASES = [
     ("f16s", (16, 16, 16), (0, 0, 0), "tgv", 0.5, 0.9, 300, 1e-3),
-    ("bf16s", (16, 16, 16), (0, 0, 0), "tgv", 0.5, 0.9, 300, 3e-3),
     ("f16s", (16, 16, 16), (0, 0, 0), "tgv", 2.0, 0.1, 200, 1e-3),
-    ("bf16s", (16, 16, 16), (0, 0, 0), "tgv", 2.0, 0.1, 200, 4e-3),
     ("f16s", (36, 9, 5), (0, 0, 1), "smooth", 1.0, 0.5, 200, 1e-3),
-    ("bf16s", (36, 9, 5), (0, 0, 1), "smooth", 1.0, 0.5, 200, 1e-2),
 ]
+
+
+def test_bf16_storage_refused_on_d3q19(V):
+    for shape in ((16, 16, 16), (5, 9, 36)):
+        with pytest.raises(V.VflbError) as e:
+            V.Sim(3, shape[2], shape[1], shape[0], "bf16s")
+        assert e.value.code == V.EINVAL
+    V.Sim(3, 16, 16, 16, "f16s")   # FP16 is offered
+    V.Sim(2, 16, 16, 1, "bf16s")   # and BF16 on D2Q9
 
 
 @pytest.mark.parametrize("storage,shape,walls,init,Wi,beta,steps,tol", ANCHOR3_CASES)
@@ -506,9 +585,10 @@ def test_anchored_16bit_d3q19_against_the_oracle(V, storage, shape, walls, init,
     o.step(steps)
     g.step(steps)
     out = compare(o, g, tol, fields=("u", "tau", "Ae"))
+    out.update(compare(o, g, pressure_bar(o, tol), fields=("p",)))
     r = g.reduce()
     assert r["nonfinite"] == 0
-    mass_tol = (1e-3 if storage == "f16s" else 4e-3) * n ** 3 * 0.02 ** 2
+    mass_tol = 1e-3 * n ** 3 * 0.02 ** 2
     assert abs(r["M"] - float(o.get_state()["f"].sum())) < mass_tol, (r, out)
 
 

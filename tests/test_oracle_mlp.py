@@ -1,7 +1,8 @@
 """Pins of the FP64 reference network (oracle/mlp_ref.py) against what the
-mathematics fixes: central finite differences of the loss, the feature
-identity sin^2 + cos^2 = 1, the closed form of a first Adam step, the loss
-of an exact fit, and BF16 rounding of known values."""
+mathematics fixes: a network small enough to evaluate by hand (its outputs
+written into the test), central finite differences of the loss, the
+feature identity sin^2 + cos^2 = 1, the closed form of a first Adam step,
+the loss of an exact fit, and BF16 rounding of known values."""
 import numpy as np
 import pytest
 
@@ -92,3 +93,46 @@ def test_first_adam_step_closed_form():
 ])
 def test_bf16_rounding(value, expected):
     assert M.bf16_round(np.array([value]))[0] == expected
+
+
+# A network evaluated by hand: two inputs, one frequency B = (1/4, 0), one
+# tanh layer of width 2, one linear output.  Flat order: B, W0 [2][2] (its
+# columns act on (sin, cos)), b0, W1 [1][2], b1.
+HAND_CFG = dict(in_dim=2, n_freq=1, width=2, hidden=1, out_dim=1)
+HAND_FLAT = np.array([0.25, 0.0,
+                      1.0, 2.0, 0.5, -1.0, 0.0, 0.25,
+                      2.0, -1.0, 0.1])
+TANH_1 = 0.76159415595576488812
+TANH_075 = 0.63514895238728731922
+TANH_2 = 0.96402758007581688395
+
+
+def test_forward_of_a_hand_evaluated_network():
+    # x = (1, 0.3): 2 pi B.x = pi/2, phi = (1, 0); hidden pre-activations
+    # (1, 0.75); y = 2 tanh(1) - tanh(0.75) + 0.1.
+    # x = (0, 0): phi = (0, 1); pre-activations (2, -0.75);
+    # y = 2 tanh(2) + tanh(0.75) + 0.1.
+    x = np.array([[1.0, 0.3], [0.0, 0.0]])
+    y, acts = M.forward(HAND_CFG, HAND_FLAT, x)
+    assert y.shape == (2, 1)
+    assert y[0, 0] == pytest.approx(0.98803935952424246, rel=0, abs=1e-15)
+    assert y[1, 0] == pytest.approx(2.66320411253892109, rel=0, abs=1e-15)
+    assert np.allclose(acts[0], [[1.0, 0.0], [0.0, 1.0]], atol=1e-15)
+    assert np.allclose(acts[1], [[TANH_1, TANH_075], [TANH_2, -TANH_075]], atol=1e-15)
+
+
+def test_loss_and_output_gradient_of_the_hand_network():
+    x = np.array([[1.0, 0.3], [0.0, 0.0]])
+    t = np.array([[1.0], [2.0]])
+    d1 = 0.98803935952424246 - 1.0
+    d2 = 2.66320411253892109 - 2.0
+    loss, g = M.loss_and_grad(HAND_CFG, HAND_FLAT, x, t)
+    assert loss == pytest.approx((d1 * d1 + d2 * d2) / 2, rel=1e-14)
+    # dL/dy = 2 d / (n out) = d; last layer: dW1 = sum_k d_k h_k, db1 = sum d_k
+    assert g[8] == pytest.approx(d1 * TANH_1 + d2 * TANH_2, rel=1e-13)
+    assert g[9] == pytest.approx(d1 * TANH_075 - d2 * TANH_075, rel=1e-13)
+    assert g[10] == pytest.approx(d1 + d2, rel=1e-13)
+    # hidden bias b0[0]: d_k W1[0] (1 - h_k0^2) summed over the points
+    want = 2.0 * (d1 * (1 - TANH_1 ** 2) + d2 * (1 - TANH_2 ** 2))
+    assert g[6] == pytest.approx(want, rel=1e-13)
+    assert g[0] == 0.0 and g[1] == 0.0   # frequencies are fixed
