@@ -1,17 +1,20 @@
 """Throughput of the fused fluctuating-LB step on one MI355X.
 
-Workload: planar Poiseuille channel, D2Q9, 8192 x 1024 nodes, periodic in x,
-halfway bounce-back walls in y, constant body force g = 8 nu U0 / L^2,
-Re = 30.72 (U0 = 0.01, L = 1024, tau_f = 1 at beta = 0.5), Wi = 1,
-FP32 arithmetic with FP32 population storage; the fluid starts at rest
-(synthetic input, no dataset).  One step is one fused stream-and-collide
-launch over the whole lattice; the FP64 residual/conservation reduction runs
-every 100 steps inside the timed region as in a production run.
+Default workload: the 3D Taylor-Green vortex on a periodic 512^3 D3Q19
+lattice (theta = 0 start with its pressure, U0 = 0.02, Re = 100, Wi = 0.5,
+beta = 0.9, L = 512/(2 pi); tau = 0 at t = 0), FP32 arithmetic and FP32
+population storage; synthetic input generated on the device, no dataset.
+One step is one fused stream-and-collide launch over the whole lattice; the
+FP64 residual/conservation reduction runs every 100 steps inside the timed
+region as in a production run.  `--workload channel` runs the 8192 x 1024
+D2Q9 Poiseuille channel instead.
 
 Prints one JSON line: MLUPS (whole job), the roofline of the step kernel
 (algorithmic bytes per lattice update / measured kernel time, against the
-8 TB/s HBM peak) and the CPU oracle timed on a bounded sample of the same
-workload.
+8 TB/s HBM peak), the CPU oracle timed on a bounded sample of the same
+workload (a 64^3 copy with identical lattice-unit parameters), and the time
+to a steady state (R < 1e-6) of held-out four-roll lattices started from
+rest and from the learned warm start.
 """
 from __future__ import annotations
 
@@ -109,7 +112,9 @@ def run_gpu(steps, warmup, storage="f32", tile=0, scheme="fluctuating", inplace=
 
 def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0):
     """3D Taylor-Green vortex, D3Q19, periodic n^3, theta = 0 start,
-    U0 = 0.02, Re = 100, Wi = 0.5, beta = 0.9, L = n/(2 pi)."""
+    U0 = 0.02, Re = 100, Wi = 0.5, beta = 0.9, L = n/(2 pi).  The FP64
+    reduction runs every REDUCE_EVERY steps inside the timed region; its
+    time is measured on the same stream and left out of the kernel time."""
     import math
     import torch
     from paper_2506_13072_amd import vflb
@@ -122,16 +127,38 @@ def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0):
     g.init_fields_device(u, None, p)
     del u, p
     g.step(warmup)
+    g.reduce()
     g.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
     e0.record(g.stream)
-    g.step(steps)
+    red_ms = 0.0
+    left = steps
+    r = None
+    while left > 0:
+        k = min(REDUCE_EVERY, left)
+        g.step(k)
+        left -= k
+        if k == REDUCE_EVERY or r is None:
+            r0 = torch.cuda.Event(enable_timing=True)
+            r1 = torch.cuda.Event(enable_timing=True)
+            r0.record(g.stream)
+            r = g.reduce()
+            r1.record(g.stream)
+            r1.synchronize()
+            red_ms += r0.elapsed_time(r1)
     e1.record(g.stream)
     e1.synchronize()
-    r = g.reduce()
-    ms = e0.elapsed_time(e1) / steps
-    return dict(step_ms=ms, GLUPS=n ** 3 / ms / 1e6, KE=r["KE"], nonfinite=r["nonfinite"])
+    wall = time.perf_counter() - t0
+    total_ms = e0.elapsed_time(e1)
+    step_ms = (total_ms - red_ms) / steps
+    out = dict(total_ms=total_ms, step_ms=step_ms, red_ms=red_ms, wall=wall,
+               GLUPS=n ** 3 / step_ms / 1e6, KE=r["KE"], R=r["R"], nonfinite=r["nonfinite"],
+               buffer_bytes=sum(int(b.numel()) for b in g.buffers))
+    del g
+    torch.cuda.empty_cache()
+    return out
 
 
 def ensemble_specs(n):
@@ -235,6 +262,22 @@ def run_gpu_warmstart(n_train=96, n_test=16, side=64, tol=1e-6, iters=8000, K0=1
                 t_cold=res["seconds_cold_after_K0"], t_warm=res["seconds_warm_after_K0"])
 
 
+def time_to_steady_state(n_train=96, n_test=16, side=64):
+    """The metric's second half on a bounded sample: held-out four-roll
+    lattices of side^2 run to R < 1e-6 from rest (plain GPU LB) and from the
+    learned warm start (fallback rule included), after training the network
+    on n_train steady states the method generated; steps summed over the
+    held-out lattices, and the error of both against a tighter reference."""
+    r = run_gpu_warmstart(n_train=n_train, n_test=n_test, side=side)
+    keep = ("cold_steps", "warm_steps", "fallbacks", "cold_converged", "warm_converged",
+            "err_cold", "err_warm", "n_train", "t_data", "t_train")
+    out = {k: (round(r[k], 6) if isinstance(r[k], float) else r[k]) for k in keep if k in r}
+    out["warm_over_cold"] = round(r["warm_steps"] / max(r["cold_steps"], 1), 4)
+    out["sample"] = (f"{n_test} held-out four-roll {side}x{side} lattices (Wi, beta drawn as "
+                     f"in the ensemble), network trained on {r['n_train']} steady states")
+    return out
+
+
 # storage modes with committed rocprofv3 records, and the tag in their names
 RECORD_TAG = {"f32": "f32", "f16s": "f16"}
 
@@ -285,7 +328,25 @@ def copy_ceiling(nbytes=4 << 30, reps=10):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
-def run_cpu_baseline(budget_s=15.0):
+def host_cpu():
+    """CPU model and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return model, nproc
+
+
+def run_cpu_baseline_channel(budget_s=15.0):
     """The FP64 oracle, single-threaded, on a 256 x 128 copy of the channel
     (the size of the paper's own timing table) with the same lattice-unit
     parameters except the width; steps until about budget_s of work."""
@@ -305,32 +366,68 @@ def run_cpu_baseline(budget_s=15.0):
         o.step(10)
         n += 10
     dt = time.perf_counter() - t0
+    model, nproc = host_cpu()
     return dict(value=nx * ny * n / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                cpu_model=model, nproc=nproc,
                 sample=f"D2Q9 {nx}x{ny} channel, same lattice parameters, {n} steps, "
                        f"FP64, single thread, {dt:.1f} s")
+
+
+def run_cpu_baseline_tgv(budget_s=15.0, n=64):
+    """The FP64 oracle, single-threaded, on an n^3 copy of the Taylor-Green
+    workload with identical lattice-unit parameters (tau_f, lambda, eta_p of
+    the 512^3 lattice: L = 512/(2 pi)) and the theta = 0 vortex of the
+    smaller lattice; steps until about budget_s of work."""
+    import math
+    from oracle import oracle as O
+    from paper_2506_13072_amd.workloads import taylor_green_3d_velocity
+    p = O.lattice_params(100.0, 0.5, 0.9, 0.02, 512 / (2 * math.pi))
+    o = O.OracleSim(3, n, n, n)
+    o.set_params(p["tau_f"], 0.501, p["lam"], p["eta_p"])
+    o.init(taylor_green_3d_velocity(n, 0.02), None, None)
+    o.step(1)
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < budget_s:
+        o.step(1)
+        k += 1
+    dt = time.perf_counter() - t0
+    model, nproc = host_cpu()
+    return dict(value=n ** 3 * k / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                cpu_model=model, nproc=nproc,
+                sample=f"D3Q19 {n}^3 Taylor-Green copy, lattice parameters of the 512^3 "
+                       f"workload, {k} steps, FP64, single thread, {dt:.1f} s")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 200 for tgv, 2000 for the D2Q9 workloads)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default: 20 for tgv, 200 otherwise)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "bf16s", "f64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="tile height: D2Q9 4, 8, 16; D3Q19 4, 8")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy kernel (counter calibration)")
-    ap.add_argument("--workload", default="channel",
+    ap.add_argument("--workload", default="tgv",
                     choices=["channel", "tgv", "ensemble", "warmstart", "schemes", "inplace"],
-                    help="channel: the 8192x1024 D2Q9 headline; tgv: 512^3 D3Q19 "
-                         "Taylor-Green vortex; ensemble: 256 four-roll lattices of "
-                         "sides 64..512 as one batch (both reported, not the headline)")
+                    help="tgv (default): the 512^3 D3Q19 Taylor-Green vortex; channel: the "
+                         "8192x1024 D2Q9 Poiseuille channel; ensemble: 256 four-roll "
+                         "lattices of sides 64..512 as one batch")
+    ap.add_argument("--no-tts", action="store_true",
+                    help="tgv: leave out the time-to-steady-state comparison")
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--ws-side", type=int, default=64, help="warmstart: lattice side")
     ap.add_argument("--ws-train", type=int, default=96, help="warmstart: training lattices")
     ap.add_argument("--ws-test", type=int, default=16, help="warmstart: held-out lattices")
     ap.add_argument("--tgv-n", type=int, default=512)
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 200 if args.workload == "tgv" else 2000
+    if args.warmup is None:
+        args.warmup = 20 if args.workload == "tgv" else 200
     if args.copy_probe:
         print(json.dumps({"copy_GBps": round(copy_ceiling(), 1)}), flush=True)
         return
@@ -458,26 +555,48 @@ def main():
         return
     if args.workload == "tgv":
         r = run_gpu_tgv(args.tgv_n, args.steps, args.warmup, args.storage, args.tile)
+        ceiling = copy_ceiling()
         bpl = bytes_per_lup(3, args.storage)
         nodes = args.tgv_n ** 3
+        mlups = nodes * args.steps / (r["total_ms"] / 1e3) / 1e6
         ach = bpl * nodes / (r["step_ms"] / 1e3) / 1e9
         traffic = None
         if args.storage in RECORD_TAG and args.tgv_n == 512 and not args.tile:
             traffic = measured_traffic(f"step3d_{RECORD_TAG[args.storage]}_tgv_512.md", "step3d")
-        print(json.dumps({"metric": "MLUPS (fused stream-collide, D3Q19)", "value": round(r["GLUPS"] * 1e3, 1),
-                          "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-                          "ms_per_step": round(r["step_ms"], 4), "higher_is_better": True,
-                          "scaling": "weak", "vs_baseline": None,
-                          "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
-                          "config": {"workload": f"3D Taylor-Green vortex D3Q19 {args.tgv_n}^3, "
-                                                 "periodic, Re=100 Wi=0.5 beta=0.9",
-                                     "storage": args.storage, "nodes": nodes},
-                          "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                                       "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                                       "traffic": None if traffic is None else round(traffic / 1e9, 4),
-                                       "traffic_unit": "GB per launch",
-                                       "algorithmic_GB_per_launch": round(bpl * nodes / 1e9, 4),
-                                       "bytes_per_lup": bpl}}), flush=True)
+        out = {
+            "metric": "MLUPS & % HBM peak; time-to-steady-state (1e-6) vs plain GPU LB",
+            "value": round(mlups, 1),
+            "unit": "MLUPS",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": round(r["total_ms"] / args.steps, 4),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32" if args.storage != "f64" else "f64",
+            "data": "synthetic",
+            "config": {"workload": f"3D Taylor-Green vortex D3Q19 {args.tgv_n}^3, periodic, "
+                                   "theta=0, U0=0.02 Re=100 Wi=0.5 beta=0.9",
+                       "storage": args.storage, "nodes": nodes,
+                       "reduce_every": REDUCE_EVERY},
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                         "traffic_unit": "GB per launch",
+                         "algorithmic_GB_per_launch": round(bpl * nodes / 1e9, 4),
+                         "bytes_per_lup": bpl,
+                         "kernel_ms": round(r["step_ms"], 4),
+                         "copy_ceiling_GBps": round(ceiling, 1),
+                         "frac_of_copy": round(ach / ceiling, 4)},
+            "residual": r["R"],
+            "nonfinite": r["nonfinite"],
+        }
+        if not args.no_tts:
+            out["time_to_steady_state"] = time_to_steady_state()
+        if not args.no_cpu:
+            out["cpu_baseline"] = run_cpu_baseline_tgv()
+        print(json.dumps(out), flush=True)
         return
     res = run_gpu(args.steps, args.warmup, args.storage, args.tile)
     ceiling = copy_ceiling()
@@ -518,7 +637,7 @@ def main():
         "residual": res["R"],
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = run_cpu_baseline()
+        out["cpu_baseline"] = run_cpu_baseline_channel()
     print(json.dumps(out), flush=True)
 
 

@@ -511,7 +511,10 @@ vflb_status vflb_mlp_train_step(vflb_mlp *mlp, const float *dev_x,
 
 /* Initialise a D2Q9 simulation from the network: inputs (x/nx, y/ny,
  * extra[0], extra[1], extra[2]) at every node, u = u_scale (y0, y1),
- * tau = tau_scale (y2, y3, y4), pressure 0, then as vflb_init_fields,
+ * tau = tau_scale (y2, y3, y4), pressure 0; on a lattice periodic on every
+ * axis the domain mean of u is removed (its total momentum changes only by
+ * the summed force, so a steady state keeps the initial momentum, zero for
+ * a start from rest); then as vflb_init_fields,
  * followed by settle_steps settling steps towards those fields with
  * settle_flags (as vflb_settle; ignored when settle_steps is 0).  The
  * simulation's residual snapshot buffer serves as scratch; both handles must

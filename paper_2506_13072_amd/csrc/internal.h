@@ -9,10 +9,11 @@
 namespace vflb {
 namespace internal {
 
-// Shape, stream and the residual-snapshot buffer of a simulation, which a
-// caller may use as scratch before (re)initialising it: FP32 fields of up
-// to `bytes` bytes.  Needs bound buffers and parameters.
-vflb_status sim_scratch(vflb_sim* s, int* D, int* nx, int* ny, hipStream_t* stream,
+// Shape, wall bits (bit a: walls on axis a), stream and the
+// residual-snapshot buffer of a simulation, which a caller may use as
+// scratch before (re)initialising it: FP32 fields of up to `bytes` bytes.
+// Needs bound buffers and parameters.
+vflb_status sim_scratch(vflb_sim* s, int* D, int* nx, int* ny, int* walls, hipStream_t* stream,
                         void** scratch, size_t* bytes);
 
 // vflb_init_fields from FP32 component-major device fields u [D][N] and

@@ -304,5 +304,33 @@ __global__ void __launch_bounds__(256) node_outputs_kernel(const float* __restri
   tau[2 * N + n] = tau_scale * r[4];
 }
 
+// Remove the domain mean of each velocity component of u [2][N] (FP32):
+// one workgroup, FP64 sums in a fixed order.  On a lattice periodic on
+// every axis the total momentum changes only by the summed body force, so
+// a steady state keeps the momentum of its initial state; a prediction
+// with a mean flow would carry it for good (and, against a forcing pattern
+// fixed in space, never settle).
+__global__ void __launch_bounds__(1024) zero_mean_kernel(float* __restrict__ u, size_t N) {
+  __shared__ double red[2][1024];
+  for (int c = 0; c < 2; ++c) {
+    double s = 0.0;
+    for (size_t n = threadIdx.x; n < N; n += 1024) s += (double)u[(size_t)c * N + n];
+    red[c][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  const float m0 = (float)(red[0][0] / (double)N), m1 = (float)(red[1][0] / (double)N);
+  for (size_t n = threadIdx.x; n < N; n += 1024) {
+    u[n] -= m0;
+    u[N + n] -= m1;
+  }
+}
+
 }  // namespace mlp
 }  // namespace vflb

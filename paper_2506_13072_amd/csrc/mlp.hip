@@ -512,11 +512,12 @@ vflb_status vflb_init_from_mlp(vflb_sim* sim, vflb_mlp* m, const double extra[3]
   if (settle_steps < 0) return mfail(m, VFLB_EINVAL, "settle_steps < 0");
   if (m->cfg.in_dim != 5 || m->cfg.out_dim != 5)
     return mfail(m, VFLB_EINVAL, "the network must map 5 inputs to 5 outputs");
-  int D = 0, nx = 0, ny = 0;
+  int D = 0, nx = 0, ny = 0, walls = 0;
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   hipStream_t st = nullptr;
-  if ((rc = vflb::internal::sim_scratch(sim, &D, &nx, &ny, &st, &scratch, &scratch_bytes)) !=
+  if ((rc = vflb::internal::sim_scratch(sim, &D, &nx, &ny, &walls, &st, &scratch,
+                                        &scratch_bytes)) !=
       VFLB_OK)
     return mfail(m, rc, "simulation: %s", vflb_last_error(sim));
   if (D != 2) return mfail(m, VFLB_EINVAL, "the warm start fills D2Q9 lattices");
@@ -535,6 +536,11 @@ vflb_status vflb_init_from_mlp(vflb_sim* sim, vflb_mlp* m, const double extra[3]
     hipLaunchKernelGGL(node_outputs_kernel, dim3((cnt + 255) / 256), dim3(256), 0, m->stream,
                        m->w<float>(m->off_Y), kOutPad, s, cnt, N, (float)u_scale,
                        (float)tau_scale, u, tau);
+    MHIP_TRY(m, hipGetLastError());
+  }
+  if (walls == 0) {
+    // periodic on every axis: start with the zero momentum of the cold start
+    hipLaunchKernelGGL(zero_mean_kernel, dim3(1), dim3(1024), 0, m->stream, u, N);
     MHIP_TRY(m, hipGetLastError());
   }
   if ((rc = vflb::internal::sim_init_f32(sim, u, tau)) != VFLB_OK)

@@ -1587,13 +1587,14 @@ const char* vflb_batch_last_error(const vflb_batch* b) {
 namespace vflb {
 namespace internal {
 
-vflb_status sim_scratch(vflb_sim* s, int* D, int* nx, int* ny, hipStream_t* stream,
+vflb_status sim_scratch(vflb_sim* s, int* D, int* nx, int* ny, int* walls, hipStream_t* stream,
                         void** scratch, size_t* bytes) {
   vflb_status rc = need_ready(s);
   if (rc != VFLB_OK) return rc;
   *D = s->D;
   *nx = s->nx;
   *ny = s->ny;
+  *walls = s->walls;
   *stream = s->stream;
   *scratch = s->buf[VFLB_BUF_SNAP];
   *bytes = s->bytes[VFLB_BUF_SNAP];

@@ -173,31 +173,34 @@ def test_run_until_compacts_and_freezes(V):
 
 def test_run_until_short_cap_does_not_shorten_the_residual_interval(V):
     # R is the relative change over the steps since the last reduction.  A
-    # neighbour's cap at t = 120 forces a check after 20 steps; a residual
+    # neighbour's cap forces a check 20 steps after a full one; a residual
     # over those 20 steps is smaller than over check_every = 100 and must
-    # not count as convergence.  The tolerance is placed between the two.
+    # not count as convergence.  After a burn-in of T0 steps (the residual
+    # then decays), the tolerance is placed between the two.
+    T0 = 1000
     spec = SPECS[0]
     probe = make_batch(V, specs=[spec])
+    probe.step(T0)
     probe.reduce()
     probe.step(100)
-    probe.reduce()
+    r100 = probe.reduce()[0, 0]   # over T0 .. T0 + 100
     probe.step(20)
-    r20 = probe.reduce()[0, 0]
-    probe.step(80)
-    r100 = probe.reduce()[0, 0]   # the 100 steps from t = 20 .. 120 would do too
+    r20 = probe.reduce()[0, 0]    # over T0 + 100 .. T0 + 120
     assert 0 < r20 < r100
     tol = float(np.sqrt(r20 * r100))
     b = make_batch(V, specs=[spec, spec])
-    steps, res, status = b.run_until(tol=tol, check_every=100, max_steps=[120, 10_000])
-    assert status[0] == V.RUN_CAPPED and steps[0] == 120
-    # the long-running instance was checked at t = 100 (full), 120 (short),
-    # 220, ... and stops only where a full interval's residual is below tol
-    assert steps[1] > 120
+    b.step(T0)
+    steps, res, status = b.run_until(tol=tol, check_every=100, max_steps=[T0 + 120, 100_000])
+    assert status[0] == V.RUN_CAPPED and steps[0] == T0 + 120
+    # the long-running instance was checked at T0 + 100 (full, R = r100 >
+    # tol), T0 + 120 (short, R = r20 < tol: not a convergence), T0 + 220, ...
+    # and stops only where a full interval's residual is below tol
+    assert steps[1] > T0 + 120
     assert status[1] in (V.RUN_CONVERGED, V.RUN_CAPPED)
     if status[1] == V.RUN_CAPPED:
-        assert steps[1] == 10_000
+        assert steps[1] == 100_000
         return
-    assert res[1] < tol and (steps[1] - 120) % 100 == 0
+    assert res[1] < tol and (steps[1] - T0 - 120) % 100 == 0
     # its residual over its last full interval, recomputed on a lone run
     # (the batched reduction sums in another order: 1e-9)
     g = V.Sim(2, spec[0][0], spec[0][1], 1, "f32")

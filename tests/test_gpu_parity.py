@@ -275,7 +275,7 @@ def test_fp16_storage_scale_is_fixed_once_initialised_and_travels_with_checkpoin
     blob = a.save()
     a.step(20)
     # a lattice whose scale differs adopts the checkpoint's on load
-    b = V.Sim(2, 16, 24, 1, "f16s")
+    b = V.Sim(2, 24, 16, 1, "f16s")   # nx = 24, ny = 16, as setup_pair's (16, 24)
     b.set_params(1.0, 1.0, 0.5, 0.01, 10.0)
     b.set_boundaries((0, 1))
     b.set_force(V.FORCE_CONST, (3e-6, -1e-6, 0.0))
