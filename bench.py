@@ -110,7 +110,14 @@ def run_gpu(steps, warmup, storage="f32", tile=0, scheme="fluctuating", inplace=
                 buffer_bytes=sum(int(b.numel()) for b in g.buffers))
 
 
-def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0):
+# stress-divergence scheme in 3D: the tau_p pass pulls the 19 (f, h)
+# populations of every node (19 * 7 words) and writes tau_p (6 words), the
+# divergence pass reads tau_p (6) and writes div tau_p (3), the step reads
+# div tau_p (3): words per update
+STRESS_DIV3_EXTRA_WORDS = 19 * 7 + 6 + 6 + 3 + 3
+
+
+def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0, scheme="fluctuating"):
     """3D Taylor-Green vortex, D3Q19, periodic n^3, theta = 0 start,
     U0 = 0.02, Re = 100, Wi = 0.5, beta = 0.9, L = n/(2 pi).  The FP64
     reduction runs every REDUCE_EVERY steps inside the timed region; its
@@ -119,7 +126,7 @@ def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0):
     import torch
     from paper_2506_13072_amd import vflb
     from paper_2506_13072_amd.workloads import taylor_green_3d_device
-    g = vflb.Sim(3, n, n, n, storage)
+    g = vflb.Sim(3, n, n, n, storage, scheme=scheme)
     g.set_params(100.0, 0.5, 0.9, 0.02, n / (2 * math.pi))
     if tile:
         g.set_tile(tile)
@@ -230,9 +237,12 @@ def run_gpu_ensemble(n, steps, warmup, storage="f32", compare_unbatched=True):
     return out
 
 
-def run_gpu_warmstart(n_train=96, n_test=16, side=64, tol=1e-6, iters=8000, K0=1000):
+def run_gpu_warmstart(n_train=96, n_test=16, side=64, tol=1e-6, iters=8000, K0=1000,
+                      settle=0, window=5, storage="f64", settle_flags=3):
     """Time to a steady state (R < tol) of held-out four-roll lattices,
-    started from rest and from the trained network (fallback rule at K0)."""
+    started from rest and from the trained network (fallback rule of the
+    warm-start module), and the error of both final states against an FP64
+    cold run of each converged to R < 1e-9."""
     import torch
     from paper_2506_13072_amd import vflb as V
     from paper_2506_13072_amd import warmstart as W
@@ -240,26 +250,38 @@ def run_gpu_warmstart(n_train=96, n_test=16, side=64, tol=1e-6, iters=8000, K0=1
     draws = ensemble_draws(n_train + n_test, seed=777)
     specs = [dict(side=side, Re=1.0, Wi=d["Wi"], beta=d["beta"], U0=0.01) for d in draws]
     t0 = time.perf_counter()
-    run = W.steady_states(V, specs[:n_train], tol=tol)
+    run = W.cold_runs(V, specs[:n_train], tol=tol, K0=K0, storage=storage)
     t_data = time.perf_counter() - t0
     ok = [i for i in range(n_train) if run["status"][i] == V.RUN_CONVERGED]
     X, T = W.training_set(V, run, specs, ok)
+    model = W.ColdModel(specs[:n_train], run)
+    del run
     mlp = V.Mlp(max_batch=16384, seed=1, sigma=1.5)
     t0 = time.perf_counter()
     hist = W.train(mlp, X, T, iters=iters, rows=16384, lr=2e-3, log_every=iters // 4)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    res = W.warm_vs_cold(V, mlp, specs[n_train:], tol=tol, K0=K0)
+    res = W.warm_vs_cold(V, mlp, specs[n_train:], model, tol=tol, K0=K0, settle=settle,
+                         window=window, storage=storage, settle_flags=settle_flags)
+    conv = lambda st: int((st == V.RUN_CONVERGED).sum())
     return dict(n_train=len(ok), t_data=t_data, t_train=t_train, loss=hist[-1][1],
                 cold_steps=int(res["cold_steps"].sum()),
                 warm_steps=int(res["effective_warm_steps"].sum()),
                 fallbacks=int(res["fallback"].sum()),
                 R_K0_cold_median=float(np.median(res["R_cold_K0"])),
                 R_K0_warm_median=float(np.median(res["R_warm_K0"])),
-                cold_converged=int((res["cold_status"] == V.RUN_CONVERGED).sum()),
-                warm_converged=int(((res["warm_status"] == V.RUN_CONVERGED) |
-                                    res["fallback"]).sum()),
-                t_cold=res["seconds_cold_after_K0"], t_warm=res["seconds_warm_after_K0"])
+                cold_converged=conv(res["cold_status"]),
+                warm_converged=conv(np.where(res["fallback"], res["cold_status"],
+                                             res["warm_status"])),
+                err_cold=float(np.median(res["err_cold"].max(1))),
+                err_warm=float(np.median(res["err_warm"].max(1))),
+                ref_converged=conv(res["ref_status"]),
+                per_lattice=dict(cold=res["cold_steps"].tolist(),
+                                 warm=res["effective_warm_steps"].tolist(),
+                                 abandoned=res["abandoned"].tolist(),
+                                 err_cold=np.round(res["err_cold"].max(1), 9).tolist(),
+                                 err_warm=np.round(res["err_warm"].max(1), 9).tolist()),
+                t_cold=res["seconds_cold"], t_warm=res["seconds_warm"])
 
 
 def time_to_steady_state(n_train=96, n_test=16, side=64):
@@ -270,11 +292,15 @@ def time_to_steady_state(n_train=96, n_test=16, side=64):
     held-out lattices, and the error of both against a tighter reference."""
     r = run_gpu_warmstart(n_train=n_train, n_test=n_test, side=side)
     keep = ("cold_steps", "warm_steps", "fallbacks", "cold_converged", "warm_converged",
-            "err_cold", "err_warm", "n_train", "t_data", "t_train")
+            "err_cold", "err_warm", "ref_converged", "n_train", "t_data", "t_train")
     out = {k: (round(r[k], 6) if isinstance(r[k], float) else r[k]) for k in keep if k in r}
     out["warm_over_cold"] = round(r["warm_steps"] / max(r["cold_steps"], 1), 4)
     out["sample"] = (f"{n_test} held-out four-roll {side}x{side} lattices (Wi, beta drawn as "
-                     f"in the ensemble), network trained on {r['n_train']} steady states")
+                     f"in the ensemble), network trained on {r['n_train']} steady states; "
+                     "steps summed over the lattices (a warm run abandoned by the fallback "
+                     "rule counts its own steps plus the cold run's); errors: median over "
+                     "the lattices of the larger of the u and tau relative L2 distances from "
+                     "an FP64 run to R < 1e-9")
     return out
 
 
@@ -412,7 +438,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy kernel (counter calibration)")
     ap.add_argument("--workload", default="tgv",
-                    choices=["channel", "tgv", "ensemble", "warmstart", "schemes", "inplace"],
+                    choices=["channel", "tgv", "ensemble", "warmstart", "schemes", "schemes3d",
+                             "inplace"],
                     help="tgv (default): the 512^3 D3Q19 Taylor-Green vortex; channel: the "
                          "8192x1024 D2Q9 Poiseuille channel; ensemble: 256 four-roll "
                          "lattices of sides 64..512 as one batch")
@@ -422,12 +449,20 @@ def main():
     ap.add_argument("--ws-side", type=int, default=64, help="warmstart: lattice side")
     ap.add_argument("--ws-train", type=int, default=96, help="warmstart: training lattices")
     ap.add_argument("--ws-test", type=int, default=16, help="warmstart: held-out lattices")
+    ap.add_argument("--ws-settle", type=int, default=0,
+                    help="warmstart: settling steps after the network's initial state")
+    ap.add_argument("--ws-settle-flags", type=int, default=3,
+                    help="warmstart: fields prescribed while settling (1 u, 2 A, 3 both)")
+    ap.add_argument("--ws-storage", default="f64", choices=["f64", "f32"],
+                    help="warmstart: storage of the runs to R < 1e-6 (FP32 rounding stalls "
+                         "these flows near R = 1e-6)")
     ap.add_argument("--tgv-n", type=int, default=512)
     args = ap.parse_args()
+    three_d = args.workload in ("tgv", "schemes3d")
     if args.steps is None:
-        args.steps = 200 if args.workload == "tgv" else 2000
+        args.steps = 200 if three_d else 2000
     if args.warmup is None:
-        args.warmup = 20 if args.workload == "tgv" else 200
+        args.warmup = 20 if three_d else 200
     if args.copy_probe:
         print(json.dumps({"copy_GBps": round(copy_ceiling(), 1)}), flush=True)
         return
@@ -436,7 +471,9 @@ def main():
               "(the multi-GPU slab decomposition is not built)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "warmstart":
-        r = run_gpu_warmstart(n_train=args.ws_train, n_test=args.ws_test, side=args.ws_side)
+        r = run_gpu_warmstart(n_train=args.ws_train, n_test=args.ws_test, side=args.ws_side,
+                              settle=args.ws_settle, storage=args.ws_storage,
+                              settle_flags=args.ws_settle_flags)
         print(json.dumps({"metric": f"time to steady state (R<1e-6), held-out four-roll "
                                     f"{args.ws_side}x{args.ws_side}, steps summed over "
                                     f"{args.ws_test} lattices",
@@ -472,6 +509,42 @@ def main():
                           "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
                           "config": {"workload": "Poiseuille channel D2Q9 8192x1024, both schemes",
                                      "storage": args.storage, "nodes": nodes},
+                          "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                       "traffic": None, "bytes_per_lup": sd["bytes_per_lup"]},
+                          "schemes": rows,
+                          "time_ratio_fluctuating_over_divergence":
+                              round(fl["ms_per_step"] / sd["ms_per_step"], 4),
+                          "memory_ratio_fluctuating_over_divergence":
+                              round(fl["buffer_bytes"] / sd["buffer_bytes"], 4)}), flush=True)
+        return
+    if args.workload == "schemes3d":
+        # the paper's 3D comparison (Taylor-Green performance table): its
+        # method against the stress-divergence scheme on the same vortex
+        n = args.tgv_n
+        nodes = n ** 3
+        wb = 8 if args.storage == "f64" else 4
+        rows = {}
+        for scheme in ("fluctuating", "stress_divergence"):
+            r = run_gpu_tgv(n, args.steps, args.warmup, args.storage, args.tile, scheme)
+            bpl = bytes_per_lup(3, args.storage) + (
+                STRESS_DIV3_EXTRA_WORDS * wb if scheme == "stress_divergence" else 0)
+            rows[scheme] = dict(MLUPS=round(nodes * args.steps / (r["total_ms"] / 1e3) / 1e6, 1),
+                                ms_per_step=round(r["total_ms"] / args.steps, 4),
+                                bytes_per_lup=bpl,
+                                achieved_GBps=round(bpl * nodes / (r["step_ms"] / 1e3) / 1e9, 1),
+                                buffer_bytes=r["buffer_bytes"])
+        fl, sd = rows["fluctuating"], rows["stress_divergence"]
+        ach = sd["achieved_GBps"]
+        print(json.dumps({"metric": "MLUPS (stress-divergence scheme, D3Q19 Taylor-Green)",
+                          "value": sd["MLUPS"], "unit": "MLUPS", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": sd["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
+                          "config": {"workload": f"3D Taylor-Green vortex D3Q19 {n}^3, both "
+                                                 "schemes", "storage": args.storage,
+                                     "nodes": nodes},
                           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                                        "traffic": None, "bytes_per_lup": sd["bytes_per_lup"]},

@@ -114,9 +114,10 @@ enum { VFLB_PERIODIC = 0, VFLB_WALLS = 1 };
  *                      and the pressure.  Its stencil is not given in the
  *                      paper; here second-order central differences of
  *                      tau_p(t), one-sided second order (-3 t0 + 4 t1 -
- *                      t2)/2 normal to a wall.  D2Q9 with FP32 or FP64
- *                      storage; tau_p and div tau_p occupy 5 more words per
- *                      node of the AUX buffer.
+ *                      t2)/2 normal to a wall.  D2Q9 and D3Q19 with FP32
+ *                      or FP64 storage; tau_p and div tau_p occupy NC + D
+ *                      more words per node of the AUX buffer (5 in 2D, 9
+ *                      in 3D).
  * The conformation equation (Sec. 2.3) is the same in both. */
 enum { VFLB_SCHEME_FLUCTUATING = 0, VFLB_SCHEME_STRESS_DIVERGENCE = 1 };
 
@@ -193,7 +194,7 @@ vflb_status vflb_create(int lattice, int nx, int ny, int nz, int storage,
 
 /* vflb_create with the scheme (VFLB_SCHEME_*; vflb_create is
  * VFLB_SCHEME_FLUCTUATING).  EINVAL for an unknown scheme, or for
- * STRESS_DIVERGENCE on D3Q19 or with 16-bit storage. */
+ * STRESS_DIVERGENCE with 16-bit storage. */
 vflb_status vflb_create_scheme(int lattice, int nx, int ny, int nz, int storage, int scheme,
                                void *hip_stream, vflb_sim **out);
 
@@ -509,12 +510,32 @@ vflb_status vflb_mlp_train_step(vflb_mlp *mlp, const float *dev_x,
                                 const float *dev_t, int64_t n, float lr,
                                 double *loss_out);
 
+/* Train on a data set in device memory: iters Adam steps, each on `rows`
+ * (<= max_batch) samples of X [n][in_dim], T [n][out_dim] (FP32) drawn with
+ * replacement (sample floor(z n / 2^64) for z the SplitMix64 output at
+ * position it * rows + r of the stream seeded with `seed`), learning rate
+ * lr (1 + cos(pi it / iters))/2, floored at lr/1000.  The targets are
+ * standardised per output (mean and standard deviation over all n samples,
+ * FP64) for training, and the standardisation is folded into the output
+ * layer at the end, so that the network predicts T itself; the Adam moments
+ * are then reset.  With log_every > 0, losses[k] receives the standardised
+ * loss of step k * log_every, and one more entry the last step's when
+ * (iters - 1) is not a multiple of log_every ((iters - 1)/log_every + 2
+ * entries at most).  Synchronises. */
+vflb_status vflb_mlp_train(vflb_mlp *mlp, const float *dev_X, const float *dev_T,
+                           int64_t n, int64_t rows, int64_t iters, float lr,
+                           uint64_t seed, int64_t log_every, double *losses);
+
 /* Initialise a D2Q9 simulation from the network: inputs (x/nx, y/ny,
  * extra[0], extra[1], extra[2]) at every node, u = u_scale (y0, y1),
- * tau = tau_scale (y2, y3, y4), pressure 0; on a lattice periodic on every
- * axis the domain mean of u is removed (its total momentum changes only by
- * the summed force, so a steady state keeps the initial momentum, zero for
- * a start from rest); then as vflb_init_fields,
+ * tau = tau_scale (y2, y3, y4), pressure 0.  On a lattice periodic on every
+ * axis (sides <= 512), u is projected onto the fields without central
+ * divergence (the step's gradient stencil), without mean and without the
+ * modes (pi, 0), (0, pi), (pi, pi) that stencil cannot see: a periodic
+ * lattice conserves the total momentum (the force permitting) and, up to
+ * sign, the staggered momentum, so a start from rest has none of either.
+ * The conformation tensor A = I + lambda tau / eta_p is kept positive
+ * definite (eigenvalues raised to at least 0.05).  Then as vflb_init_fields,
  * followed by settle_steps settling steps towards those fields with
  * settle_flags (as vflb_settle; ignored when settle_steps is 0).  The
  * simulation's residual snapshot buffer serves as scratch; both handles must

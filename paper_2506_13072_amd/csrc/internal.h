@@ -9,12 +9,22 @@
 namespace vflb {
 namespace internal {
 
-// Shape, wall bits (bit a: walls on axis a), stream and the
-// residual-snapshot buffer of a simulation, which a caller may use as
-// scratch before (re)initialising it: FP32 fields of up to `bytes` bytes.
-// Needs bound buffers and parameters.
-vflb_status sim_scratch(vflb_sim* s, int* D, int* nx, int* ny, int* walls, hipStream_t* stream,
-                        void** scratch, size_t* bytes);
+// What a warm start needs to know of a simulation before (re)initialising
+// it: shape, wall bits (bit a: walls on axis a), stream, lambda / eta_p
+// (0 without polymer), and two device buffers it may use as scratch until
+// then: the residual-snapshot buffer (FP32 fields of up to `bytes` bytes)
+// and the second population buffer (`big`, `big_bytes`; 256 bytes in
+// place).  Needs bound buffers and parameters.
+struct SimScratch {
+  int D, nx, ny, walls;
+  hipStream_t stream;
+  double lam_over_eta;
+  void* scratch;
+  size_t bytes;
+  void* big;
+  size_t big_bytes;
+};
+vflb_status sim_scratch(vflb_sim* s, SimScratch* out);
 
 // vflb_init_fields from FP32 component-major device fields u [D][N] and
 // tau [NC][N] (pressure 0).

@@ -38,7 +38,8 @@ template <class R> struct ForceArgs {
   R F0[3];        // uniform force (CONST, COS_T at this time level)
   R amp[2];       // FOUR_ROLL amplitudes
   const R* tab;   // FOUR_ROLL tables: sin(kx x)[nx], cos(kx x)[nx], sin(ky y)[ny], cos(ky y)[ny]
-  const R* div;   // D2Q9 stress-divergence scheme: div tau_p [2][nx ny] added to F; else null
+  const R* div;   // stress-divergence scheme: div tau_p [div_d][N] added to F; else null
+  int div_d;      // components of div (the lattice dimension)
 };
 
 template <class S> struct StepArgs {
@@ -108,9 +109,13 @@ __device__ inline size_t pull_index(int i, int x, int y, int z, const Geo& g) {
   return tuple_of<D>(j, node_of(s[0], s[1], s[2], g), g.N);
 }
 
+// Body force at node (x, y, z) of the lattice g: the force field of fa
+// (four-roll tables depend on x and y only), plus div tau_p of that node in
+// the stress-divergence scheme.
 template <class R>
-__device__ inline void force_at(const ForceArgs<R>& fa, int x, int y, int nx,
-                                int ny, R* F) {
+__device__ inline void force_at(const ForceArgs<R>& fa, int x, int y, int z, const Geo& g,
+                                R* F) {
+  const int nx = g.nx, ny = g.ny;
   F[0] = F[1] = F[2] = 0;
   if (fa.kind == FORCE_CONST || fa.kind == FORCE_COS_T) {
     F[0] = fa.F0[0];
@@ -125,9 +130,10 @@ __device__ inline void force_at(const ForceArgs<R>& fa, int x, int y, int nx,
     F[1] = fa.amp[1] * cx[x] * sy[y];
   }
   if (fa.div) {
-    const size_t n = (size_t)y * nx + x, M = (size_t)nx * ny;
+    const size_t n = ((size_t)z * ny + y) * nx + x, M = g.N;
     F[0] += fa.div[n];
     F[1] += fa.div[M + n];
+    if (fa.div_d == 3) F[2] += fa.div[2 * M + n];
   }
 }
 
@@ -194,7 +200,7 @@ __device__ inline void node_moments(const S* pin, const typename StoreT<S>::R* a
     for (int c = 0; c < NC; ++c) m.h[c][i] = hv[c];
   }
   R F[3];
-  force_at<R>(fa, x, y, g.nx, g.ny, F);
+  force_at<R>(fa, x, y, z, g, F);
   m.u[2] = 0;
 #pragma unroll
   for (int b = 0; b < D; ++b) {
@@ -583,36 +589,47 @@ typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 // differences, one-sided second order normal to a wall (stress_div_kernel);
 // the step kernels add it to F wherever they evaluate the force.  D2Q9.
 
-template <class S>
+template <int D, class S>
 __global__ void __launch_bounds__(256) taup_kernel(const S* __restrict__ pin, Geo g,
                                                    typename StoreT<S>::R eta_over_lam,
                                                    typename StoreT<S>::R* __restrict__ taup) {
   using R = typename StoreT<S>::R;
+  using L = Lat<D>;
+  constexpr int Q = L::Q, NC = L::NC;
   const size_t N = g.N;
   for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
        n += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
-    R e[3] = {0, 0, 0};
+    int x, y, z;
+    node_xyz<D>(n, g, x, y, z);
+    R e[NC];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      R f, hv[3];
-      if constexpr (StoreT<S>::kPlanar)
-        Pops<2, S>::load(pin, pull_index<2>(i, x, y, 0, g), N, (R)1, (R)1, f, hv);
+    for (int c = 0; c < NC; ++c) e[c] = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R f, hv[NC];
+      const size_t t = pull_index<D>(i, x, y, z, g);
+      if constexpr (D == 2 && !StoreT<S>::kPlanar)
+        Pops<2, S>::template load<true>(pin, t, N, (R)1, (R)1, f, hv);
       else
-        Pops<2, S>::template load<true>(pin, pull_index<2>(i, x, y, 0, g), N, (R)1, (R)1, f, hv);
+        Pops<D, S>::load(pin, t, N, (R)1, (R)1, f, hv);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) e[c] += hv[c];
+      for (int c = 0; c < NC; ++c) e[c] += hv[c];
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) taup[(size_t)c * N + n] = eta_over_lam * e[c];
+    for (int c = 0; c < NC; ++c) taup[(size_t)c * N + n] = eta_over_lam * e[c];
   }
 }
 
-// derivative along axis a (0: x, 1: y) of the plane t at node (x, y)
+// derivative along axis a of the plane t at node (x, y, z): second-order
+// central differences, periodic wrap; next to a wall the one-sided second
+// order (-3 t0 + 4 t1 - t2)/2 (first order with two nodes across)
 template <class R>
-__device__ inline R stress_derivative(const R* t, int x, int y, int a, const Geo& g) {
-  const int n = a == 0 ? g.nx : g.ny, c = a == 0 ? x : y;
-  auto at = [&](int k) { return a == 0 ? t[(size_t)y * g.nx + k] : t[(size_t)k * g.nx + x]; };
+__device__ inline R stress_derivative(const R* t, int x, int y, int z, int a, const Geo& g) {
+  const int n = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz), c = a == 0 ? x : (a == 1 ? y : z);
+  auto at = [&](int k) {
+    const int xx = a == 0 ? k : x, yy = a == 1 ? k : y, zz = a == 2 ? k : z;
+    return t[((size_t)zz * g.ny + yy) * g.nx + xx];
+  };
   if (!(g.walls & (1 << a))) {
     const int cm = c == 0 ? n - 1 : c - 1, cp = c == n - 1 ? 0 : c + 1;
     return (R)0.5 * (at(cp) - at(cm));
@@ -624,18 +641,29 @@ __device__ inline R stress_derivative(const R* t, int x, int y, int a, const Geo
   return (R)0.5 * ((R)3 * at(n - 1) - (R)4 * at(n - 2) + at(n - 3));
 }
 
-template <class R>
+// (div tau_p)_b = sum_a d_a tau_ab, tau_p [NC][N] in the component order of
+// the lattice (2D: xx, xy, yy; 3D: xx, yy, zz, xy, xz, yz)
+template <int D, class R>
 __global__ void __launch_bounds__(256) stress_div_kernel(const R* __restrict__ taup, Geo g,
                                                          R* __restrict__ div) {
+  using L = Lat<D>;
   const size_t N = g.N;
-  const R* txx = taup;
-  const R* txy = taup + N;
-  const R* tyy = taup + 2 * N;
   for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
        n += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
-    div[n] = stress_derivative(txx, x, y, 0, g) + stress_derivative(txy, x, y, 1, g);
-    div[N + n] = stress_derivative(txy, x, y, 0, g) + stress_derivative(tyy, x, y, 1, g);
+    int x, y, z;
+    node_xyz<D>(n, g, x, y, z);
+    R dv[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b) dv[b] = 0;
+#pragma unroll
+    for (int c = 0; c < L::NC; ++c) {
+      const R* t = taup + (size_t)c * N;
+      const int a = L::ca(c), b = L::cb(c);
+      dv[b] += stress_derivative(t, x, y, z, a, g);
+      if (a != b) dv[a] += stress_derivative(t, x, y, z, b, g);
+    }
+#pragma unroll
+    for (int b = 0; b < D; ++b) div[(size_t)b * N + n] = dv[b];
   }
 }
 

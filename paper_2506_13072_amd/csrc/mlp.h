@@ -270,6 +270,78 @@ __global__ void __launch_bounds__(256) cast_layer_kernel(const float* __restrict
   WT16[(size_t)k * out_pad + o] = w16;
 }
 
+// Per-output mean and standard deviation of the targets T [n][out] (FP64,
+// two passes, fixed order; one workgroup per output column): stats[c] the
+// mean, stats[out + c] the standard deviation (1 where it is 0).
+__global__ void __launch_bounds__(256) col_stats_kernel(const float* __restrict__ T, int64_t n,
+                                                        int out, double* __restrict__ stats) {
+  const int c = blockIdx.x;
+  __shared__ double red[256];
+  auto block_sum = [&](double v) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+  };
+  double s = 0.0;
+  for (int64_t m = threadIdx.x; m < n; m += 256) s += (double)T[m * out + c];
+  const double mean = block_sum(s) / (double)n;
+  double q = 0.0;
+  for (int64_t m = threadIdx.x; m < n; m += 256) {
+    const double d = (double)T[m * out + c] - mean;
+    q += d * d;
+  }
+  const double var = block_sum(q) / (double)n;
+  if (threadIdx.x == 0) {
+    stats[c] = mean;
+    stats[out + c] = var > 0.0 ? sqrt(var) : 1.0;
+  }
+}
+
+// A random minibatch of `rows` rows of (X [n][in_dim], T [n][out]): row r
+// takes sample floor(z n / 2^64), z the output of position key + r of the
+// SplitMix64 stream (Steele, Lea, Flood 2014; counter-based, so every row is
+// drawn independently of the launch shape); targets standardised with
+// stats (mean, std).
+__global__ void __launch_bounds__(256) gather_kernel(const float* __restrict__ X,
+                                                     const float* __restrict__ T, int64_t n,
+                                                     int in_dim, int out, int rows,
+                                                     uint64_t seed, uint64_t key,
+                                                     const double* __restrict__ stats,
+                                                     float* __restrict__ xb,
+                                                     float* __restrict__ tb) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  uint64_t z = seed + (key + (uint64_t)r + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const int64_t m = (int64_t)__umul64hi(z, (uint64_t)n);
+  for (int d = 0; d < in_dim; ++d) xb[(size_t)r * in_dim + d] = X[m * in_dim + d];
+  for (int c = 0; c < out; ++c)
+    tb[(size_t)r * out + c] =
+        (float)(((double)T[m * out + c] - stats[c]) / stats[out + c]);
+}
+
+// Fold the target standardisation into the output layer (W [out][in],
+// b [out], FP32): the network then predicts std * y + mean.
+__global__ void __launch_bounds__(256) fold_output_kernel(float* __restrict__ W,
+                                                          float* __restrict__ b, int out, int in,
+                                                          const double* __restrict__ stats) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < out * in) {
+    W[i] = (float)((double)W[i] * stats[out + i / in]);
+  } else if (i < out * in + out) {
+    const int o = i - out * in;
+    b[o] = (float)((double)b[o] * stats[out + o] + stats[o]);
+  }
+}
+
 // Network inputs of the nodes [n0, n0 + cnt) of an nx x ny lattice:
 // (x / nx, y / ny, extra[0], extra[1], extra[2]).
 __global__ void __launch_bounds__(256) node_inputs_kernel(int nx, int ny, size_t n0, int cnt,
@@ -304,32 +376,102 @@ __global__ void __launch_bounds__(256) node_outputs_kernel(const float* __restri
   tau[2 * N + n] = tau_scale * r[4];
 }
 
-// Remove the domain mean of each velocity component of u [2][N] (FP32):
-// one workgroup, FP64 sums in a fixed order.  On a lattice periodic on
-// every axis the total momentum changes only by the summed body force, so
-// a steady state keeps the momentum of its initial state; a prediction
-// with a mean flow would carry it for good (and, against a forcing pattern
-// fixed in space, never settle).
-__global__ void __launch_bounds__(1024) zero_mean_kernel(float* __restrict__ u, size_t N) {
-  __shared__ double red[2][1024];
-  for (int c = 0; c < 2; ++c) {
-    double s = 0.0;
-    for (size_t n = threadIdx.x; n < N; n += 1024) s += (double)u[(size_t)c * N + n];
-    red[c][threadIdx.x] = s;
+// ---------------------------------------------------------------------
+// Projection of a predicted velocity onto the discretely solenoidal fields
+// of a periodic nx x ny lattice.  The step's velocity gradient is the
+// central difference, whose Fourier symbol is i (sin kx, sin ky); the
+// projection removes the part of each mode along that symbol (its central
+// divergence), and the four modes where the symbol vanishes: the mean
+// (kx, ky) = (0, 0), whose momentum a fully periodic lattice conserves, and
+// (pi, 0), (0, pi), (pi, pi), which the gradient cannot see and on which
+// streaming flips the sign of the momentum every step (the staggered
+// momentum is conserved up to sign), so that a prediction carrying them
+// would keep them for good.  Both are absent from a start from rest.
+// Naive separable DFTs (n <= 512 per axis): complex FP32 fields, FP64 sums.
+
+// real [ncomp][N] -> complex
+__global__ void __launch_bounds__(256) to_complex_kernel(const float* __restrict__ in, size_t cnt,
+                                                         float2* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < cnt) out[i] = make_float2(in[i], 0.0f);
+}
+
+// One DFT pass of ncomp complex fields [ncomp][ny][nx] along x (axis 0) or
+// y (axis 1) with exponent sign sgn: out(k) = sum_j in(j) exp(sgn 2 pi i k j / n).
+__global__ void __launch_bounds__(256) dft_pass_kernel(const float2* __restrict__ in,
+                                                       float2* __restrict__ out, int nx, int ny,
+                                                       int ncomp, int axis, int sgn) {
+  const size_t N = (size_t)nx * ny, idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)ncomp * N) return;
+  const size_t c = idx / N, r = idx % N;
+  const int y = (int)(r / nx), x = (int)(r % nx);
+  const int n = axis == 0 ? nx : ny, k = axis == 0 ? x : y;
+  const float2* src = in + c * N;
+  double re = 0.0, im = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const float2 v = axis == 0 ? src[(size_t)y * nx + j] : src[(size_t)j * nx + x];
+    const long long m = ((long long)k * j) % n;
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)n, &sn, &cs);
+    sn *= (double)sgn;
+    re += (double)v.x * cs - (double)v.y * sn;
+    im += (double)v.x * sn + (double)v.y * cs;
   }
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] += red[1][threadIdx.x + w];
-    }
-    __syncthreads();
+  out[idx] = make_float2((float)re, (float)im);
+}
+
+// Remove from U [2][ny][nx] (spectrum of u) its part along the central
+// difference symbol, and the modes where that symbol vanishes.
+__global__ void __launch_bounds__(256) solenoidal_kernel(float2* __restrict__ U, int nx, int ny) {
+  const size_t N = (size_t)nx * ny, r = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= N) return;
+  const int ky = (int)(r / nx), kx = (int)(r % nx);
+  const double sx = sinpi(2.0 * kx / nx), sy = sinpi(2.0 * ky / ny);
+  const bool blind = (2 * kx) % nx == 0 && (2 * ky) % ny == 0;
+  const float2 a = U[r], b = U[N + r];
+  if (blind) {
+    U[r] = make_float2(0.0f, 0.0f);
+    U[N + r] = make_float2(0.0f, 0.0f);
+    return;
   }
-  const float m0 = (float)(red[0][0] / (double)N), m1 = (float)(red[1][0] / (double)N);
-  for (size_t n = threadIdx.x; n < N; n += 1024) {
-    u[n] -= m0;
-    u[N + n] -= m1;
+  const double ss = sx * sx + sy * sy;
+  const double dr = (sx * a.x + sy * b.x) / ss, di = (sx * a.y + sy * b.y) / ss;
+  U[r] = make_float2((float)(a.x - sx * dr), (float)(a.y - sx * di));
+  U[N + r] = make_float2((float)(b.x - sy * dr), (float)(b.y - sy * di));
+}
+
+// real part / N back into u [2][N]
+__global__ void __launch_bounds__(256) from_complex_kernel(const float2* __restrict__ in,
+                                                           size_t cnt, double inv_n,
+                                                           float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < cnt) out[i] = (float)((double)in[i].x * inv_n);
+}
+
+// Keep the predicted conformation tensor A = I + c tau (c = lambda/eta_p)
+// positive definite, as Oldroyd-B keeps it: its eigenvalues are raised to
+// at least a_min, eigenvectors kept; tau [3][N] (xx, xy, yy) rewritten.
+__global__ void __launch_bounds__(256) conformation_floor_kernel(float* __restrict__ tau, size_t N,
+                                                                 double c, double a_min) {
+  const size_t n = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const double axx = 1.0 + c * tau[n], axy = c * tau[N + n], ayy = 1.0 + c * tau[2 * N + n];
+  const double m = 0.5 * (axx + ayy), d = 0.5 * (axx - ayy), r = sqrt(d * d + axy * axy);
+  const double l1 = m + r, l2 = m - r;
+  if (l2 >= a_min) return;
+  const double m1 = l1 > a_min ? l1 : a_min, m2 = a_min;
+  // A' = m1 e1 e1^T + m2 e2 e2^T, e1 the eigenvector of l1
+  double ex = 1.0, ey = 0.0;
+  if (r > 0) {
+    const double th = 0.5 * atan2(2.0 * axy, axx - ayy);
+    ex = cos(th);
+    ey = sin(th);
   }
+  const double bxx = m1 * ex * ex + m2 * ey * ey, bxy = (m1 - m2) * ex * ey,
+               byy = m1 * ey * ey + m2 * ex * ex;
+  tau[n] = (float)((bxx - 1.0) / c);
+  tau[N + n] = (float)(bxy / c);
+  tau[2 * N + n] = (float)((byy - 1.0) / c);
 }
 
 }  // namespace mlp

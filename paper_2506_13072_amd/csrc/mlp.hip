@@ -30,7 +30,7 @@ struct vflb_mlp {
   std::vector<size_t> oW, ob, omW, ovW, omb, ovb, oW16, oWT16, oG, ogb;
   // WORK buffer (byte offsets)
   size_t off_x = 0, off_phi = 0, off_phiT = 0, off_Y = 0, off_dY = 0, off_dYT = 0, off_P = 0,
-         off_lpart = 0, off_loss = 0;
+         off_lpart = 0, off_loss = 0, off_tb = 0, off_stats = 0;
   std::vector<size_t> oH32, oH16, oHT16;
   size_t off_dZ[2] = {0, 0}, off_dZT[2] = {0, 0};
   size_t p_floats = 0;  // capacity of the split-K partial buffer
@@ -48,6 +48,8 @@ namespace {
 thread_local std::string g_mlp_create_error;
 constexpr int kOutPad = 64;   // padded width of the output layer
 constexpr int kMaxSplit = 32; // split-K slices of the weight gradients
+// smallest eigenvalue of a predicted conformation tensor (A = I at rest)
+constexpr double kConformationFloor = 0.05;
 
 size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -265,6 +267,39 @@ vflb_status upload(vflb_mlp* m, const float* host) {
   return VFLB_OK;
 }
 
+// one Adam step (learning rate lr) of every layer from the gradients in
+// PARAMS; refreshes the BF16 weight copies
+vflb_status adam_update(vflb_mlp* m, float lr) {
+  m->adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  for (int l = 0; l < m->nl; ++l) {
+    AdamArgs a{};
+    a.W = m->p<float>(m->oW[l]);
+    a.b = m->p<float>(m->ob[l]);
+    a.mW = m->p<float>(m->omW[l]);
+    a.vW = m->p<float>(m->ovW[l]);
+    a.mb = m->p<float>(m->omb[l]);
+    a.vb = m->p<float>(m->ovb[l]);
+    a.G = m->p<float>(m->oG[l]);
+    a.gb = m->p<float>(m->ogb[l]);
+    a.W16 = m->p<bf16>(m->oW16[l]);
+    a.WT16 = m->p<bf16>(m->oWT16[l]);
+    a.out = m->lout[l];
+    a.in = m->lin[l];
+    a.out_pad = m->lpad[l];
+    a.lr = lr;
+    a.beta1 = b1;
+    a.beta2 = b2;
+    a.eps = 1e-8f;
+    a.c1 = (float)(1.0 - std::pow((double)b1, (double)m->adam_t));
+    a.c2 = (float)(1.0 - std::pow((double)b2, (double)m->adam_t));
+    const int cnt = a.out * a.in + a.out;
+    hipLaunchKernelGGL(adam_kernel, dim3((cnt + 255) / 256), dim3(256), 0, m->stream, a);
+    MHIP_TRY(m, hipGetLastError());
+  }
+  return VFLB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -339,6 +374,8 @@ vflb_status vflb_mlp_create(const vflb_mlp_cfg* cfg, void* hip_stream, vflb_mlp*
   m->off_P = o; o += a256(4 * m->p_floats);
   m->off_lpart = o; o += a256(8 * ((M + 255) / 256));
   m->off_loss = o; o += 256;
+  m->off_tb = o; o += a256(4 * M * c.out_dim);
+  m->off_stats = o; o += a256(8 * 2 * c.out_dim);
   m->bytes[VFLB_MLP_BUF_WORK] = o;
   *out = m;
   return VFLB_OK;
@@ -467,33 +504,7 @@ vflb_status vflb_mlp_train_step(vflb_mlp* m, const float* dev_x, const float* de
   const int rows = rows_of(n);
   if ((rc = forward(m, dev_x, n, rows)) != VFLB_OK) return rc;
   if ((rc = backward(m, dev_t, n, rows)) != VFLB_OK) return rc;
-  m->adam_t += 1;
-  const float b1 = 0.9f, b2 = 0.999f;
-  for (int l = 0; l < m->nl; ++l) {
-    AdamArgs a{};
-    a.W = m->p<float>(m->oW[l]);
-    a.b = m->p<float>(m->ob[l]);
-    a.mW = m->p<float>(m->omW[l]);
-    a.vW = m->p<float>(m->ovW[l]);
-    a.mb = m->p<float>(m->omb[l]);
-    a.vb = m->p<float>(m->ovb[l]);
-    a.G = m->p<float>(m->oG[l]);
-    a.gb = m->p<float>(m->ogb[l]);
-    a.W16 = m->p<bf16>(m->oW16[l]);
-    a.WT16 = m->p<bf16>(m->oWT16[l]);
-    a.out = m->lout[l];
-    a.in = m->lin[l];
-    a.out_pad = m->lpad[l];
-    a.lr = lr;
-    a.beta1 = b1;
-    a.beta2 = b2;
-    a.eps = 1e-8f;
-    a.c1 = (float)(1.0 - std::pow((double)b1, (double)m->adam_t));
-    a.c2 = (float)(1.0 - std::pow((double)b2, (double)m->adam_t));
-    const int cnt = a.out * a.in + a.out;
-    hipLaunchKernelGGL(adam_kernel, dim3((cnt + 255) / 256), dim3(256), 0, m->stream, a);
-    MHIP_TRY(m, hipGetLastError());
-  }
+  if ((rc = adam_update(m, lr)) != VFLB_OK) return rc;
   if (loss_out) {
     double s = 0;
     MHIP_TRY(m, hipMemcpyAsync(&s, m->w<double>(m->off_loss), sizeof s, hipMemcpyDeviceToHost,
@@ -501,6 +512,64 @@ vflb_status vflb_mlp_train_step(vflb_mlp* m, const float* dev_x, const float* de
     MHIP_TRY(m, hipStreamSynchronize(m->stream));
     *loss_out = s / ((double)n * m->cfg.out_dim);
   }
+  return VFLB_OK;
+}
+
+vflb_status vflb_mlp_train(vflb_mlp* m, const float* dev_X, const float* dev_T, int64_t n,
+                           int64_t rows, int64_t iters, float lr, uint64_t seed,
+                           int64_t log_every, double* losses) {
+  vflb_status rc = need_mlp(m);
+  if (rc != VFLB_OK) return rc;
+  if (!dev_X || !dev_T || n < 1) return mfail(m, VFLB_EINVAL, "need n >= 1 and device data");
+  if (rows < 1 || rows > m->cfg.max_batch)
+    return mfail(m, VFLB_EINVAL, "need 1 <= rows <= max_batch");
+  if (iters < 0 || !(lr > 0)) return mfail(m, VFLB_EINVAL, "need iters >= 0 and lr > 0");
+  if (log_every < 0 || (log_every > 0 && !losses))
+    return mfail(m, VFLB_EINVAL, "log_every > 0 needs a losses array");
+  const vflb_mlp_cfg& c = m->cfg;
+  double* stats = m->w<double>(m->off_stats);
+  hipLaunchKernelGGL(col_stats_kernel, dim3(c.out_dim), dim3(256), 0, m->stream, dev_T, n,
+                     c.out_dim, stats);
+  MHIP_TRY(m, hipGetLastError());
+  float* xb = m->w<float>(m->off_x);
+  float* tb = m->w<float>(m->off_tb);
+  const int prow = rows_of(rows);
+  for (int64_t it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
+                       m->stream, dev_X, dev_T, n, c.in_dim, c.out_dim, (int)rows, seed,
+                       (uint64_t)it * (uint64_t)rows, stats, xb, tb);
+    MHIP_TRY(m, hipGetLastError());
+    const double cosr = 0.5 * (1.0 + std::cos(3.14159265358979323846 * (double)it / (double)iters));
+    const float rate = (float)std::max((double)lr * cosr, 1e-3 * (double)lr);
+    if ((rc = forward(m, xb, rows, prow)) != VFLB_OK) return rc;
+    if ((rc = backward(m, tb, rows, prow)) != VFLB_OK) return rc;
+    if ((rc = adam_update(m, rate)) != VFLB_OK) return rc;
+    if (log_every > 0 && (it % log_every == 0 || it == iters - 1)) {
+      double sq = 0;
+      MHIP_TRY(m, hipMemcpyAsync(&sq, m->w<double>(m->off_loss), sizeof sq,
+                                 hipMemcpyDeviceToHost, m->stream));
+      MHIP_TRY(m, hipStreamSynchronize(m->stream));
+      losses[it / log_every + (it % log_every ? 1 : 0)] = sq / ((double)rows * c.out_dim);
+    }
+  }
+  // the network learned standardised targets: fold (mean, std) into its
+  // output layer, so that it predicts the targets themselves; the Adam
+  // moments no longer match the folded layer and are reset
+  const int L = m->nl - 1;
+  const int cnt = m->lout[L] * m->lin[L] + m->lout[L];
+  hipLaunchKernelGGL(fold_output_kernel, dim3((cnt + 255) / 256), dim3(256), 0, m->stream,
+                     m->p<float>(m->oW[L]), m->p<float>(m->ob[L]), m->lout[L], m->lin[L], stats);
+  MHIP_TRY(m, hipGetLastError());
+  if ((rc = recast(m)) != VFLB_OK) return rc;
+  for (int l = 0; l < m->nl; ++l) {
+    const size_t wbytes = sizeof(float) * m->lout[l] * m->lin[l], bbytes = sizeof(float) * m->lpad[l];
+    MHIP_TRY(m, hipMemsetAsync(m->p<float>(m->omW[l]), 0, wbytes, m->stream));
+    MHIP_TRY(m, hipMemsetAsync(m->p<float>(m->ovW[l]), 0, wbytes, m->stream));
+    MHIP_TRY(m, hipMemsetAsync(m->p<float>(m->omb[l]), 0, bbytes, m->stream));
+    MHIP_TRY(m, hipMemsetAsync(m->p<float>(m->ovb[l]), 0, bbytes, m->stream));
+  }
+  m->adam_t = 0;
+  MHIP_TRY(m, hipStreamSynchronize(m->stream));
   return VFLB_OK;
 }
 
@@ -512,19 +581,16 @@ vflb_status vflb_init_from_mlp(vflb_sim* sim, vflb_mlp* m, const double extra[3]
   if (settle_steps < 0) return mfail(m, VFLB_EINVAL, "settle_steps < 0");
   if (m->cfg.in_dim != 5 || m->cfg.out_dim != 5)
     return mfail(m, VFLB_EINVAL, "the network must map 5 inputs to 5 outputs");
-  int D = 0, nx = 0, ny = 0, walls = 0;
-  void* scratch = nullptr;
-  size_t scratch_bytes = 0;
-  hipStream_t st = nullptr;
-  if ((rc = vflb::internal::sim_scratch(sim, &D, &nx, &ny, &walls, &st, &scratch,
-                                        &scratch_bytes)) !=
-      VFLB_OK)
+  vflb::internal::SimScratch ss{};
+  if ((rc = vflb::internal::sim_scratch(sim, &ss)) != VFLB_OK)
     return mfail(m, rc, "simulation: %s", vflb_last_error(sim));
-  if (D != 2) return mfail(m, VFLB_EINVAL, "the warm start fills D2Q9 lattices");
-  if (st != m->stream) return mfail(m, VFLB_EINVAL, "simulation and network need the same stream");
+  if (ss.D != 2) return mfail(m, VFLB_EINVAL, "the warm start fills D2Q9 lattices");
+  if (ss.stream != m->stream)
+    return mfail(m, VFLB_EINVAL, "simulation and network need the same stream");
+  const int nx = ss.nx, ny = ss.ny;
   const size_t N = (size_t)nx * ny;
-  if (scratch_bytes < 5 * N * sizeof(float)) return mfail(m, VFLB_ENOMEM, "scratch too small");
-  float* u = static_cast<float*>(scratch);
+  if (ss.bytes < 5 * N * sizeof(float)) return mfail(m, VFLB_ENOMEM, "scratch too small");
+  float* u = static_cast<float*>(ss.scratch);
   float* tau = u + 2 * N;
   float* X = m->w<float>(m->off_x);
   for (size_t s = 0; s < N; s += m->cfg.max_batch) {
@@ -538,9 +604,29 @@ vflb_status vflb_init_from_mlp(vflb_sim* sim, vflb_mlp* m, const double extra[3]
                        (float)tau_scale, u, tau);
     MHIP_TRY(m, hipGetLastError());
   }
-  if (walls == 0) {
-    // periodic on every axis: start with the zero momentum of the cold start
-    hipLaunchKernelGGL(zero_mean_kernel, dim3(1), dim3(1024), 0, m->stream, u, N);
+  const unsigned g1 = (unsigned)((N + 255) / 256), g2 = (unsigned)((2 * N + 255) / 256);
+  if (ss.walls == 0) {
+    // periodic on every axis: project u onto the discretely solenoidal
+    // fields, without mean and staggered momentum, as a start from rest is
+    if (nx > 512 || ny > 512)
+      return mfail(m, VFLB_EINVAL, "the velocity projection runs on lattices of side <= 512");
+    if (ss.big_bytes < 2 * 2 * N * sizeof(float2))
+      return mfail(m, VFLB_EINVAL, "the warm start needs two population buffers");
+    float2* A = static_cast<float2*>(ss.big);
+    float2* B = A + 2 * N;
+    hipLaunchKernelGGL(to_complex_kernel, dim3(g2), dim3(256), 0, m->stream, u, 2 * N, A);
+    hipLaunchKernelGGL(dft_pass_kernel, dim3(g2), dim3(256), 0, m->stream, A, B, nx, ny, 2, 0, -1);
+    hipLaunchKernelGGL(dft_pass_kernel, dim3(g2), dim3(256), 0, m->stream, B, A, nx, ny, 2, 1, -1);
+    hipLaunchKernelGGL(solenoidal_kernel, dim3(g1), dim3(256), 0, m->stream, A, nx, ny);
+    hipLaunchKernelGGL(dft_pass_kernel, dim3(g2), dim3(256), 0, m->stream, A, B, nx, ny, 2, 1, 1);
+    hipLaunchKernelGGL(dft_pass_kernel, dim3(g2), dim3(256), 0, m->stream, B, A, nx, ny, 2, 0, 1);
+    hipLaunchKernelGGL(from_complex_kernel, dim3(g2), dim3(256), 0, m->stream, A, 2 * N,
+                       1.0 / (double)N, u);
+    MHIP_TRY(m, hipGetLastError());
+  }
+  if (ss.lam_over_eta > 0) {
+    hipLaunchKernelGGL(conformation_floor_kernel, dim3(g1), dim3(256), 0, m->stream, tau, N,
+                       ss.lam_over_eta, kConformationFloor);
     MHIP_TRY(m, hipGetLastError());
   }
   if ((rc = vflb::internal::sim_init_f32(sim, u, tau)) != VFLB_OK)

@@ -212,7 +212,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
   // ---- velocities into LDS
   R u[3] = {0, 0, 0}, F[3] = {0, 0, 0};
   if (valid) {
-    force_at<R>(a.F, wx, wy, g.nx, g.ny, F);
+    force_at<R>(a.F, wx, wy, 0, g, F);
     velocity2(f, F, u);
     if (CLAMP && (a.clamp_flags & 1)) {
       u[0] = (R)a.clamp[(size_t)wy * g.nx + wx];
@@ -224,7 +224,7 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
   }
   if (hvalid) {
     R Fh[3], uh[3];
-    force_at<R>(a.F, hx, hy, g.nx, g.ny, Fh);
+    force_at<R>(a.F, hx, hy, 0, g, Fh);
     velocity2(fh, Fh, uh);
     if (CLAMP && (a.clamp_flags & 1)) {
       uh[0] = (R)a.clamp[(size_t)hy * g.nx + hx];
@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(256) aa_velocity_kernel(const S* __restrict__ 
     f[0] = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) f[i] = Pops<2, S>::load_f(pop, pull_index<2>(i, x, y, 0, g), N, inv_sf);
-    force_at<R>(fa, x, y, g.nx, g.ny, F);
+    force_at<R>(fa, x, y, 0, g, F);
     velocity2(f, F, u);
     U[n] = u[0];
     U[N + n] = u[1];
@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(256) aa_step_kernel(StepArgs<S> a,
     }
     if (!a.first) Aux<2, R>::load(aux, n, N, chip, up);
     R F[3] = {0, 0, 0};
-    force_at<R>(a.F, x, y, g.nx, g.ny, F);
+    force_at<R>(a.F, x, y, 0, g, F);
     const R u[3] = {U[n], U[N + n], (R)0};
     if constexpr (!kF64) __builtin_amdgcn_s_setprio(0);
     R e[NC];

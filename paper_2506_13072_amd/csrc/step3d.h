@@ -280,7 +280,9 @@ template <int TY> struct AnchorStage<true, TY> {
 // FP64 state and the anchored 16-bit step do not fit 256 VGPRs: they run one
 // wave per SIMD, which opens the accumulation registers to the allocator
 // instead of scratch memory.
-template <class S, int TY, int ZC, bool WALLS, bool FULL>
+// DIV: the stress-divergence scheme (the force of every node includes
+// div tau_p of its plane, read from a.F.div; no f^B).
+template <class S, int TY, int ZC, bool WALLS, bool FULL, bool DIV = false>
 __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchored) ? 1 : 2)
     step3d_kernel(StepArgs<S> a, int ntx, int nty) {
   using R = typename StoreT<S>::R;
@@ -352,9 +354,15 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
     hx = clampc(hx, g.nx);
     hy = clampc(hy, g.ny);
   }
+  // body force of the own column and the ring node, without div tau_p (the
+  // force fields are independent of z)
   R Fown[3] = {0, 0, 0}, Fring[3] = {0, 0, 0};
-  force_at<R>(a.F, ox, oy, g.nx, g.ny, Fown);
-  force_at<R>(a.F, hx, hy, g.nx, g.ny, Fring);
+  {
+    ForceArgs<R> fb = a.F;
+    fb.div = nullptr;
+    force_at<R>(fb, ox, oy, 0, g, Fown);
+    force_at<R>(fb, hx, hy, 0, g, Fring);
+  }
 
   // plane index for loads: wrapped, clamped beyond a wall (values unused)
   auto load_z = [&](int zp) {
@@ -365,6 +373,19 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   auto plane_ok = [&](int zp) {
     int zw = zp;
     return wrap_coord(zw, g.nz, g.walls & 4);
+  };
+  // the force at column (cx, cy) of plane zp: Fb, plus div tau_p there in
+  // the stress-divergence scheme (added as force_at adds it)
+  auto force_z = [&](int cx, int cy, int zp, const R* Fb, R* F) {
+    F[0] = Fb[0];
+    F[1] = Fb[1];
+    F[2] = Fb[2];
+    if constexpr (DIV) {
+      const size_t nd = node_of(cx, cy, load_z(zp), g);
+      F[0] += a.F.div[nd];
+      F[1] += a.F.div[N + nd];
+      F[2] += a.F.div[2 * N + nd];
+    }
   };
   // anchored storage: the anchors of plane zp (tile and two-node ring) into
   // its stage slot by LDS-DMA; a lane's slot index follows its lane number,
@@ -455,9 +476,11 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   auto publish_u = [&](int zp, const R* fo, const R* fr) {
     const bool ok = plane_ok(zp);
     const int rs = ring_slot(zp);
-    R u[3], v[3];
-    pair_velocity(fo, Fown, u);
-    pair_velocity(fr, Fring, v);
+    R u[3], v[3], Fo[3], Fr[3];
+    force_z(ox, oy, zp, Fown, Fo);
+    force_z(hx, hy, zp, Fring, Fr);
+    pair_velocity(fo, Fo, u);
+    pair_velocity(fr, Fr, v);
     if (ok && vxy && s == 0) {
       ring[rs][0][oslot] = u[0];
       ring[rs][1][oslot] = u[1];
@@ -600,7 +623,8 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
 #pragma clang fp contract(fast)
       const int rc = ring_slot(z), rm = ring_slot(z - 1), rp = ring_slot(z + 1);
       const R u[3] = {ring[rc][0][oslot], ring[rc][1][oslot], ring[rc][2][oslot]};
-      const R* F = Fown;
+      R F[3];
+      force_z(ox, oy, z, Fown, F);
       // moments of the pulled state
       R e[NC];
 #pragma unroll
@@ -618,7 +642,12 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
 #pragma unroll
       for (int c = 0; c < NC; ++c) tau[c] = a.P.eta_over_lam * e[c];
       R fB[L::Q];
-      fluct_term<R>(tau, a.P.inv_tau_f, fB, (L*)nullptr);
+      if constexpr (DIV) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) fB[i] = 0;
+      } else {
+        fluct_term<R>(tau, a.P.inv_tau_f, fB, (L*)nullptr);
+      }
       const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
       const R Fu = F[0] * u[0] + F[1] * u[1] + F[2] * u[2];
       constexpr R w0 = (R)L::w(0);

@@ -102,15 +102,35 @@ void drop_graphs(vflb_sim* s) {
 }
 
 // D3Q19: 32 x tile_y node columns, tile_y 4 (two workgroups per CU) or 8
-template <class S, int TY, int ZC, bool WALLS>
+template <class S, int TY, int ZC, bool WALLS, bool DIV = false>
 void launch_step3d(dim3 grid, hipStream_t st, const StepArgs<S>& a, int ntx, int nty, bool any_full,
                    bool any_ragged) {
   if (any_full)
-    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, true>), grid, dim3(64, TY), 0, st, a, ntx,
-                       nty);
-  if (any_ragged)
-    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, false>), grid, dim3(64, TY), 0, st, a,
+    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, true, DIV>), grid, dim3(64, TY), 0, st, a,
                        ntx, nty);
+  if (any_ragged)
+    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, false, DIV>), grid, dim3(64, TY), 0, st,
+                       a, ntx, nty);
+}
+
+// D3Q19 launches for tile height TY: walls or not, the stress-divergence
+// scheme or not (FP32 / FP64 storage only)
+template <class S, int TY, int ZC>
+void launch_step3d_ty(const vflb_sim* s, dim3 grid, hipStream_t st, const StepArgs<S>& a,
+                      int ntx, int nty, bool any_full, bool any_ragged) {
+  if constexpr (!StoreT<S>::kAnchored) {
+    if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
+      if (s->walls)
+        launch_step3d<S, TY, ZC, true, true>(grid, st, a, ntx, nty, any_full, any_ragged);
+      else
+        launch_step3d<S, TY, ZC, false, true>(grid, st, a, ntx, nty, any_full, any_ragged);
+      return;
+    }
+  }
+  if (s->walls)
+    launch_step3d<S, TY, ZC, true>(grid, st, a, ntx, nty, any_full, any_ragged);
+  else
+    launch_step3d<S, TY, ZC, false>(grid, st, a, ntx, nty, any_full, any_ragged);
 }
 
 int tile_y_3d(const vflb_sim* s) { return s->tile_y == 8 ? 8 : 4; }
@@ -148,10 +168,11 @@ ForceArgs<R> force_of(const vflb_sim* s, int64_t t) {
   fa.amp[0] = (R)s->famp[0];
   fa.amp[1] = (R)s->famp[1];
   fa.tab = reinterpret_cast<const R*>(static_cast<char*>(s->buf[VFLB_BUF_WORK]) + s->off_tab);
-  // stress-divergence scheme: div tau_p [2][N] after chi, u, tau_p in AUX
+  // stress-divergence scheme: div tau_p [D][N] after chi, u, tau_p in AUX
   fa.div = s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE
-               ? static_cast<const R*>(s->buf[VFLB_BUF_AUX]) + (size_t)(5 + 3) * s->N
-               : nullptr;  // D2Q9 only: chi, u are 5 words per node
+               ? static_cast<const R*>(s->buf[VFLB_BUF_AUX]) + (size_t)(2 * s->NC + s->D) * s->N
+               : nullptr;
+  fa.div_d = fa.div ? s->D : 0;
   if (s->fkind == VFLB_FORCE_CONST) {
     for (int a = 0; a < s->D; ++a) fa.F0[a] = (R)s->famp[a];
   } else if (s->fkind == VFLB_FORCE_COS_T) {
@@ -178,7 +199,8 @@ Geo geo_of(const vflb_sim* s) { return geo_of(s, s->t); }
 // tau_p [3][N], div tau_p [2][N]; in-place streaming: u(t) [2][N]
 size_t aux_taup_words(const vflb_sim* s) { return (size_t)(s->NC + s->D) * s->N; }
 size_t aux_u_words(const vflb_sim* s) {
-  return aux_taup_words(s) + (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? 5 * s->N : 0);
+  return aux_taup_words(s) +
+         (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? (size_t)(s->NC + s->D) * s->N : 0);
 }
 
 int grid1d(const vflb_sim* s, int block) {
@@ -221,12 +243,20 @@ vflb_status launch_divergence(vflb_sim* s, int64_t t, hipStream_t st, int parity
   } else {
     const S* pin = static_cast<const S*>(s->buf[VFLB_BUF_POP0 + (s->inplace ? 0 : parity)]);
     R* taup = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + aux_taup_words(s);
-    R* div = taup + (size_t)3 * s->N;
+    R* div = taup + (size_t)s->NC * s->N;
     const int g = grid1d(s, 256);
-    hipLaunchKernelGGL((taup_kernel<S>), dim3(g), dim3(256), 0, st, pin, geo_of(s, t),
-                       (R)(s->lp.eta_p / s->lp.lambda), taup);
-    hipLaunchKernelGGL((stress_div_kernel<R>), dim3(g), dim3(256), 0, st, taup, geo_of(s, t),
-                       div);
+    const R k = (R)(s->lp.eta_p / s->lp.lambda);
+    if (s->D == 2) {
+      hipLaunchKernelGGL((taup_kernel<2, S>), dim3(g), dim3(256), 0, st, pin, geo_of(s, t), k,
+                         taup);
+      hipLaunchKernelGGL((stress_div_kernel<2, R>), dim3(g), dim3(256), 0, st, taup,
+                         geo_of(s, t), div);
+    } else if constexpr (!StoreT<S>::kPlanar) {
+      hipLaunchKernelGGL((taup_kernel<3, S>), dim3(g), dim3(256), 0, st, pin, geo_of(s, t), k,
+                         taup);
+      hipLaunchKernelGGL((stress_div_kernel<3, R>), dim3(g), dim3(256), 0, st, taup,
+                         geo_of(s, t), div);
+    }
     HIP_TRY(s, hipGetLastError());
     return VFLB_OK;
   }
@@ -270,21 +300,11 @@ vflb_status launch_tiled(vflb_sim* s, hipStream_t st, StepArgs<S> a) {
     const bool any_ragged = s->nx % 32 != 0 || s->ny % ty != 0;
     bool eight = ty == 8;
     if constexpr (!StoreT<S>::kAnchored) {  // anchored 16-bit: 32 x 4 only (LDS)
-      if (eight) {
-        if (s->walls)
-          launch_step3d<S, 8, ZC, true>(grid, st, a, ntx, nty, any_full, any_ragged);
-        else
-          launch_step3d<S, 8, ZC, false>(grid, st, a, ntx, nty, any_full, any_ragged);
-      }
+      if (eight) launch_step3d_ty<S, 8, ZC>(s, grid, st, a, ntx, nty, any_full, any_ragged);
     } else {
       eight = false;
     }
-    if (!eight) {
-      if (s->walls)
-        launch_step3d<S, 4, ZC, true>(grid, st, a, ntx, nty, any_full, any_ragged);
-      else
-        launch_step3d<S, 4, ZC, false>(grid, st, a, ntx, nty, any_full, any_ragged);
-    }
+    if (!eight) launch_step3d_ty<S, 4, ZC>(s, grid, st, a, ntx, nty, any_full, any_ragged);
   }
   HIP_TRY(s, hipGetLastError());
   return VFLB_OK;
@@ -292,11 +312,9 @@ vflb_status launch_tiled(vflb_sim* s, hipStream_t st, StepArgs<S> a) {
 
 template <int D, class S>
 vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
-  if constexpr (D == 2) {
-    if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
-      vflb_status rc = launch_divergence<S>(s, t, st, parity);
-      if (rc != VFLB_OK) return rc;
-    }
+  if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
+    vflb_status rc = launch_divergence<S>(s, t, st, parity);
+    if (rc != VFLB_OK) return rc;
   }
   StepArgs<S> a = make_step_args<S>(s, t, parity);
   if constexpr (!StoreT<S>::kPlanar) {
@@ -349,11 +367,9 @@ int grid_for(size_t n) {
 template <int D, class S>
 vflb_status launch_moments(vflb_sim* s, int field, double* out, const Box& box) {
   using R = typename StoreT<S>::R;
-  if constexpr (D == 2) {  // the force of the current state includes div tau_p(t)
-    if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
-      vflb_status rc = launch_divergence<S>(s, s->t, s->stream, s->cur);
-      if (rc != VFLB_OK) return rc;
-    }
+  if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {  // the force includes div tau_p(t)
+    vflb_status rc = launch_divergence<S>(s, s->t, s->stream, s->cur);
+    if (rc != VFLB_OK) return rc;
   }
   R isf = (R)1, ish = (R)1;
   if (s->storage == VFLB_F16S) {
@@ -371,11 +387,9 @@ vflb_status launch_moments(vflb_sim* s, int field, double* out, const Box& box) 
 template <int D, class S>
 vflb_status launch_reduce(vflb_sim* s, double* dev_res) {
   using R = typename StoreT<S>::R;
-  if constexpr (D == 2) {
-    if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
-      vflb_status rc = launch_divergence<S>(s, s->t, s->stream, s->cur);
-      if (rc != VFLB_OK) return rc;
-    }
+  if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
+    vflb_status rc = launch_divergence<S>(s, s->t, s->stream, s->cur);
+    if (rc != VFLB_OK) return rc;
   }
   R isf = (R)1, ish = (R)1;
   if (s->storage == VFLB_F16S) {
@@ -532,10 +546,9 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
                 "storage there); use VFLB_F16S");
   if (scheme != VFLB_SCHEME_FLUCTUATING && scheme != VFLB_SCHEME_STRESS_DIVERGENCE)
     return fail(nullptr, VFLB_EINVAL, "unknown scheme %d", scheme);
-  if (scheme == VFLB_SCHEME_STRESS_DIVERGENCE &&
-      (lattice != VFLB_D2Q9 || (storage != VFLB_F32 && storage != VFLB_F64)))
+  if (scheme == VFLB_SCHEME_STRESS_DIVERGENCE && storage != VFLB_F32 && storage != VFLB_F64)
     return fail(nullptr, VFLB_EINVAL,
-                "the stress-divergence scheme runs on D2Q9 with FP32 or FP64 storage");
+                "the stress-divergence scheme runs with FP32 or FP64 storage");
   if (options & ~VFLB_OPT_INPLACE) return fail(nullptr, VFLB_EINVAL, "unknown options %#x", options);
   const bool inplace = (options & VFLB_OPT_INPLACE) != 0;
   if (inplace && (lattice != VFLB_D2Q9 || (storage != VFLB_F32 && storage != VFLB_F64) || view))
@@ -563,11 +576,11 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
   s->bytes[VFLB_BUF_POP0] = s->bytes[VFLB_BUF_POP1] = align256(
       anchored ? (lattice == VFLB_D2Q9 ? Anchor2::bytes(N) : Anchor3::bytes(N)) : sb * words);
   if (inplace) s->bytes[VFLB_BUF_POP1] = 256;  // unused
-  // AUX: chi(t-1), u(t-1); the stress-divergence scheme adds tau_p [3][N]
-  // and div tau_p [2][N]; in-place streaming u(t) [2][N]
+  // AUX: chi(t-1), u(t-1); the stress-divergence scheme adds tau_p [NC][N]
+  // and div tau_p [D][N]; in-place streaming u(t) [2][N]
   const size_t u_now = inplace ? 2 : 0;
-  s->bytes[VFLB_BUF_AUX] = align256(
-      ab * ((s->NC + s->D) + (scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? 5 : 0) + u_now) * N);
+  const size_t div_words = scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? s->NC + s->D : 0;
+  s->bytes[VFLB_BUF_AUX] = align256(ab * ((s->NC + s->D) + div_words + u_now) * N);
   s->bytes[VFLB_BUF_SNAP] = align256(ab * (s->NC + s->D) * N);
   s->off_tab = 0;
   s->off_part = align256(ab * 2 * ((size_t)nx + ny));
@@ -1587,17 +1600,19 @@ const char* vflb_batch_last_error(const vflb_batch* b) {
 namespace vflb {
 namespace internal {
 
-vflb_status sim_scratch(vflb_sim* s, int* D, int* nx, int* ny, int* walls, hipStream_t* stream,
-                        void** scratch, size_t* bytes) {
+vflb_status sim_scratch(vflb_sim* s, SimScratch* out) {
   vflb_status rc = need_ready(s);
   if (rc != VFLB_OK) return rc;
-  *D = s->D;
-  *nx = s->nx;
-  *ny = s->ny;
-  *walls = s->walls;
-  *stream = s->stream;
-  *scratch = s->buf[VFLB_BUF_SNAP];
-  *bytes = s->bytes[VFLB_BUF_SNAP];
+  out->D = s->D;
+  out->nx = s->nx;
+  out->ny = s->ny;
+  out->walls = s->walls;
+  out->stream = s->stream;
+  out->lam_over_eta = s->lp.eta_p > 0 ? s->lp.lambda / s->lp.eta_p : 0.0;
+  out->scratch = s->buf[VFLB_BUF_SNAP];
+  out->bytes = s->bytes[VFLB_BUF_SNAP];
+  out->big = s->buf[VFLB_BUF_POP1];
+  out->big_bytes = s->bytes[VFLB_BUF_POP1];
   return VFLB_OK;
 }
 

@@ -132,6 +132,8 @@ def lib():
         L.vflb_mlp_forward.argtypes = [P, P, P, I64]
         L.vflb_mlp_grad.argtypes = [P, P, P, I64, P, ctypes.POINTER(D)]
         L.vflb_mlp_train_step.argtypes = [P, P, P, I64, ctypes.c_float, ctypes.POINTER(D)]
+        L.vflb_mlp_train.argtypes = [P, P, P, I64, I64, I64, ctypes.c_float, ctypes.c_uint64,
+                                     I64, ctypes.POINTER(D)]
         L.vflb_init_from_mlp.argtypes = [P, P, ctypes.POINTER(D), D, D, I64, I]
         L.vflb_settle.argtypes = [P, P, I64, I]
         L.vflb_settle.restype = I
@@ -141,7 +143,7 @@ def lib():
         L.vflb_mlp_last_error.restype = ctypes.c_char_p
         for name in ("vflb_mlp_create", "vflb_mlp_query_buffers", "vflb_mlp_bind_buffers",
                      "vflb_mlp_init", "vflb_mlp_set_params", "vflb_mlp_get_params",
-                     "vflb_mlp_forward", "vflb_mlp_grad", "vflb_mlp_train_step",
+                     "vflb_mlp_forward", "vflb_mlp_grad", "vflb_mlp_train_step", "vflb_mlp_train",
                      "vflb_init_from_mlp"):
             getattr(L, name).restype = I
         L.vflb_batch_destroy.argtypes = [P]
@@ -572,6 +574,25 @@ class Mlp:
                                              ctypes.c_void_p(tt.data_ptr()), tx.shape[0],
                                              g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
         return loss.value, g
+
+    def train(self, X_dev, T_dev, rows, iters, lr, seed=0, log_every=0):
+        """vflb_mlp_train on device tensors X [n, in_dim], T [n, out_dim]
+        (random minibatches, cosine rate, target standardisation folded
+        into the output layer); returns the logged losses."""
+        n_log = (iters - 1) // log_every + 2 if log_every > 0 and iters > 0 else 0
+        losses = (ctypes.c_double * max(n_log, 1))()
+        self.torch.cuda.current_stream(self.device).synchronize()
+        _mcheck(self._h, lib().vflb_mlp_train(self._h, ctypes.c_void_p(X_dev.data_ptr()),
+                                              ctypes.c_void_p(T_dev.data_ptr()),
+                                              int(X_dev.shape[0]), int(rows), int(iters),
+                                              float(lr), int(seed) & ((1 << 64) - 1),
+                                              int(log_every), losses))
+        if not n_log:
+            return []
+        steps = list(range(0, iters, log_every))
+        if (iters - 1) % log_every:
+            steps.append(iters - 1)
+        return [(k, losses[j]) for j, k in enumerate(steps)]
 
     def train_step(self, x_dev, t_dev, lr, want_loss=True):
         """One Adam step on device tensors x [n, in_dim], t [n, out_dim]."""

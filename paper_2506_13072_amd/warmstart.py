@@ -1,10 +1,10 @@
 """Learned warm start for steady four-roll-mill states (orchestration only).
 
 Every computation runs in libvflb: batches of lattices run to their steady
-states (vflb_batch_run_until), the network trains on those states
-(vflb_mlp_train_step), and a new lattice starts from the network's
-prediction (vflb_init_from_mlp) instead of from rest.  This module only
-decides what to call.
+states (vflb_batch_run_until), the network trains on those states on the
+device (vflb_mlp_train: minibatch draws, standardised targets, Adam), and a
+new lattice starts from the network's prediction (vflb_init_from_mlp)
+instead of from rest.  This module only decides what to call.
 
 Inputs of the network per node: (x/n, y/n, w, b, r) with
 w = P (ln Wi - ln 0.1)/ln 50, b = P (beta - 0.1)/0.8, r = P ln Re: the
@@ -12,13 +12,17 @@ parameter coordinates span [0, P] with P = 1/4, so that the Gaussian
 frequencies vary the features four times more slowly along the parameters
 than across the lattice.  Outputs: (u/U0, v/U0, txx/S, txy/S, tyy/S) with
 the stress scale S = eta_p U0 k, k = 2 pi / n (viscous stress of the
-forcing mode).  Training standardises each output column; the affine map
-back is folded into the output layer afterwards, so the trained network
-predicts the normalised fields directly.
+forcing mode).
 
-Fallback: a warm-started lattice is abandoned for the cold run of the same
-lattice when its state is non-finite or its residual after K0 steps
-exceeds the cold run's residual after K0 steps.
+Fallback.  A warm run is judged without running the cold one: the training
+runs (from rest) give, for their parameters, the residual after K0 steps
+and the steps to the tolerance.  A held-out lattice takes both from its
+nearest training runs in (ln Wi, beta).  The warm run is abandoned for a
+cold start when its state is non-finite, when its residual after K0 steps
+exceeds the predicted cold residual, or when, after a further window of
+checks, the decay rate of its residual projects more steps to the
+tolerance than the predicted cold run needs.  Its steps so far are then
+counted on top of the cold run's.
 """
 from __future__ import annotations
 
@@ -62,16 +66,32 @@ def four_roll_batch(V, specs, storage="f32", stream=None):
     return b, scales
 
 
-def steady_states(V, specs, tol=1e-6, check_every=100, storage="f32"):
-    """Run every instance from rest to R < tol (or its cap) in one batch."""
+def residual_at(b, t_end, check_every):
+    """Step every active instance to time level t_end and return the
+    residuals over its last check_every steps."""
+    b.step(t_end - check_every - b[0].t)
+    b.reduce()
+    b.step(check_every)
+    return b.reduce()
+
+
+def cold_runs(V, specs, tol=1e-6, check_every=100, K0=1000, storage="f32", caps=None):
+    """Every instance from rest to R < tol (or its cap) in one batch, with its
+    residual after K0 steps on the way."""
     b, scales = four_roll_batch(V, specs, storage)
     for i in range(len(specs)):
         b[i].init_fields()
-    caps = [step_cap(V, sp) for sp in specs]
+    if caps is None:
+        caps = [max(step_cap(V, sp), K0 + check_every) for sp in specs]
     t0 = time.perf_counter()
+    red = residual_at(b, K0, check_every)
     steps, res, status = b.run_until(tol, check_every, caps)
-    return dict(batch=b, scales=scales, steps=steps, R=res, status=status,
+    return dict(batch=b, scales=scales, steps=steps, R=res, status=status, R_K0=red[:, 0].copy(),
                 seconds=time.perf_counter() - t0)
+
+
+# the training runs of earlier versions of this module went under this name
+steady_states = cold_runs
 
 
 def training_set(V, run, specs, which):
@@ -92,93 +112,144 @@ def training_set(V, run, specs, which):
     return np.concatenate(xs).astype(np.float32), np.concatenate(ts).astype(np.float32)
 
 
-def fold_output_affine(mlp, mean, std):
-    """Make the network predict std * y + mean: scale the rows of the last
-    layer and shift its bias (flat order: last layer W, then b, at the end)."""
-    p = mlp.get_params().astype(np.float64)
-    out = len(mean)
-    width = mlp.cfg["width"]
-    b0 = p.size - out
-    w0 = b0 - out * width
-    W = p[w0:b0].reshape(out, width)
-    p[w0:b0] = (W * std[:, None]).ravel()
-    p[b0:] = p[b0:] * std + mean
-    mlp.set_params(p.astype(np.float32))
-
-
 def train(mlp, X, T, iters, rows, lr, seed=0, log_every=0):
-    """Adam on random minibatches of `rows` points with a cosine-decayed
-    rate, on standardised targets; the standardisation is folded into the
-    output layer at the end.  Returns the loss history (standardised units,
-    every log_every iterations)."""
+    """vflb_mlp_train on the data set (copied to the device once): random
+    minibatches of `rows` points, cosine-decayed rate, targets standardised
+    and the standardisation folded into the output layer by the library.
+    Returns the loss history (standardised units)."""
     import torch
-    dev = mlp.device
-    mean = T.mean(0).astype(np.float64)
-    std = T.std(0).astype(np.float64)
-    std[std == 0] = 1.0
-    Xd = torch.as_tensor(X, device=dev)
-    Td = torch.as_tensor(((T - mean) / std).astype(np.float32), device=dev)
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
-    xb = torch.empty(rows, X.shape[1], device=dev)
-    tb = torch.empty(rows, T.shape[1], device=dev)
-    hist = []
-    torch.cuda.synchronize(dev)
-    with torch.cuda.stream(mlp.stream):
-        for it in range(iters):
-            idx = torch.randint(0, X.shape[0], (rows,), device=dev, generator=g)
-            torch.index_select(Xd, 0, idx, out=xb)
-            torch.index_select(Td, 0, idx, out=tb)
-            rate = lr * 0.5 * (1 + math.cos(math.pi * it / iters))
-            want = log_every and (it % log_every == 0 or it == iters - 1)
-            loss = mlp.train_step(xb, tb, max(rate, 1e-3 * lr), want_loss=bool(want))
-            if want:
-                hist.append((it, loss))
-    mlp.stream.synchronize()
-    fold_output_affine(mlp, mean, std)
-    return hist
+    Xd = torch.as_tensor(X, device=mlp.device)
+    Td = torch.as_tensor(T, device=mlp.device)
+    return mlp.train(Xd, Td, rows, iters, lr, seed=seed, log_every=log_every)
 
 
-def warm_vs_cold(V, mlp, specs, tol=1e-6, check_every=100, K0=1000, storage="f32",
-                 u_scale_factor=1.0, settle=0, settle_flags=2):
-    """Held-out instances from rest and from the network, with the fallback
-    rule at K0.  Returns per-instance step counts and timings."""
+class ColdModel:
+    """What the training runs (from rest) say about a cold run at new
+    parameters: the mean of log R(K0) and of log steps-to-tol over the k
+    nearest converged training runs in (ln Wi / ln 50, (beta - 0.1)/0.8)."""
+
+    def __init__(self, specs, run, k=3):
+        ok = [i for i in range(len(specs)) if run["status"][i] == 1]
+        self.P = np.array([self._coord(specs[i]) for i in ok])
+        self.logR = np.log(np.maximum(run["R_K0"][ok], 1e-300))
+        self.logS = np.log(run["steps"][ok].astype(np.float64))
+        self.k = min(k, len(ok))
+
+    @staticmethod
+    def _coord(sp):
+        return ((math.log(sp["Wi"]) - math.log(WI_LO)) / math.log(WI_HI / WI_LO),
+                (sp["beta"] - BETA_LO) / (BETA_HI - BETA_LO))
+
+    def predict(self, sp):
+        d = np.linalg.norm(self.P - np.array(self._coord(sp)), axis=1)
+        nn = np.argsort(d)[: self.k]
+        return float(np.exp(self.logR[nn].mean())), float(np.exp(self.logS[nn].mean()))
+
+
+def warm_runs(V, mlp, specs, model, tol=1e-6, check_every=100, K0=1000, window=5,
+              storage="f32", settle=0, settle_flags=2, u_scale_factor=1.0):
+    """Held-out instances started from the network, judged by the fallback
+    rule (module docstring) and run to R < tol.  Returns the batch, the steps
+    of each warm run, the step at which a rejected run was abandoned (0
+    when kept), and the residual history of the probe."""
     import torch
     n = len(specs)
-    caps = np.array([max(step_cap(V, sp), K0 + check_every) for sp in specs])
-    cold, scales = four_roll_batch(V, specs, storage)
-    warm, _ = four_roll_batch(V, specs, storage, stream=mlp.stream)
-    for i in range(n):
-        cold[i].init_fields()
+    caps = np.array([max(step_cap(V, sp), K0 + (window + 1) * check_every) for sp in specs])
+    warm, scales = four_roll_batch(V, specs, storage, stream=mlp.stream)
+    flags = settle_flags if settle else 0
     t0 = time.perf_counter()
     for i, sp in enumerate(specs):
         warm[i].init_from_mlp(mlp, norm_inputs(sp["Wi"], sp["beta"], sp["Re"]),
-                              sp["U0"] * u_scale_factor, scales[i], settle, settle_flags)
+                              sp["U0"] * u_scale_factor, scales[i], settle, flags)
     torch.cuda.synchronize()
     t_infer = time.perf_counter() - t0
-    # residual at K0 (change over the last check_every steps) on both sides;
-    # settling steps count as steps of the warm run
-    out = {}
-    for name, b in (("cold", cold), ("warm", warm)):
-        b.step(K0 - check_every - (settle if name == "warm" else 0))
-        b.reduce()
-        b.step(check_every)
-        out[name] = b.reduce()
-    r_cold, r_warm = out["cold"][:, 0], out["warm"][:, 0]
-    bad = ~np.isfinite(r_warm) | (out["warm"][:, 7] > 0) | (r_warm > r_cold)
+    pred = [model.predict(sp) for sp in specs]
+    red = residual_at(warm, K0, check_every)
+    R0 = red[:, 0]
+    abandoned = np.zeros(n, dtype=np.int64)
+    done = np.zeros(n, dtype=bool)
+    steps = np.zeros(n, dtype=np.int64)
+    status = np.zeros(n, dtype=np.int32)
     for i in range(n):
-        if bad[i]:
+        if not np.isfinite(R0[i]) or red[i, 7] > 0 or R0[i] > pred[i][0]:
+            abandoned[i] = K0
+        elif R0[i] < tol:
+            done[i], steps[i], status[i] = True, K0, V.RUN_CONVERGED
+        if abandoned[i] or done[i]:
+            warm.set_active(i, False)
+    # window of checks: decay rate of the residual, projected steps to tol
+    hist = [R0.copy()]
+    ts = [K0]
+    for w in range(window):
+        if not any(warm.is_active(i) for i in range(n)):
+            break
+        warm.step(check_every)
+        r = warm.reduce()[:, 0]
+        hist.append(r.copy())
+        ts.append(K0 + (w + 1) * check_every)
+        for i in range(n):
+            if warm.is_active(i) and r[i] < tol:
+                done[i], steps[i], status[i] = True, ts[-1], V.RUN_CONVERGED
+                warm.set_active(i, False)
+    H = np.array(hist)
+    tt = np.array(ts, dtype=np.float64)
+    projected = np.full(n, np.nan)
+    for i in range(n):
+        if not warm.is_active(i):
+            continue
+        logR = np.log(np.maximum(H[:, i], 1e-300))
+        rate = -np.polyfit(tt, logR, 1)[0]   # per step
+        projected[i] = (tt[-1] + math.log(H[-1, i] / tol) / rate) if rate > 0 else math.inf
+        if projected[i] > pred[i][1]:
+            abandoned[i] = int(tt[-1])
             warm.set_active(i, False)
     t1 = time.perf_counter()
-    s_cold, R_cold, st_cold = cold.run_until(tol, check_every, caps)
+    s_w, R_w, st_w = warm.run_until(tol, check_every, caps)
     torch.cuda.synchronize()
-    t_cold = time.perf_counter() - t1
-    t2 = time.perf_counter()
-    s_warm, R_warm, st_warm = warm.run_until(tol, check_every, caps)
-    torch.cuda.synchronize()
-    t_warm = time.perf_counter() - t2
-    eff = np.where(bad, K0 + s_cold, s_warm)
-    return dict(cold_steps=s_cold, warm_steps=s_warm, effective_warm_steps=eff, fallback=bad,
-                cold_status=st_cold, warm_status=st_warm, R_cold_K0=r_cold, R_warm_K0=r_warm,
-                R_cold=R_cold, R_warm=R_warm, seconds_cold_after_K0=t_cold,
-                seconds_warm_after_K0=t_warm, seconds_inference=t_infer, cold=cold, warm=warm)
+    t_run = time.perf_counter() - t1
+    for i in range(n):
+        if abandoned[i]:
+            status[i] = V.RUN_SKIPPED   # the cold run replaces it
+        elif not done[i]:
+            steps[i], status[i] = s_w[i], st_w[i]
+    return dict(batch=warm, steps=steps, status=status, abandoned=abandoned, R_K0=R0,
+                R_hist=H, t_hist=tt, projected=projected,
+                pred_R_K0=np.array([p[0] for p in pred]),
+                pred_steps=np.array([p[1] for p in pred]),
+                seconds_inference=t_infer, seconds_run=t_run)
+
+
+def field_errors(V, sim, ref):
+    """Relative L2 distance of u and tau of sim from those of ref."""
+    out = []
+    for f in (V.FIELD_U, V.FIELD_TAU):
+        a, b = sim.read(f), ref.read(f)
+        out.append(float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
+    return out
+
+
+def warm_vs_cold(V, mlp, specs, model, tol=1e-6, check_every=100, K0=1000, window=5,
+                 storage="f32", settle=0, settle_flags=2, ref_tol=1e-9, u_scale_factor=1.0):
+    """Held-out instances from rest and from the network (with the fallback
+    rule), each to R < tol, and an FP64 cold run of each to R < ref_tol as
+    the reference the final fields of both are measured against."""
+    n = len(specs)
+    cold = cold_runs(V, specs, tol, check_every, K0, storage)
+    warm = warm_runs(V, mlp, specs, model, tol, check_every, K0, window, storage, settle,
+                     settle_flags, u_scale_factor)
+    eff = np.where(warm["abandoned"] > 0, warm["abandoned"] + cold["steps"], warm["steps"])
+    ref_caps = [3 * max(step_cap(V, sp), K0 + check_every) for sp in specs]
+    ref = cold_runs(V, specs, ref_tol, check_every, K0, "f64", caps=ref_caps)
+    err_cold = np.array([field_errors(V, cold["batch"][i], ref["batch"][i]) for i in range(n)])
+    err_warm = np.array([field_errors(V, (cold if warm["abandoned"][i] else warm)["batch"][i],
+                                      ref["batch"][i]) for i in range(n)])
+    return dict(cold_steps=cold["steps"], cold_status=cold["status"], R_cold_K0=cold["R_K0"],
+                warm_steps=warm["steps"], warm_status=warm["status"], R_warm_K0=warm["R_K0"],
+                abandoned=warm["abandoned"], effective_warm_steps=eff,
+                fallback=warm["abandoned"] > 0, projected=warm["projected"],
+                pred_R_K0=warm["pred_R_K0"], pred_steps=warm["pred_steps"],
+                err_cold=err_cold, err_warm=err_warm, ref_status=ref["status"],
+                ref_R=ref["R"], ref_steps=ref["steps"],
+                seconds_cold=cold["seconds"], seconds_warm=warm["seconds_run"],
+                seconds_inference=warm["seconds_inference"], warm=warm["batch"],
+                cold=cold["batch"])

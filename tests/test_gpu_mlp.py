@@ -208,22 +208,40 @@ def test_init_from_mlp_sets_the_predicted_fields(V):
     mo = sim.moments()
     assert sim.t == 0
     # the forward pass on the same inputs gives the same outputs (FP32
-    # scaling); the lattice is periodic on both axes, so the prediction's
-    # mean velocity is removed: the total momentum starts at zero
+    # scaling); the lattice is periodic on both axes, so the velocity is
+    # projected onto the fields without central divergence, mean and
+    # staggered modes (numpy's FFT as the reference of the library's DFT)
     y32 = y.astype(np.float32)  # the kernel scales in FP32
-    u32 = np.float32(0.01) * y32[:, :2]
-    m32 = (u32.astype(np.float64).sum(0) / (nx * ny)).astype(np.float32)
-    assert np.abs(m32).max() > 1e-3 * np.abs(u32).max()   # there was a mean to remove
-    u0 = u32 - m32
-    assert rel(mo["u"], u0) <= 1e-6
-    assert np.abs(mo["u"].sum(0)).max() <= 1e-6 * np.abs(mo["u"]).max()
-    assert rel(mo["tau"], 2e-5 * y[:, 2:]) <= 1e-6
+    u32 = (np.float32(0.01) * y32[:, :2]).astype(np.float64)
+    U = [np.fft.fft2(u32[:, c].reshape(ny, nx)) for c in range(2)]
+    KX, KY = np.meshgrid(np.arange(nx), np.arange(ny))
+    sx, sy = np.sin(2 * np.pi * KX / nx), np.sin(2 * np.pi * KY / ny)
+    blind = ((2 * KX) % nx == 0) & ((2 * KY) % ny == 0)
+    ss = np.where(blind, 1.0, sx * sx + sy * sy)
+    d = (sx * U[0] + sy * U[1]) / ss
+    U = [np.where(blind, 0, U[0] - sx * d), np.where(blind, 0, U[1] - sy * d)]
+    u0 = np.stack([np.fft.ifft2(U[c]).real.ravel() for c in range(2)], 1)
+    assert rel(u32, u0) > 1e-3                     # there was something to remove
+    assert rel(mo["u"], u0) <= 1e-5, rel(mo["u"], u0)
+    # no central divergence, no mean
+    ux, uy = mo["u"][:, 0].reshape(ny, nx), mo["u"][:, 1].reshape(ny, nx)
+    div = 0.5 * (np.roll(ux, -1, 1) - np.roll(ux, 1, 1) + np.roll(uy, -1, 0) - np.roll(uy, 1, 0))
+    assert np.abs(div).max() <= 1e-5 * np.abs(mo["u"]).max()
+    assert np.abs(mo["u"].mean(0)).max() <= 1e-6 * np.abs(mo["u"]).max()
+    # tau: the network's, unless the conformation floor moved it (A = I +
+    # c tau with c = lambda / eta_p)
+    lp = sim.lattice_params()
+    c = lp["lam"] / lp["eta_p"]
+    t32 = (np.float32(2e-5) * y32[:, 2:]).astype(np.float64)
+    axx, axy, ayy = 1 + c * t32[:, 0], c * t32[:, 1], 1 + c * t32[:, 2]
+    lmin = 0.5 * (axx + ayy) - np.sqrt(0.25 * (axx - ayy) ** 2 + axy ** 2)
+    keep = lmin >= 0.05
+    assert rel(mo["tau"][keep], t32[keep]) <= 1e-6
     # the same state as vflb_init_fields of those fields with p = 0 (the
     # read-back pressure carries the tau_f f^B_0 term of the stress)
     ref = V.Sim(2, nx, ny, 1, "f64")
     ref.set_params(1.0, 0.5, 0.5, 0.01, nx / (2 * np.pi))
-    ref.init_fields(u0.astype(np.float64),
-                    (np.float32(2e-5) * y32[:, 2:]).astype(np.float64), None)
+    ref.init_fields(sim.read(V.FIELD_U), sim.read(V.FIELD_TAU), None)
     mr = ref.moments()
     for k in ("u", "p", "tau"):
         assert rel(mo[k], mr[k]) <= 1e-12, k

@@ -359,6 +359,62 @@ def test_stress_divergence_fp64_parity_100_steps(V, shape, walls, force):
     assert AN.rel_l2(sg["h"], so["h"]) < 1e-12
 
 
+# D3Q19 (the 3D comparison of the paper's Taylor-Green performance table):
+# periodic, z walls across a chunk edge, y walls with two z-chunks and
+# ragged x, a thin lattice (one-sided stencils meet)
+CASES_DIV3 = [
+    ((6, 6, 6), (0, 0, 0), "const"),
+    ((37, 5, 8), (0, 0, 1), "cos_t"),
+    ((40, 6, 70), (0, 1, 0), "four_roll"),
+    ((5, 9, 36), (1, 0, 1), "const"),
+    ((4, 3, 7), (0, 1, 0), "none"),
+]
+
+
+@pytest.mark.parametrize("shape,walls,force", CASES_DIV3)
+def test_stress_divergence_d3q19_fp64_parity_100_steps(V, shape, walls, force):
+    o, g = setup_pair(V, 3, shape, "f64", walls, force, init="smooth", seed=17,
+                      scheme="stress_divergence")
+    o.step(100)
+    g.step(100)
+    compare(o, g, 1e-12)
+    so, sg = o.get_state(), g.state()
+    assert AN.rel_l2(sg["f"], so["f"]) < 1e-12
+    assert AN.rel_l2(sg["h"], so["h"]) < 1e-12
+
+
+def test_stress_divergence_d3q19_fp32_parity_and_tiles(V):
+    o, g = setup_pair(V, 3, (36, 10, 40), "f32", (0, 1, 0), "const", init="smooth", seed=18,
+                      scheme="stress_divergence")
+    o.step(60)
+    g.step(60)
+    compare(o, g, 1e-5, fields=("u", "tau", "Ae"))
+    # the 32 x 8 tiles give the same iteration (FMA contraction inside a
+    # node's own arithmetic may differ in the last bit: 1e-6)
+    h = setup_pair(V, 3, (36, 10, 40), "f32", (0, 1, 0), "const", init="smooth", seed=18,
+                   scheme="stress_divergence")[1]
+    h.set_tile(8)
+    h.step(60)
+    for k in ("u", "tau"):
+        assert AN.rel_l2(h.moments()[k], g.moments()[k]) < 1e-6, k
+
+
+def test_stress_divergence_d3q19_differs_and_equals_without_polymer(V):
+    res = {}
+    for beta in (0.5, 1.0):
+        for scheme in ("fluctuating", "stress_divergence"):
+            g = setup_pair(V, 3, (8, 8, 8), "f64", (0, 0, 1), "const", init="smooth", seed=4,
+                           scheme=scheme, beta=beta)[1]
+            g.step(30)
+            res[beta, scheme] = (g.state(), g.moments()["u"])
+    # different iterations, close velocities
+    d = AN.rel_l2(res[0.5, "stress_divergence"][1], res[0.5, "fluctuating"][1])
+    assert 1e-9 < d < 1e-1
+    for k in ("f", "h"):   # no polymer: the same iteration
+        assert np.array_equal(res[1.0, "stress_divergence"][0][k],
+                              res[1.0, "fluctuating"][0][k]), k
+
+
 def test_stress_divergence_fp32_parity(V):
     # the FP32 bar on the fields the paper's method is held to (u, tau, A - I)
     o, g = setup_pair(V, 2, (64, 64), "f32", (0, 1, 0), "const", init="smooth", seed=2,
@@ -383,7 +439,7 @@ def test_stress_divergence_differs_from_the_paper_method(V):
 
 
 def test_stress_divergence_rejected_where_not_built(V):
-    for args in ((3, 8, 8, 8, "f32"), (2, 8, 8, 1, "f16s"), (2, 8, 8, 1, "bf16s")):
+    for args in ((3, 8, 8, 8, "f16s"), (2, 8, 8, 1, "f16s"), (2, 8, 8, 1, "bf16s")):
         with pytest.raises(V.VflbError):
             V.Sim(*args, scheme="stress_divergence")
 
