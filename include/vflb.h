@@ -280,6 +280,20 @@ int64_t vflb_time(const vflb_sim *sim);
  * Returns VFLB_EUNSTABLE when out[7] > 0 (out is still filled). */
 vflb_status vflb_reduce(vflb_sim *sim, double out[14]);
 
+/* vflb_reduce for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, values and snapshot update as vflb_reduce, but the
+ * per-block partial sums and the results live in a static device array of
+ * the library (17 x 1024 + 17 doubles, 139 KB, one copy per GPU, held until
+ * the process ends) instead of the VFLB_BUF_WORK buffer.  It calls no
+ * hipMalloc/hipFree.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (several host threads, or streams of different
+ * simulations running concurrently) race and must be serialised by the
+ * caller.  EINVAL if a reduction ever needed more partials than the array
+ * holds (it cannot with the library's launch shape); otherwise as
+ * vflb_reduce, which it synchronises like. */
+vflb_status vflb_reduce_noalloc(vflb_sim *sim, double out[14]);
+
 /* Write a read-back field (VFLB_FIELD_*) as FP64 into the caller's device
  * array of n doubles (n must equal the field size). */
 vflb_status vflb_read(vflb_sim *sim, int field, double *dev_dst, size_t n);

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/vflb.h"
 #include "kernels.h"
@@ -385,7 +386,7 @@ vflb_status launch_moments(vflb_sim* s, int field, double* out, const Box& box) 
 }
 
 template <int D, class S>
-vflb_status launch_reduce(vflb_sim* s, double* dev_res) {
+vflb_status launch_reduce(vflb_sim* s, double* part, double* dev_res) {
   using R = typename StoreT<S>::R;
   if (s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE) {
     vflb_status rc = launch_divergence<S>(s, s->t, s->stream, s->cur);
@@ -397,7 +398,6 @@ vflb_status launch_reduce(vflb_sim* s, double* dev_res) {
     ish = (R)std::ldexp(1.0, -s->log2_sh);
   }
   const int nb = grid1d(s, 256);
-  double* part = reinterpret_cast<double*>(static_cast<char*>(s->buf[VFLB_BUF_WORK]) + s->off_part);
   hipLaunchKernelGGL((reduce_kernel<D, S>), dim3(nb), dim3(256), 0, s->stream,
                      static_cast<const S*>(s->buf[VFLB_BUF_POP0 + s->cur]),
                      static_cast<const R*>(s->buf[VFLB_BUF_AUX]),
@@ -448,7 +448,9 @@ template <int D, class S> struct MomOp {
   }
 };
 template <int D, class S> struct RedOp {
-  static vflb_status run(vflb_sim* s, double* res) { return launch_reduce<D, S>(s, res); }
+  static vflb_status run(vflb_sim* s, double* part, double* res) {
+    return launch_reduce<D, S>(s, part, res);
+  }
 };
 
 // The 14 reported values from the NRED sums; marks the snapshot valid.
@@ -822,8 +824,73 @@ vflb_status vflb_reduce(vflb_sim* s, double out[14]) {
   if (rc != VFLB_OK) return rc;
   if (!out) return fail(s, VFLB_EINVAL, "out is NULL");
   if (!s->inited) return fail(s, VFLB_ESTATE, "initialise the fields first");
-  double* dres = reinterpret_cast<double*>(static_cast<char*>(s->buf[VFLB_BUF_WORK]) + s->off_res);
-  rc = dispatch<RedOp>(s, dres);
+  char* work = static_cast<char*>(s->buf[VFLB_BUF_WORK]);
+  double* dres = reinterpret_cast<double*>(work + s->off_res);
+  rc = dispatch<RedOp>(s, reinterpret_cast<double*>(work + s->off_part), dres);
+  if (rc != VFLB_OK) return rc;
+  double r[NRED];
+  HIP_TRY(s, hipMemcpyAsync(r, dres, sizeof r, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  return finish_reduce(s, r, out);
+}
+
+}  // extern "C"
+
+// Reduction scratch of vflb_reduce_noalloc: the per-block partial sums and
+// the NRED results, one copy per GPU for the life of the process.  In host
+// code `scratch` names a host-side stand-in, never the device memory: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchWords = (size_t)NRED * kRedBlocksMax + NRED;
+static __device__ __align__(256) double scratch[kScratchWords];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the device of `stream`; looked up once per
+// device, with that device current.
+vflb_status scratch_address(vflb_sim* s, hipStream_t stream, double** out) {
+  int dev = 0;
+  if (stream) HIP_TRY(s, hipStreamGetDevice(stream, &dev));
+  else HIP_TRY(s, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(s, VFLB_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    int cur = 0;
+    HIP_TRY(s, hipGetDevice(&cur));
+    if (cur != dev) HIP_TRY(s, hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail(s, VFLB_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return VFLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vflb_status vflb_reduce_noalloc(vflb_sim* s, double out[14]) {
+  vflb_status rc = need_ready(s);
+  if (rc != VFLB_OK) return rc;
+  if (!out) return fail(s, VFLB_EINVAL, "out is NULL");
+  if (!s->inited) return fail(s, VFLB_ESTATE, "initialise the fields first");
+  const size_t need = (size_t)NRED * grid1d(s, 256) + NRED;
+  if (need > kScratchWords)
+    return fail(s, VFLB_EINVAL, "reduction needs %zu scratch words, the static buffer holds %zu",
+                need, kScratchWords);
+  double* sp = nullptr;
+  if ((rc = scratch_address(s, s->stream, &sp)) != VFLB_OK) return rc;
+  // every partial of [0, grid) is written before the finishing pass reads
+  // it, so nothing needs clearing between calls
+  double* dres = sp + (size_t)NRED * kRedBlocksMax;
+  rc = dispatch<RedOp>(s, sp, dres);
   if (rc != VFLB_OK) return rc;
   double r[NRED];
   HIP_TRY(s, hipMemcpyAsync(r, dres, sizeof r, hipMemcpyDeviceToHost, s->stream));

@@ -92,6 +92,7 @@ def lib():
         L.vflb_time.argtypes = [P]
         L.vflb_time.restype = I64
         L.vflb_reduce.argtypes = [P, ctypes.POINTER(D)]
+        L.vflb_reduce_noalloc.argtypes = [P, ctypes.POINTER(D)]
         L.vflb_read.argtypes = [P, I, P, SZ]
         L.vflb_read_box.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), P, SZ]
         L.vflb_read_box.restype = I
@@ -161,7 +162,7 @@ def lib():
                      "vflb_bind_buffers",
                      "vflb_set_params", "vflb_get_lattice_params", "vflb_set_force",
                      "vflb_set_boundaries", "vflb_set_storage_scale", "vflb_init_fields",
-                     "vflb_step", "vflb_reduce", "vflb_read", "vflb_state_size",
+                     "vflb_step", "vflb_reduce", "vflb_reduce_noalloc", "vflb_read", "vflb_state_size",
                      "vflb_save", "vflb_load", "vflb_set_tile"):
             getattr(L, name).restype = I
         _lib = L
@@ -323,9 +324,13 @@ class Sim:
     def synchronize(self):
         self.stream.synchronize()
 
-    def reduce(self, allow_unstable=False):
+    def reduce(self, allow_unstable=False, noalloc=False):
+        """FP64 reductions (vflb_reduce; vflb_reduce_noalloc with
+        noalloc=True, which keeps its partial sums in the library's static
+        device array instead of the work buffer)."""
         out = (ctypes.c_double * 14)()
-        rc = lib().vflb_reduce(self.handle, out)
+        fn = lib().vflb_reduce_noalloc if noalloc else lib().vflb_reduce
+        rc = fn(self.handle, out)
         if rc != OK and not (allow_unstable and rc == EUNSTABLE):
             _check(self.handle, rc)
         o = list(out)
