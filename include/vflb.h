@@ -545,9 +545,11 @@ vflb_status vflb_mlp_train(vflb_mlp *mlp, const float *dev_X, const float *dev_T
  * tau = tau_scale (y2, y3, y4), pressure 0.  On a lattice periodic on every
  * axis (sides <= 512), u is projected onto the fields without central
  * divergence (the step's gradient stencil), without mean and without the
- * modes (pi, 0), (0, pi), (pi, pi) that stencil cannot see: a periodic
- * lattice conserves the total momentum (the force permitting) and, up to
- * sign, the staggered momentum, so a start from rest has none of either.
+ * Nyquist lines kx = pi, ky = pi: a periodic lattice conserves the total
+ * momentum (the force permitting) and, up to sign, the momentum of the
+ * alternating (-1)^x and (-1)^y components, so a start from rest has none of
+ * either.  With walls, the alternating component along each periodic axis
+ * of even length is removed (its momentum is kept up to sign there too).
  * The conformation tensor A = I + lambda tau / eta_p is kept positive
  * definite (eigenvalues raised to at least 0.05).  Then as vflb_init_fields,
  * followed by settle_steps settling steps towards those fields with

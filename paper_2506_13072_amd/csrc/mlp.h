@@ -421,13 +421,16 @@ __global__ void __launch_bounds__(256) dft_pass_kernel(const float2* __restrict_
 }
 
 // Remove from U [2][ny][nx] (spectrum of u) its part along the central
-// difference symbol, and the modes where that symbol vanishes.
+// difference symbol, the mean, and the Nyquist lines kx = pi and ky = pi
+// (a smooth flow has no content there; streaming flips the sign of the
+// momentum of the kx = pi line every step, so its sum over the lattice is
+// kept up to sign).
 __global__ void __launch_bounds__(256) solenoidal_kernel(float2* __restrict__ U, int nx, int ny) {
   const size_t N = (size_t)nx * ny, r = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (r >= N) return;
   const int ky = (int)(r / nx), kx = (int)(r % nx);
   const double sx = sinpi(2.0 * kx / nx), sy = sinpi(2.0 * ky / ny);
-  const bool blind = (2 * kx) % nx == 0 && (2 * ky) % ny == 0;
+  const bool blind = (kx == 0 && ky == 0) || 2 * kx == nx || 2 * ky == ny;
   const float2 a = U[r], b = U[N + r];
   if (blind) {
     U[r] = make_float2(0.0f, 0.0f);
@@ -438,6 +441,28 @@ __global__ void __launch_bounds__(256) solenoidal_kernel(float2* __restrict__ U,
   const double dr = (sx * a.x + sy * b.x) / ss, di = (sx * a.y + sy * b.y) / ss;
   U[r] = make_float2((float)(a.x - sx * dr), (float)(a.y - sx * di));
   U[N + r] = make_float2((float)(b.x - sy * dr), (float)(b.y - sy * di));
+}
+
+// On a lattice with walls: remove from u [2][N] the alternating component
+// (-1)^c along each periodic axis of even length (axis 0: x, 1: y), line by
+// line: its momentum along that axis is kept up to sign by streaming, also
+// next to halfway bounce-back walls on the other axis.  One lane per line.
+__global__ void __launch_bounds__(256) remove_alternating_kernel(float* __restrict__ u, int nx,
+                                                                 int ny, int axis) {
+  const int line = blockIdx.x * 256 + threadIdx.x;
+  const int nl = axis == 0 ? ny : nx, n = axis == 0 ? nx : ny;
+  if (line >= nl) return;
+  const size_t N = (size_t)nx * ny;
+  for (int c = 0; c < 2; ++c) {
+    float* f = u + (size_t)c * N;
+    auto at = [&](int j) -> float& {
+      return axis == 0 ? f[(size_t)line * nx + j] : f[(size_t)j * nx + line];
+    };
+    double a = 0.0;
+    for (int j = 0; j < n; ++j) a += (j & 1) ? -(double)at(j) : (double)at(j);
+    a /= (double)n;
+    for (int j = 0; j < n; ++j) at(j) = (float)((double)at(j) - ((j & 1) ? -a : a));
+  }
 }
 
 // real part / N back into u [2][N]

@@ -623,6 +623,15 @@ vflb_status vflb_init_from_mlp(vflb_sim* sim, vflb_mlp* m, const double extra[3]
     hipLaunchKernelGGL(from_complex_kernel, dim3(g2), dim3(256), 0, m->stream, A, 2 * N,
                        1.0 / (double)N, u);
     MHIP_TRY(m, hipGetLastError());
+  } else {
+    // walls: remove the alternating component along each periodic axis
+    for (int axis = 0; axis < 2; ++axis) {
+      const int n = axis == 0 ? nx : ny, lines = axis == 0 ? ny : nx;
+      if ((ss.walls >> axis) & 1 || n % 2 != 0) continue;
+      hipLaunchKernelGGL(remove_alternating_kernel, dim3((lines + 255) / 256), dim3(256), 0,
+                         m->stream, u, nx, ny, axis);
+      MHIP_TRY(m, hipGetLastError());
+    }
   }
   if (ss.lam_over_eta > 0) {
     hipLaunchKernelGGL(conformation_floor_kernel, dim3(g1), dim3(256), 0, m->stream, tau, N,

@@ -1,4 +1,5 @@
-"""Learned warm start for steady four-roll-mill states (orchestration only).
+"""Learned warm start for steady four-roll-mill and channel states
+(orchestration only).
 
 Every computation runs in libvflb: batches of lattices run to their steady
 states (vflb_batch_run_until), the network trains on those states on the
@@ -6,13 +7,20 @@ device (vflb_mlp_train: minibatch draws, standardised targets, Adam), and a
 new lattice starts from the network's prediction (vflb_init_from_mlp)
 instead of from rest.  This module only decides what to call.
 
-Inputs of the network per node: (x/n, y/n, w, b, r) with
+Two geometries (one network each): the simplified four-roll mill
+(Sec. 3.1; periodic n x n, force of amplitude 2 nu_s U0 k^2) and the planar
+Poiseuille channel (Sec. 3.2; walls in y, constant force 8 nu U0 / L^2,
+L = ny).  The channel flow does not depend on x, so channels of 4 x ny
+nodes hold the state of any longer channel of the same height.
+
+Inputs of the network per node: (x/nx, y/ny, w, b, r) with
 w = P (ln Wi - ln 0.1)/ln 50, b = P (beta - 0.1)/0.8, r = P ln Re: the
 parameter coordinates span [0, P] with P = 1/4, so that the Gaussian
 frequencies vary the features four times more slowly along the parameters
 than across the lattice.  Outputs: (u/U0, v/U0, txx/S, txy/S, tyy/S) with
 the stress scale S = eta_p U0 k, k = 2 pi / n (viscous stress of the
-forcing mode).
+forcing mode) for the four-roll mill and S = eta_p 4 U0 / L (wall shear
+stress) for the channel.
 
 Fallback.  A warm run is judged without running the cold one: the training
 runs (from rest) give, for their parameters, the residual after K0 steps
@@ -43,9 +51,27 @@ def norm_inputs(Wi, beta, Re):
             PARAM_SPAN * (beta - BETA_LO) / (BETA_HI - BETA_LO), PARAM_SPAN * math.log(Re))
 
 
+CHANNEL_NX = 4
+
+
+def dims_of(sp):
+    """Lattice size of a spec: side x side (four-roll mill) or
+    CHANNEL_NX x side (channel)."""
+    if sp.get("geometry", "four_roll") == "channel":
+        return (CHANNEL_NX, sp["side"])
+    return (sp["side"], sp["side"])
+
+
 def lattice_of(V, sim, sp):
-    """Parameters and four-roll force of one instance; returns the lattice
+    """Parameters, boundaries and force of one instance; returns the lattice
     parameters and the stress scale."""
+    if sp.get("geometry", "four_roll") == "channel":
+        L = float(sp["side"])
+        sim.set_params(sp["Re"], sp["Wi"], sp["beta"], sp["U0"], L)
+        sim.set_boundaries((V.PERIODIC, V.WALLS))
+        lp = sim.lattice_params()
+        sim.set_force(V.FORCE_CONST, (8 * (lp["nu_s"] + lp["nu_p"]) * sp["U0"] / L ** 2, 0.0, 0.0))
+        return lp, lp["eta_p"] * 4 * sp["U0"] / L
     sim.set_params(sp["Re"], sp["Wi"], sp["beta"], sp["U0"], sp["side"] / (2 * math.pi))
     lp = sim.lattice_params()
     k = 2 * math.pi / sp["side"]
@@ -55,15 +81,41 @@ def lattice_of(V, sim, sp):
 
 
 def step_cap(V, sp, cap=2_000_000):
-    """min(cap, 50 lambda) steps."""
+    """min(cap, 50 T) steps, T the slower of the relaxation time lambda and,
+    in the channel, the viscous time L^2 / nu."""
+    if sp.get("geometry", "four_roll") == "channel":
+        L = float(sp["side"])
+        nu = sp["U0"] * L / sp["Re"]
+        return int(min(cap, 50 * max(sp["Wi"] * L / sp["U0"], L * L / nu)))
     lam = sp["Wi"] * (sp["side"] / (2 * math.pi)) / sp["U0"]
     return int(min(cap, 50 * lam))
 
 
 def four_roll_batch(V, specs, storage="f32", stream=None):
-    b = V.Batch([(sp["side"], sp["side"]) for sp in specs], storage, stream=stream)
+    """A batch of the instances of specs (either geometry), configured."""
+    b = V.Batch([dims_of(sp) for sp in specs], storage, stream=stream)
     scales = [lattice_of(V, b[i], sp)[1] for i, sp in enumerate(specs)]
     return b, scales
+
+
+batch_of = four_roll_batch
+
+
+def channel_steady(ny, g, nu_s, nu_p, lam, D):
+    """Steady Oldroyd-B channel (Sec. 3.2) on the nodes y = j + 1/2 of a
+    channel of height L = ny between halfway walls: u = g y (L - y)/(2 nu),
+    A_xy = lam u', A_yy = 1, A_xx = 1 + 2 (lam u')^2 + 4 D lam^3 (g/nu)^2 (the
+    last term from the diffusion D of the conformation scheme), and the
+    polymer stress tau = (eta_p / lam)(A - I), eta_p = nu_p.  Returns u [ny],
+    tau [ny, 3] (xx, xy, yy)."""
+    y = np.arange(ny) + 0.5
+    nu = nu_s + nu_p
+    u = g * y * (ny - y) / (2 * nu)
+    du = g * (ny - 2 * y) / (2 * nu)
+    axy = lam * du
+    axx = 1 + 2 * axy ** 2 + 4 * D * lam ** 3 * (g / nu) ** 2
+    k = nu_p / lam
+    return u, np.stack([k * (axx - 1), k * axy, 0 * y], 1)
 
 
 def residual_at(b, t_end, check_every):
@@ -99,13 +151,14 @@ def training_set(V, run, specs, which):
     xs, ts = [], []
     for i in which:
         sp, sim = specs[i], run["batch"][i]
-        n = sp["side"]
+        nx, ny = dims_of(sp)
         u = sim.read(V.FIELD_U)
         tau = sim.read(V.FIELD_TAU)
-        gx, gy = np.meshgrid(np.arange(n) / n, np.arange(n) / n)
+        gx, gy = np.meshgrid(np.arange(nx) / nx, np.arange(ny) / ny)
         w, bb, r = norm_inputs(sp["Wi"], sp["beta"], sp["Re"])
-        x = np.stack([gx.ravel(), gy.ravel(), np.full(n * n, w), np.full(n * n, bb),
-                      np.full(n * n, r)], axis=1)
+        m = nx * ny
+        x = np.stack([gx.ravel(), gy.ravel(), np.full(m, w), np.full(m, bb),
+                      np.full(m, r)], axis=1)
         t = np.concatenate([u / sp["U0"], tau / run["scales"][i]], axis=1)
         xs.append(x)
         ts.append(t)
@@ -219,12 +272,70 @@ def warm_runs(V, mlp, specs, model, tol=1e-6, check_every=100, K0=1000, window=5
                 seconds_inference=t_infer, seconds_run=t_run)
 
 
+def analytic_batch(V, specs, storage="f64"):
+    """Channels started from the analytic steady state (channel_steady), an
+    equilibrium-only start like the network's."""
+    b, _ = four_roll_batch(V, specs, storage)
+    for i, sp in enumerate(specs):
+        lp = b[i].lattice_params()
+        nx, ny = dims_of(sp)
+        g = 8 * (lp["nu_s"] + lp["nu_p"]) * sp["U0"] / ny ** 2
+        u1, tau1 = channel_steady(ny, g, lp["nu_s"], lp["nu_p"], lp["lam"],
+                                  (lp["tau_h"] - 0.5) / 3)
+        u = np.zeros((ny, nx, 2))
+        u[:, :, 0] = u1[:, None]
+        tau = np.repeat(tau1[:, None, :], nx, axis=1)
+        b[i].init_fields(u.reshape(-1, 2), tau.reshape(-1, 3), None)
+    return b
+
+
+def analytic_runs(V, specs, tol=1e-6, check_every=100, storage="f64"):
+    """The analytic start (analytic_batch) run to R < tol: what a perfect
+    prediction of the fields buys."""
+    b = analytic_batch(V, specs, storage)
+    caps = [step_cap(V, sp) for sp in specs]
+    steps, res, status = b.run_until(tol, check_every, caps)
+    return dict(batch=b, steps=steps, status=status, R=res)
+
+
 def field_errors(V, sim, ref):
     """Relative L2 distance of u and tau of sim from those of ref."""
     out = []
     for f in (V.FIELD_U, V.FIELD_TAU):
         a, b = sim.read(f), ref.read(f)
         out.append(float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
+    return out
+
+
+def steps_to_accuracy(V, b, ref_fields, target, caps, every=500):
+    """Step the active instances of b and return, per instance, the first
+    time level (checked every `every` steps) at which the larger of its u
+    and tau relative L2 distances from ref_fields[i] = (u, tau) is at most
+    target[i]; caps[i] when that does not happen by then."""
+    n = len(b)
+    out = np.array(caps, dtype=np.int64)
+    done = np.zeros(n, dtype=bool)
+
+    def check(i):
+        u, tau = ref_fields[i]
+        e = max(np.linalg.norm(b[i].read(V.FIELD_U) - u) / np.linalg.norm(u),
+                np.linalg.norm(b[i].read(V.FIELD_TAU) - tau) / max(np.linalg.norm(tau), 1e-300))
+        if e <= target[i]:
+            done[i] = True
+            out[i] = b[i].t
+            b.set_active(i, False)
+
+    for i in range(n):
+        if b.is_active(i):
+            check(i)
+    while any(b.is_active(i) for i in range(n)):
+        b.step(every)
+        for i in range(n):
+            if b.is_active(i):
+                if b[i].t >= caps[i]:
+                    b.set_active(i, False)
+                else:
+                    check(i)
     return out
 
 
@@ -243,13 +354,29 @@ def warm_vs_cold(V, mlp, specs, model, tol=1e-6, check_every=100, K0=1000, windo
     err_cold = np.array([field_errors(V, cold["batch"][i], ref["batch"][i]) for i in range(n)])
     err_warm = np.array([field_errors(V, (cold if warm["abandoned"][i] else warm)["batch"][i],
                                       ref["batch"][i]) for i in range(n)])
+    # the same final accuracy: steps of a fresh warm start until it is as
+    # close to the reference as the cold run was when it stopped (a run the
+    # fallback rule abandons keeps the cold run's count)
+    ref_fields = [(ref["batch"][i].read(V.FIELD_U), ref["batch"][i].read(V.FIELD_TAU))
+                  for i in range(n)]
+    target = err_cold.max(1)
+    again, scales = four_roll_batch(V, specs, storage, stream=mlp.stream)
+    for i, sp in enumerate(specs):
+        again[i].init_from_mlp(mlp, norm_inputs(sp["Wi"], sp["beta"], sp["Re"]),
+                               sp["U0"] * u_scale_factor, scales[i], settle,
+                               settle_flags if settle else 0)
+        if warm["abandoned"][i]:
+            again.set_active(i, False)
+    acc = steps_to_accuracy(V, again, ref_fields, target, ref_caps)
+    eff_acc = np.where(warm["abandoned"] > 0, warm["abandoned"] + cold["steps"], acc)
     return dict(cold_steps=cold["steps"], cold_status=cold["status"], R_cold_K0=cold["R_K0"],
+                warm_steps_same_accuracy=eff_acc,
                 warm_steps=warm["steps"], warm_status=warm["status"], R_warm_K0=warm["R_K0"],
                 abandoned=warm["abandoned"], effective_warm_steps=eff,
                 fallback=warm["abandoned"] > 0, projected=warm["projected"],
                 pred_R_K0=warm["pred_R_K0"], pred_steps=warm["pred_steps"],
                 err_cold=err_cold, err_warm=err_warm, ref_status=ref["status"],
-                ref_R=ref["R"], ref_steps=ref["steps"],
+                ref_R=ref["R"], ref_steps=ref["steps"], ref=ref["batch"],
                 seconds_cold=cold["seconds"], seconds_warm=warm["seconds_run"],
                 seconds_inference=warm["seconds_inference"], warm=warm["batch"],
                 cold=cold["batch"])

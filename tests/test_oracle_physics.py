@@ -265,3 +265,20 @@ def test_four_roll_mill_low_wi():
         assert A[c, c, 0] - 1 == pytest.approx(Axx - 1, rel=3e-2)
         assert A[c, c, 2] - 1 == pytest.approx(Ayy - 1, rel=3e-2)
         assert abs(A[c, c, 1]) < 1e-10
+
+
+def test_warm_start_channel_profile_matches_the_analytic_solution():
+    # the warm-start module's steady channel state (product side) against
+    # the oracle's closed form of Sec. 3.2 (with the conformation scheme's
+    # diffusion), written independently
+    from paper_2506_13072_amd import warmstart as W
+    ny, g, nu_s, nu_p, lam = 64, 3e-7, 0.2, 0.3, 4000.0
+    D = (0.501 - 0.5) / 3
+    u, tau = W.channel_steady(ny, g, nu_s, nu_p, lam, D)
+    y = np.arange(ny) + 0.5
+    ux, Axx, Axy, Ayy = AN.poiseuille_steady(y, ny, g, nu_s, nu_p, lam, D)
+    k = nu_p / lam
+    assert np.allclose(u, ux, rtol=1e-14, atol=0)
+    assert np.allclose(tau[:, 0], k * (Axx - 1), rtol=1e-13, atol=0)
+    assert np.allclose(tau[:, 1], k * Axy, rtol=1e-13, atol=1e-30)
+    assert np.all(tau[:, 2] == 0) and np.all(Ayy == 1)
