@@ -117,7 +117,7 @@ def run_gpu(steps, warmup, storage="f32", tile=0, scheme="fluctuating", inplace=
 STRESS_DIV3_EXTRA_WORDS = 19 * 7 + 6 + 6 + 3 + 3
 
 
-def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0, scheme="fluctuating"):
+def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0, scheme="fluctuating", inplace=False):
     """3D Taylor-Green vortex, D3Q19, periodic n^3, theta = 0 start,
     U0 = 0.02, Re = 100, Wi = 0.5, beta = 0.9, L = n/(2 pi).  The FP64
     reduction runs every REDUCE_EVERY steps inside the timed region; its
@@ -126,7 +126,7 @@ def run_gpu_tgv(n, steps, warmup, storage="f32", tile=0, scheme="fluctuating"):
     import torch
     from paper_2506_13072_amd import vflb
     from paper_2506_13072_amd.workloads import taylor_green_3d_device
-    g = vflb.Sim(3, n, n, n, storage, scheme=scheme)
+    g = vflb.Sim(3, n, n, n, storage, scheme=scheme, inplace=inplace)
     g.set_params(100.0, 0.5, 0.9, 0.02, n / (2 * math.pi))
     if tile:
         g.set_tile(tile)
@@ -300,26 +300,30 @@ def run_gpu_warmstart(n_train=96, n_test=16, side=64, tol=1e-6, iters=8000, K0=1
                 t_cold=res["seconds_cold"], t_warm=res["seconds_warm"])
 
 
-def time_to_steady_state(n_train=96, n_test=16, side=64):
-    """The metric's second half on a bounded sample: held-out four-roll
-    lattices of side^2 run to R < 1e-6 from rest (plain GPU LB) and from the
-    learned warm start (fallback rule included), after training the network
-    on n_train steady states the method generated; steps summed over the
-    held-out lattices, and the error of both against a tighter reference."""
-    r = run_gpu_warmstart(n_train=n_train, n_test=n_test, side=side)
-    keep = ("cold_steps", "warm_steps", "warm_steps_same_accuracy", "fallbacks",
-            "cold_converged", "warm_converged", "err_cold", "err_warm", "ref_converged",
-            "n_train", "t_data", "t_train")
-    out = {k: (round(r[k], 6) if isinstance(r[k], float) else r[k]) for k in keep if k in r}
-    out["warm_over_cold"] = round(r["warm_steps"] / max(r["cold_steps"], 1), 4)
-    out["warm_over_cold_same_accuracy"] = round(r["warm_steps_same_accuracy"] /
-                                                max(r["cold_steps"], 1), 4)
-    out["sample"] = (f"{n_test} held-out four-roll {side}x{side} lattices (Wi, beta drawn as "
-                     f"in the ensemble), network trained on {r['n_train']} steady states; "
-                     "steps summed over the lattices (a warm run abandoned by the fallback "
-                     "rule counts its own steps plus the cold run's); errors: median over "
-                     "the lattices of the larger of the u and tau relative L2 distances from "
-                     "an FP64 run to R < 1e-9")
+def time_to_steady_state():
+    """The metric's second half on bounded samples of both warm-start
+    geometries: 16 held-out lattices each, run to R < 1e-6 from rest (the
+    plain GPU LB) and from the learned warm start (fallback rule included),
+    FP64 storage; steps summed over the lattices, also to the cold runs'
+    final accuracy against an FP64 run to R < 1e-9."""
+    out = {}
+    for geometry, side in (("channel", 128), ("four_roll", 64)):
+        r = run_gpu_warmstart(n_train=96, n_test=16, side=side, geometry=geometry)
+        keep = ("cold_steps", "warm_steps", "warm_steps_same_accuracy", "fallbacks",
+                "cold_converged", "warm_converged", "err_cold", "err_warm", "ref_converged",
+                "n_train", "analytic_steps_same_accuracy")
+        g = {k: (round(r[k], 6) if isinstance(r[k], float) else r[k]) for k in keep if k in r}
+        g["warm_over_cold"] = round(r["warm_steps"] / max(r["cold_steps"], 1), 4)
+        g["warm_over_cold_same_accuracy"] = round(r["warm_steps_same_accuracy"] /
+                                                  max(r["cold_steps"], 1), 4)
+        shape = f"4x{side} channels" if geometry == "channel" else f"{side}x{side} four-roll"
+        g["sample"] = (f"16 held-out {shape} (Wi, beta drawn as in the ensemble), network "
+                       f"trained on {r['n_train']} steady states; steps summed over the "
+                       "lattices; a warm run abandoned by the fallback rule counts its own "
+                       "steps plus the cold run's; errors: median over the lattices of the "
+                       "larger of the u and tau relative L2 distances from an FP64 run to "
+                       "R < 1e-9")
+        out[geometry] = g
     return out
 
 
@@ -458,7 +462,7 @@ def main():
                     help="only run the streaming-copy kernel (counter calibration)")
     ap.add_argument("--workload", default="tgv",
                     choices=["channel", "tgv", "ensemble", "warmstart", "schemes", "schemes3d",
-                             "inplace"],
+                             "inplace", "inplace3d"],
                     help="tgv (default): the 512^3 D3Q19 Taylor-Green vortex; channel: the "
                          "8192x1024 D2Q9 Poiseuille channel; ensemble: 256 four-roll "
                          "lattices of sides 64..512 as one batch")
@@ -480,7 +484,7 @@ def main():
                          "these flows near R = 1e-6)")
     ap.add_argument("--tgv-n", type=int, default=512)
     args = ap.parse_args()
-    three_d = args.workload in ("tgv", "schemes3d")
+    three_d = args.workload in ("tgv", "schemes3d", "inplace3d")
     if args.steps is None:
         args.steps = 200 if three_d else 2000
     if args.warmup is None:
@@ -579,6 +583,42 @@ def main():
                               round(fl["ms_per_step"] / sd["ms_per_step"], 4),
                           "memory_ratio_fluctuating_over_divergence":
                               round(fl["buffer_bytes"] / sd["buffer_bytes"], 4)}), flush=True)
+        return
+    if args.workload == "inplace3d":
+        # one population buffer (AA streaming, one lane per node) against the
+        # two-buffer z-march on the Taylor-Green vortex
+        n = args.tgv_n
+        nodes = n ** 3
+        wb = 8 if args.storage == "f64" else 4
+        rows = {}
+        for name, inplace in (("two_buffers", False), ("in_place", True)):
+            r = run_gpu_tgv(n, args.steps, args.warmup, args.storage, args.tile, inplace=inplace)
+            # in place adds a velocity pass: 18 moving f read, u written, u read
+            bpl = bytes_per_lup(3, args.storage) + ((18 + 3 + 3) * wb if inplace else 0)
+            rows[name] = dict(MLUPS=round(nodes * args.steps / (r["total_ms"] / 1e3) / 1e6, 1),
+                              ms_per_step=round(r["total_ms"] / args.steps, 4),
+                              bytes_per_lup=bpl,
+                              achieved_GBps=round(bpl * nodes / (r["step_ms"] / 1e3) / 1e9, 1),
+                              buffer_bytes=r["buffer_bytes"])
+        tb, ip = rows["two_buffers"], rows["in_place"]
+        ach = ip["achieved_GBps"]
+        print(json.dumps({"metric": "MLUPS (in-place AA streaming, D3Q19 Taylor-Green)",
+                          "value": ip["MLUPS"], "unit": "MLUPS", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": ip["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
+                          "config": {"workload": f"3D Taylor-Green vortex D3Q19 {n}^3, one "
+                                                 "population buffer vs two",
+                                     "storage": args.storage, "nodes": nodes},
+                          "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                       "traffic": None, "bytes_per_lup": ip["bytes_per_lup"]},
+                          "layouts": rows,
+                          "time_ratio_in_place_over_two_buffers":
+                              round(ip["ms_per_step"] / tb["ms_per_step"], 4),
+                          "memory_ratio_in_place_over_two_buffers":
+                              round(ip["buffer_bytes"] / tb["buffer_bytes"], 4)}), flush=True)
         return
     if args.workload == "inplace":
         # one population buffer (AA streaming) against the two-buffer step

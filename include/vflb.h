@@ -205,9 +205,12 @@ vflb_status vflb_create_scheme(int lattice, int nx, int ny, int nz, int storage,
  *     opposite directions; a step at odd t reads them where their writers
  *     left them and writes into the slots of the readers of the next step.
  *     The same-time velocity gradient then needs u of the neighbours before
- *     they are overwritten: a velocity pass per step writes u(t) (2 more
- *     words per node of AUX).  Results equal the two-buffer step's bit for
- *     bit.  D2Q9, FP32 or FP64 storage, single lattices; no settling.  The
+ *     they are overwritten: a velocity pass per step writes u(t) (D more
+ *     words per node of AUX).  D2Q9: results equal the two-buffer step's
+ *     bit for bit.  D3Q19: one lane per node (the two-buffer step's z-march
+ *     pulls planes ahead of the planes it writes, which in place would
+ *     overwrite values not yet read), the same iteration up to rounding.
+ *     FP32 or FP64 storage, single lattices; no settling.  The
  *     population layout alternates with the parity of t; checkpoints record
  *     it (vflb_load refuses a checkpoint of the other layout). */
 enum { VFLB_OPT_INPLACE = 1 };

@@ -16,6 +16,7 @@
 #include "kernels.h"
 #include "step2d.h"
 #include "step3d.h"
+#include "aa3d.h"
 #include "internal.h"
 
 using namespace vflb;
@@ -61,7 +62,7 @@ struct vflb_sim {
   const float* clamp = nullptr;  // settling targets while vflb::internal::sim_settle runs
   int clamp_flags = 0;
   int scheme = VFLB_SCHEME_FLUCTUATING;
-  bool inplace = false;  // one population buffer, AA streaming (D2Q9)
+  bool inplace = false;  // one population buffer, AA streaming
   int model = VFLB_MODEL_OLDROYD_B;
   double mparam = 0.0;
   std::string err;
@@ -197,7 +198,7 @@ Geo geo_of(const vflb_sim* s, int64_t t) {
 Geo geo_of(const vflb_sim* s) { return geo_of(s, s->t); }
 
 // AUX layout: chi(t-1) [NC][N], u(t-1) [D][N]; stress-divergence scheme:
-// tau_p [3][N], div tau_p [2][N]; in-place streaming: u(t) [2][N]
+// tau_p [NC][N], div tau_p [D][N]; in-place streaming: u(t) [D][N]
 size_t aux_taup_words(const vflb_sim* s) { return (size_t)(s->NC + s->D) * s->N; }
 size_t aux_u_words(const vflb_sim* s) {
   return aux_taup_words(s) +
@@ -318,6 +319,18 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
     if (rc != VFLB_OK) return rc;
   }
   StepArgs<S> a = make_step_args<S>(s, t, parity);
+  if constexpr (D == 3 && !StoreT<S>::kAnchored) {
+    if (s->inplace) {  // in place: same-time velocity, then the step
+      using R = typename StoreT<S>::R;
+      R* U = static_cast<R*>(s->buf[VFLB_BUF_AUX]) + aux_u_words(s);
+      const int nb = (int)std::min<size_t>((s->N + 255) / 256, (size_t)1 << 16);
+      hipLaunchKernelGGL((aa3_velocity_kernel<S>), dim3(nb), dim3(256), 0, st, a.pin, a.g, a.F,
+                         a.inv_sf, U);
+      hipLaunchKernelGGL((aa3_step_kernel<S>), dim3(nb), dim3(256), 0, st, a, (const R*)U);
+      HIP_TRY(s, hipGetLastError());
+      return VFLB_OK;
+    }
+  }
   if constexpr (!StoreT<S>::kPlanar) {
     return launch_tiled<D, S>(s, st, a);
   } else {  // in place: same-time velocity, then the step
@@ -553,9 +566,9 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
                 "the stress-divergence scheme runs with FP32 or FP64 storage");
   if (options & ~VFLB_OPT_INPLACE) return fail(nullptr, VFLB_EINVAL, "unknown options %#x", options);
   const bool inplace = (options & VFLB_OPT_INPLACE) != 0;
-  if (inplace && (lattice != VFLB_D2Q9 || (storage != VFLB_F32 && storage != VFLB_F64) || view))
+  if (inplace && ((storage != VFLB_F32 && storage != VFLB_F64) || view))
     return fail(nullptr, VFLB_EINVAL,
-                "in-place streaming runs on single D2Q9 lattices with FP32 or FP64 storage");
+                "in-place streaming runs on single lattices with FP32 or FP64 storage");
   vflb_sim* s = new vflb_sim();
   s->scheme = scheme;
   s->inplace = inplace;
@@ -580,7 +593,7 @@ vflb_status sim_new(int lattice, int nx, int ny, int nz, int storage, hipStream_
   if (inplace) s->bytes[VFLB_BUF_POP1] = 256;  // unused
   // AUX: chi(t-1), u(t-1); the stress-divergence scheme adds tau_p [NC][N]
   // and div tau_p [D][N]; in-place streaming u(t) [2][N]
-  const size_t u_now = inplace ? 2 : 0;
+  const size_t u_now = inplace ? (size_t)s->D : 0;
   const size_t div_words = scheme == VFLB_SCHEME_STRESS_DIVERGENCE ? s->NC + s->D : 0;
   s->bytes[VFLB_BUF_AUX] = align256(ab * ((s->NC + s->D) + div_words + u_now) * N);
   s->bytes[VFLB_BUF_SNAP] = align256(ab * (s->NC + s->D) * N);

@@ -62,7 +62,7 @@ def test_create_rejects_sizes_and_options_not_built(lib):
     assert mk(3, 1024, 512, 513, 2, 0, 0) == 1
     assert b"exceeds" in lib.vflb_last_error(None)
     assert mk(2, 8, 8, 1, 1, 0, 2) == 1              # unknown option bit
-    assert mk(3, 8, 8, 8, 1, 0, 1) == 1              # in place: D2Q9 only
+    assert mk(3, 8, 8, 8, 2, 0, 1) == 1              # in place: not 16-bit
     assert mk(2, 8, 8, 1, 2, 0, 1) == 1              # in place: not 16-bit
     assert mk(3, 8, 8, 8, 2, 1, 0) == 1              # comparison scheme: not 16-bit
     assert mk(2, 8, 8, 1, 1, 5, 0) == 1              # unknown scheme

@@ -605,9 +605,66 @@ def test_inplace_keeps_one_population_buffer_and_is_rejected_where_not_built(V):
     pb = [x.numel() for x in b.buffers]
     assert pb[V.BUF_POP1] <= 256 and pb[V.BUF_POP0] == pa[V.BUF_POP0]
     assert pb[V.BUF_AUX] == pa[V.BUF_AUX] + 2 * 4 * 64 * 32
-    for args in ((3, 8, 8, 8, "f32"), (2, 8, 8, 1, "f16s"), (2, 8, 8, 1, "bf16s")):
+    for args in ((3, 8, 8, 8, "f16s"), (2, 8, 8, 1, "f16s"), (2, 8, 8, 1, "bf16s")):
         with pytest.raises(V.VflbError):
             V.Sim(*args, inplace=True)
+
+
+# ------------------------------------------------- in place, D3Q19
+# One lane per node and the generic collision (not the z-march's lane-pair
+# arithmetic): the same iteration up to rounding, so held to the oracle at
+# the usual bars rather than bitwise to the two-buffer state.
+INPLACE3_CASES = [
+    ((6, 6, 6), (0, 0, 0), "const"),
+    ((5, 9, 36), (0, 0, 1), "cos_t"),
+    ((40, 6, 7), (1, 1, 0), "four_roll"),
+    ((3, 4, 5), (1, 1, 1), "none"),
+]
+
+
+@pytest.mark.parametrize("shape,walls,force", INPLACE3_CASES)
+def test_inplace_d3q19_fp64_parity(V, shape, walls, force):
+    o, g = setup_pair(V, 3, shape, "f64", walls, force, init="smooth", seed=23, inplace=True)
+    assert g.inplace
+    for n in (1, 2, 64, 33):   # odd and even time levels, a captured graph
+        o.step(n)
+        g.step(n)
+        compare(o, g, 1e-12)
+    so, sg = o.get_state(), g.state()
+    assert AN.rel_l2(sg["f"], so["f"]) < 1e-12
+    assert AN.rel_l2(sg["h"], so["h"]) < 1e-12
+
+
+def test_inplace_d3q19_fp32_models_schemes_and_checkpoints(V):
+    o, g = setup_pair(V, 3, (36, 10, 12), "f32", (0, 1, 0), "const", init="smooth", seed=24,
+                      inplace=True)
+    o.step(41)
+    g.step(41)
+    compare(o, g, 1e-5, fields=("u", "tau", "Ae"))
+    blob = g.save()   # at an odd time level
+    g.step(20)
+    h = setup_pair(V, 3, (36, 10, 12), "f32", (0, 1, 0), "const", init="smooth", seed=1,
+                   inplace=True)[1]
+    h.load(blob)
+    h.step(20)
+    for k in (V.FIELD_F, V.FIELD_H, V.FIELD_CHI_PREV, V.FIELD_U_PREV):
+        assert np.array_equal(g.read(k), h.read(k)), k
+    for scheme, model, mparam in (("stress_divergence", None, 0.0),
+                                  ("fluctuating", O.MODEL_GIESEKUS, 0.2)):
+        o, g = stretched_pair(V, 3, (6, 7, 9), "f64", (0, 0, 1), "const", model, mparam,
+                              scheme=scheme, inplace=True)
+        o.step(37)
+        g.step(37)
+        compare(o, g, 1e-12)
+
+
+def test_inplace_d3q19_keeps_one_population_buffer(V):
+    a = V.Sim(3, 32, 8, 8, "f32")
+    b = V.Sim(3, 32, 8, 8, "f32", inplace=True)
+    pa = [x.numel() for x in a.buffers]
+    pb = [x.numel() for x in b.buffers]
+    assert pb[V.BUF_POP1] <= 256 and pb[V.BUF_POP0] == pa[V.BUF_POP0]
+    assert pb[V.BUF_AUX] == pa[V.BUF_AUX] + 3 * 4 * 32 * 8 * 8
 
 
 # ------------------------------------------------- anchored 16-bit D3Q19

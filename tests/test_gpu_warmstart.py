@@ -87,3 +87,48 @@ def test_settling_removes_the_initial_transient(env):
         b.step(100)
         r[settle] = b.reduce()[:, 0]
     assert np.all(r[1000] < 0.1 * r[0]), r
+
+
+# ------------------------------------------------------------ channel
+# The Poiseuille half of the warm start: 4 x 128 channels (the flow does not
+# depend on x), networks trained on steady states the batched LB generated,
+# held-out channels judged at the same final accuracy as their cold runs
+# against an FP64 run converged to R < 1e-9.
+
+@pytest.fixture(scope="module")
+def channel_env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_13072_amd import vflb as V
+    from paper_2506_13072_amd import warmstart as W
+    from paper_2506_13072_amd.workloads import ensemble_draws
+    draws = ensemble_draws(52, seed=777)
+    specs = [dict(side=128, Re=1.0, Wi=d["Wi"], beta=d["beta"], U0=0.01, geometry="channel")
+             for d in draws]
+    run = W.cold_runs(V, specs[:48], tol=1e-6, storage="f64")
+    ok = [i for i in range(48) if run["status"][i] == V.RUN_CONVERGED]
+    X, T = W.training_set(V, run, specs, ok)
+    model = W.ColdModel(specs[:48], run)
+    mlp = V.Mlp(max_batch=8192, seed=5, sigma=1.5)
+    W.train(mlp, X, T, iters=4000, rows=8192, lr=2e-3)
+    return dict(V=V, W=W, specs=specs, mlp=mlp, model=model, ok=ok)
+
+
+@pytest.mark.timeout(600)
+def test_channel_warm_start_reaches_the_same_accuracy_sooner(channel_env):
+    V, W = channel_env["V"], channel_env["W"]
+    assert len(channel_env["ok"]) >= 44
+    test = channel_env["specs"][48:]
+    res = W.warm_vs_cold(V, channel_env["mlp"], test, channel_env["model"], tol=1e-6,
+                         storage="f64")
+    assert np.all(res["cold_status"] == V.RUN_CONVERGED)
+    cold, warm = res["cold_steps"].sum(), res["warm_steps_same_accuracy"].sum()
+    print("cold", res["cold_steps"], "warm (same accuracy)", res["warm_steps_same_accuracy"])
+    assert warm < 0.8 * cold, (warm, cold)
+    # the analytic steady state, the upper bound of any equilibrium-only start
+    ref = [(res["ref"][i].read(V.FIELD_U), res["ref"][i].read(V.FIELD_TAU))
+           for i in range(len(test))]
+    an = W.steps_to_accuracy(V, W.analytic_batch(V, test), ref, res["err_cold"].max(1),
+                             [3 * W.step_cap(V, sp) for sp in test])
+    assert an.sum() < cold
