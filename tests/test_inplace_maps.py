@@ -93,3 +93,95 @@ def test_in_place_maps_are_race_free_and_equal_two_buffer_streaming(nx, ny, wall
         for y, x, i in itertools.product(range(ny), range(nx), range(9)):
             assert two[read_slot(i, x, y, nx, ny, walls, 0)] == \
                 one[read_slot(i, x, y, nx, ny, walls, nm)], (t, x, y, i)
+
+
+# ---------------------------------------------------------------- D3Q19
+# The same two maps for the 19 velocities (order of App. A; opposite pairs
+# (2k-1, 2k)), with walls on any subset of the three axes: the in-place
+# D3Q19 step (aa3d.h) uses them through pull_index and aa_write_index<3>.
+C3 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+      (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
+      (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+OPP3 = [0] + [k + 1 if k % 2 else k - 1 for k in range(1, 19)]
+
+
+def read_slot3(i, p, n, walls, mode):
+    N = n[0] * n[1] * n[2]
+    node = lambda q: (q[2] * n[1] + q[1]) * n[0] + q[0]
+    if mode == 1:
+        return i * N + node(p)
+    s, bounce = [p[a] - C3[i][a] for a in range(3)], False
+    for a in range(3):
+        if C3[i][a] != 0 and not 0 <= s[a] < n[a]:
+            if walls & (1 << a):
+                bounce = True
+            else:
+                s[a] = n[a] - 1 if s[a] < 0 else 0
+    j = OPP3[i] if mode == 2 else i
+    if bounce:
+        return OPP3[j] * N + node(p)
+    return j * N + node(s)
+
+
+def write_slot3(i, p, n, walls, mode):
+    N = n[0] * n[1] * n[2]
+    node = lambda q: (q[2] * n[1] + q[1]) * n[0] + q[0]
+    o = OPP3[i]
+    if mode == 1:
+        return o * N + node(p)
+    t = [p[a] + C3[i][a] for a in range(3)]
+    if any(walls & (1 << a) and not 0 <= t[a] < n[a] for a in range(3)):
+        return o * N + node(p)
+    return i * N + node([t[a] % n[a] for a in range(3)])
+
+
+CASES3 = [(n, w) for n, w in itertools.product([(1, 2, 3), (2, 2, 2), (3, 2, 4), (2, 3, 1)],
+                                               range(8))
+          if all(not (w & (1 << a)) or n[a] >= 2 for a in range(3))]
+
+
+def test_d3q19_opposites():
+    assert all(tuple(-c for c in C3[i]) == C3[OPP3[i]] for i in range(19))
+
+
+@pytest.mark.parametrize("n,walls", CASES3)
+def test_d3q19_in_place_maps_are_race_free_and_equal_two_buffer_streaming(n, walls):
+    N = n[0] * n[1] * n[2]
+    nodes = list(itertools.product(range(n[0]), range(n[1]), range(n[2])))
+    f0 = np.random.default_rng(sum(n) + 10 * walls).normal(size=(19, N))
+    two = np.full(19 * N, np.nan)
+    one = np.full(19 * N, np.nan)
+    idx = lambda p: (p[2] * n[1] + p[1]) * n[0] + p[0]
+    for p, i in itertools.product(nodes, range(19)):
+        two[read_slot3(i, p, n, walls, 0)] = f0[i, idx(p)]
+        one[read_slot3(i, p, n, walls, 1)] = f0[i, idx(p)]
+    assert not np.isnan(two).any() and not np.isnan(one).any()
+    for t in range(4):
+        nxt = np.full(19 * N, np.nan)
+        for p in nodes:
+            fs = [v * 1.0001 + 0.37 * ((7 * p[0] + 3 * p[1] + 5 * p[2] + i + t) % 5)
+                  for i, v in enumerate(two[read_slot3(i, p, n, walls, 0)] for i in range(19))]
+            for i in range(19):
+                nxt[i * N + idx(p)] = fs[i]
+        two = nxt
+        mode = 1 if t % 2 == 0 else 2
+        reader, writer, new = {}, {}, one.copy()
+        for p in nodes:
+            f = []
+            for i in range(19):
+                k = read_slot3(i, p, n, walls, mode)
+                assert reader.setdefault(k, idx(p)) == idx(p)
+                f.append(one[k])
+            fs = [v * 1.0001 + 0.37 * ((7 * p[0] + 3 * p[1] + 5 * p[2] + i + t) % 5)
+                  for i, v in enumerate(f)]
+            for i, v in enumerate(fs):
+                k = write_slot3(i, p, n, walls, mode)
+                assert writer.setdefault(k, idx(p)) == idx(p)
+                new[k] = v
+        assert len(reader) == len(writer) == 19 * N
+        assert all(reader[k] == writer[k] for k in writer)
+        one = new
+        nm = 1 if (t + 1) % 2 == 0 else 2
+        for p, i in itertools.product(nodes, range(19)):
+            assert two[read_slot3(i, p, n, walls, 0)] == one[read_slot3(i, p, n, walls, nm)], \
+                (t, p, i)
