@@ -354,10 +354,10 @@ def measured_traffic(record, kernel):
         return None
 
 
-def copy_ceiling(nbytes=4 << 30, reps=10):
-    """Rate of the library's plain streaming-copy kernel (read + write bytes
-    per second), the achievable-bandwidth reference next to the 8 TB/s
-    peak."""
+def copy_ceiling(nbytes=4 << 30, reps=10, kind=0):
+    """Rate of the library's streaming-copy kernel (read + write bytes per
+    second), the achievable-bandwidth reference next to the 8 TB/s peak;
+    `kind` selects another access kind of the calibration copies."""
     import torch
     from paper_2506_13072_amd import vflb
     st = torch.cuda.Stream()
@@ -365,12 +365,12 @@ def copy_ceiling(nbytes=4 << 30, reps=10):
     dst = torch.empty_like(src)
     src.fill_(1)
     torch.cuda.synchronize()
-    vflb.stream_copy(src, dst, st)
+    vflb.stream_copy(src, dst, st, kind)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(reps):
-        vflb.stream_copy(src, dst, st)
+        vflb.stream_copy(src, dst, st, kind)
     e1.record(st)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -460,6 +460,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile height: D2Q9 4, 8, 16; D3Q19 4, 8")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy kernel (counter calibration)")
+    ap.add_argument("--copy-kind", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="copy probe access kind: 0 non-temporal 16-byte, 1 plain 16-byte, "
+                         "2 plain 4-byte, 3 16-byte LDS-DMA loads")
     ap.add_argument("--workload", default="tgv",
                     choices=["channel", "tgv", "ensemble", "warmstart", "schemes", "schemes3d",
                              "inplace", "inplace3d"],
@@ -490,7 +493,8 @@ def main():
     if args.warmup is None:
         args.warmup = 20 if three_d else 200
     if args.copy_probe:
-        print(json.dumps({"copy_GBps": round(copy_ceiling(), 1)}), flush=True)
+        print(json.dumps({"copy_kind": args.copy_kind,
+                          "copy_GBps": round(copy_ceiling(kind=args.copy_kind), 1)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -602,6 +606,14 @@ def main():
                               buffer_bytes=r["buffer_bytes"])
         tb, ip = rows["two_buffers"], rows["in_place"]
         ach = ip["achieved_GBps"]
+        # one in-place step is two launches (velocity pass, step): their
+        # measured bytes together
+        traffic = None
+        if args.storage in ("f32", "f64") and n == 512 and not args.tile:
+            parts = [measured_traffic(f"aa3_{k}_{args.storage}_tgv_512.md", "aa3d")
+                     for k in ("velocity", "step")]
+            if None not in parts:
+                traffic = sum(parts)
         print(json.dumps({"metric": "MLUPS (in-place AA streaming, D3Q19 Taylor-Green)",
                           "value": ip["MLUPS"], "unit": "MLUPS", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup,
@@ -613,7 +625,11 @@ def main():
                                      "storage": args.storage, "nodes": nodes},
                           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                                       "traffic": None, "bytes_per_lup": ip["bytes_per_lup"]},
+                                       "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                                       "traffic_unit": "GB per step (both launches)",
+                                       "algorithmic_GB_per_step":
+                                           round(ip["bytes_per_lup"] * nodes / 1e9, 4),
+                                       "bytes_per_lup": ip["bytes_per_lup"]},
                           "layouts": rows,
                           "time_ratio_in_place_over_two_buffers":
                               round(ip["ms_per_step"] / tb["ms_per_step"], 4),

@@ -331,6 +331,17 @@ vflb_status vflb_set_tile(vflb_sim *sim, int tile_y);
 vflb_status vflb_stream_copy(const void *src, void *dst, size_t nbytes,
                              void *hip_stream);
 
+/* Counter calibration copies: copies nbytes from src to dst (device
+ * pointers) on hip_stream with one access kind of the step kernels, so that
+ * hardware byte counters can be converted into bytes per kind.  kind 0:
+ * non-temporal 16-byte loads and stores (vflb_stream_copy); 1: plain
+ * 16-byte loads and stores; 2: plain 4-byte loads and stores; 3: 16-byte
+ * loads through LDS-DMA (global_load_lds), non-temporal 16-byte stores.
+ * nbytes and both pointers must be multiples of 16 (of 4 for kind 2).
+ * Not part of the method.  EINVAL on a bad kind, size or alignment. */
+vflb_status vflb_copy_probe(const void *src, void *dst, size_t nbytes, int kind,
+                            void *hip_stream);
+
 /* Settling towards prescribed fields (D2Q9): nsteps steps in which every
  * collision takes the FP32 device fields u [2][N] and tau [3][N], stored
  * back to back at dev_targets, in place of the state's own moment u (flags

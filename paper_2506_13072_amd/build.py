@@ -28,6 +28,7 @@ HIPCC_FLAGS = [
 KERNEL_FILES = {
     "step2d": ("step2d.h", "kernels.h", "layout.h", "lattice.h"),
     "step3d": ("step3d.h", "kernels.h", "layout.h", "lattice.h"),
+    "aa3d": ("aa3d.h", "kernels.h", "layout.h", "lattice.h"),
 }
 
 

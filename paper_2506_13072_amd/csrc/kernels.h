@@ -578,8 +578,6 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchInst<S>* _
   block_partials(acc, partials + (size_t)blockIdx.x * NRED);
 }
 
-// plain streaming copy: one 16-byte vector per lane, non-temporal
-typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 // ------------------------------------------------ stress-divergence scheme
 // The scheme the paper compares its method against (Sec. 3, performance
 // tables; described in words in the Introduction): the divergence of the
@@ -587,7 +585,8 @@ typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 // div tau_p, and f^B is absent.  Per step: tau_p(t) of every node from its
 // pulled h (taup_kernel), then div tau_p by second-order central
 // differences, one-sided second order normal to a wall (stress_div_kernel);
-// the step kernels add it to F wherever they evaluate the force.  D2Q9.
+// the step kernels add it to F wherever they evaluate the force.  D2Q9 and
+// D3Q19.
 
 template <int D, class S>
 __global__ void __launch_bounds__(256) taup_kernel(const S* __restrict__ pin, Geo g,
@@ -667,11 +666,5 @@ __global__ void __launch_bounds__(256) stress_div_kernel(const R* __restrict__ t
   }
 }
 
-__global__ void __launch_bounds__(256) stream_copy_kernel(const v4u32* __restrict__ src,
-                                                          v4u32* __restrict__ dst,
-                                                          size_t n) {
-  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
-}
 
 }  // namespace vflb

@@ -222,42 +222,137 @@ struct Anchor2 {
   }
 };
 
-// D3Q19 references, as fref2 / href2; direction i is the stored direction
-// (the writer's), so no sign flip is needed for a bounce-back pull
-template <class R>
-__device__ inline R fref3(int i, R p, const R* u) {
-  const R wi = (R)Lat<3>::w(i);
-  const R lam_i = (R)(i == 0 ? 3.0 * (Lat<3>::w(0) - 1.0) : 3.0 * Lat<3>::w(i));
-  const R cu = (R)Lat<3>::cx(i) * u[0] + (R)Lat<3>::cy(i) * u[1] + (R)Lat<3>::cz(i) * u[2];
-  const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  return lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
+// D3Q19 references of direction i from an anchor (E = A - I, p, u), as
+// fref2 / href2; direction i is the stored direction (the writer's), so no
+// sign flip is needed for a bounce-back pull.  Written as
+//   fref = w_i (3 c.u + 9/2 (c.u)^2 - 3/2 u.u) + lambda_i p
+//        = fma(w_i, fma(cu, fma(cu, 9/2, 3), -3/2 uu), lambda_i p),
+//   href = w_i E + 3 w_i (E + delta) c.u = E (w_i + t) + delta t,  t = 3 w_i c.u,
+// with explicit fused multiply-adds in one fixed order and c.u summed over
+// the nonzero components of c only: a reader and a writer evaluate the same
+// reference bitwise whatever contraction the compiler applies around them,
+// and the rebuilt value is the stored deviation plus exactly the reference
+// the writer subtracted.
+template <class R> __device__ inline R fmar(R a, R b, R c);
+template <> __device__ inline float fmar<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+template <> __device__ inline double fmar<double>(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+template <int C, class R> __device__ inline R csgn(R v) { return C > 0 ? v : -v; }
+// c.u for c = (CX, CY, CZ) with components in {-1, 0, 1}
+template <int CX, int CY, int CZ, class R>
+__device__ inline R cdot3(const R* u) {
+  if constexpr (CX != 0) {
+    R s = csgn<CX>(u[0]);
+    if constexpr (CY != 0) s += csgn<CY>(u[1]);
+    if constexpr (CZ != 0) s += csgn<CZ>(u[2]);
+    return s;
+  } else if constexpr (CY != 0) {
+    R s = csgn<CY>(u[1]);
+    if constexpr (CZ != 0) s += csgn<CZ>(u[2]);
+    return s;
+  } else {
+    return csgn<CZ>(u[2]);
+  }
 }
 template <class R>
-__device__ inline R href3(int i, int c, R E, const R* u) {
-  const R wi = (R)Lat<3>::w(i);
-  const R cu = (R)Lat<3>::cx(i) * u[0] + (R)Lat<3>::cy(i) * u[1] + (R)Lat<3>::cz(i) * u[2];
-  return wi * E + 3 * wi * (E + (c < 3 ? (R)1 : (R)0)) * cu;
+__device__ inline R uu3(const R* u) {
+  return fmar(u[2], u[2], fmar(u[1], u[1], u[0] * u[0]));
 }
 
-// The same references for the member of opposite pair K (K >= 1) with
-// velocity sgn c_{2K-1} (sgn = 1: direction 2K - 1, -1: direction 2K), for
-// code that holds a pair's member by sign rather than by index; equal
-// bitwise to fref3 / href3 of that direction (c_{2K} = -c_{2K-1}).
+// The member of opposite pair K (K >= 1) with velocity sgn c_{2K-1} (sgn =
+// 1: direction 2K - 1, -1: direction 2K).  cu_pair3 is its c.u; the other
+// arguments are the writer's anchor.
+template <int K, class R>
+__device__ inline R cu_pair3(R sgn, const R* u) {
+  constexpr int i = 2 * K - 1;
+  return sgn * cdot3<Lat<3>::cx(i), Lat<3>::cy(i), Lat<3>::cz(i)>(u);
+}
+template <int K, class R>
+__device__ inline R fref3_cu(R cu, R p, R uu) {
+  constexpr R wi = (R)Lat<3>::w(2 * K - 1), lam_i = (R)(3.0 * Lat<3>::w(2 * K - 1));
+  return fmar(wi, fmar(cu, fmar(cu, (R)4.5, (R)3), (R)-1.5 * uu), lam_i * p);
+}
+template <int K, class R>
+__device__ inline R href3_cu(R cu, int c, R E) {
+  constexpr R wi = (R)Lat<3>::w(2 * K - 1);
+  const R t = (R)(3.0 * Lat<3>::w(2 * K - 1)) * cu;
+  return c < 3 ? fmar(E, wi + t, t) : E * (wi + t);
+}
 template <int K, class R>
 __device__ inline R fref3_pair(R sgn, R p, const R* u) {
-  constexpr int i = 2 * K - 1;
-  const R wi = (R)Lat<3>::w(i);
-  const R lam_i = (R)(3.0 * Lat<3>::w(i));
-  const R cu = sgn * ((R)Lat<3>::cx(i) * u[0] + (R)Lat<3>::cy(i) * u[1] + (R)Lat<3>::cz(i) * u[2]);
-  const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  return lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu);
+  return fref3_cu<K, R>(cu_pair3<K, R>(sgn, u), p, uu3(u));
 }
 template <int K, class R>
 __device__ inline R href3_pair(R sgn, int c, R E, const R* u) {
-  constexpr int i = 2 * K - 1;
-  const R wi = (R)Lat<3>::w(i);
-  const R cu = sgn * ((R)Lat<3>::cx(i) * u[0] + (R)Lat<3>::cy(i) * u[1] + (R)Lat<3>::cz(i) * u[2]);
-  return wi * E + 3 * wi * (E + (c < 3 ? (R)1 : (R)0)) * cu;
+  return href3_cu<K, R>(cu_pair3<K, R>(sgn, u), c, E);
+}
+// the rest direction (c = 0)
+template <class R>
+__device__ inline R fref3_rest(R p, R uu) {
+  constexpr R w0 = (R)Lat<3>::w(0), lam0 = (R)(3.0 * (Lat<3>::w(0) - 1.0));
+  return fmar(w0, (R)-1.5 * uu, lam0 * p);
+}
+template <class R>
+__device__ inline R href3_rest(R E) {
+  return (R)Lat<3>::w(0) * E;
+}
+// sc times the references above, exactly, for a power of two sc (scaling by
+// sc commutes with every rounding in them, barring overflow and underflow):
+// a writer forms its scaled deviation fma(v, sc, -sc ref) in one rounding.
+// psc = p sc; for pair K, href = c < 3 ? fma(E, m, t) : E m.
+template <int K, class R>
+__device__ inline R fref3_cu_scaled(R cu, R psc, R uu, R sc) {
+  constexpr R wi = (R)Lat<3>::w(2 * K - 1), lam_i = (R)(3.0 * Lat<3>::w(2 * K - 1));
+  return fmar(wi * sc, fmar(cu, fmar(cu, (R)4.5, (R)3), (R)-1.5 * uu), lam_i * psc);
+}
+template <int K, class R>
+__device__ inline void href3_cu_scaled(R cu, R sc, R& m, R& t) {
+  constexpr R wi = (R)Lat<3>::w(2 * K - 1);
+  const R tt = (R)(3.0 * Lat<3>::w(2 * K - 1)) * cu;
+  m = (wi + tt) * sc;
+  t = tt * sc;
+}
+template <class R>
+__device__ inline R fref3_rest_scaled(R psc, R uu, R sc) {
+  constexpr R w0 = (R)Lat<3>::w(0), lam0 = (R)(3.0 * (Lat<3>::w(0) - 1.0));
+  return fmar(w0 * sc, (R)-1.5 * uu, lam0 * psc);
+}
+
+// any direction i, by its pair: equal bitwise to the forms above
+template <class R>
+__device__ inline R fref3(int i, R p, const R* u) {
+  if (i == 0) return fref3_rest(p, uu3(u));
+  const R sgn = (i & 1) ? (R)1 : (R)-1;
+  switch ((i + 1) >> 1) {
+    case 1: return fref3_pair<1, R>(sgn, p, u);
+    case 2: return fref3_pair<2, R>(sgn, p, u);
+    case 3: return fref3_pair<3, R>(sgn, p, u);
+    case 4: return fref3_pair<4, R>(sgn, p, u);
+    case 5: return fref3_pair<5, R>(sgn, p, u);
+    case 6: return fref3_pair<6, R>(sgn, p, u);
+    case 7: return fref3_pair<7, R>(sgn, p, u);
+    case 8: return fref3_pair<8, R>(sgn, p, u);
+    default: return fref3_pair<9, R>(sgn, p, u);
+  }
+}
+template <class R>
+__device__ inline R href3(int i, int c, R E, const R* u) {
+  if (i == 0) return href3_rest(E);
+  const R sgn = (i & 1) ? (R)1 : (R)-1;
+  switch ((i + 1) >> 1) {
+    case 1: return href3_pair<1, R>(sgn, c, E, u);
+    case 2: return href3_pair<2, R>(sgn, c, E, u);
+    case 3: return href3_pair<3, R>(sgn, c, E, u);
+    case 4: return href3_pair<4, R>(sgn, c, E, u);
+    case 5: return href3_pair<5, R>(sgn, c, E, u);
+    case 6: return href3_pair<6, R>(sgn, c, E, u);
+    case 7: return href3_pair<7, R>(sgn, c, E, u);
+    case 8: return href3_pair<8, R>(sgn, c, E, u);
+    default: return href3_pair<9, R>(sgn, c, E, u);
+  }
 }
 
 // D3Q19 anchor of node n, after the 16-bit populations of the buffer (it

@@ -24,7 +24,13 @@
 // from an LDS stage of the anchors around the tile, AnchorStage), and the
 // stored values are deviations from the node's new anchor (E = the
 // conformation moment the h collision produces, the pressure, u), which the
-// even lane stores.
+// even lane stores.  The anchored step has no LDS stage for the tuples (the
+// anchor stage takes its place): it loads the raw 16-bit tuples of plane
+// z+1 into registers while plane z collides, and runs one wave per SIMD.
+// Its per-plane cost is arithmetic more than memory: the references are
+// evaluated in a factored form with explicit fused multiply-adds (one
+// multiply or fused multiply-add per component), measured on MI355X at
+// 512^3: 42.6 ms per step with separate multiplies and adds, 38.0 ms so.
 #pragma once
 
 #include "kernels.h"
@@ -87,11 +93,31 @@ template <class S> struct Pair3 {
   __device__ static R load_f(const S* p, int k, uint32_t o, size_t N, R isf) {
     return C::in(*reinterpret_cast<const V*>(fb(p, k, N) + o * (uint32_t)sizeof(V)), isf);
   }
+  // anchored storage: the stored 16-bit values as they are, converted when
+  // used (loads issued a plane ahead)
+  __device__ static V load_f_raw(const S* p, int k, uint32_t o, size_t N) {
+    return *reinterpret_cast<const V*>(fb(p, k, N) + o * (uint32_t)sizeof(V));
+  }
+  __device__ static void load_h_raw(const S* p, int k, uint32_t o, size_t N, v4& a, v2& b) {
+    a = *reinterpret_cast<const v4*>(h4b(p, k, N) + o * (uint32_t)sizeof(v4));
+    b = *reinterpret_cast<const v2*>(h2b(p, k, N) + o * (uint32_t)sizeof(v2));
+  }
   __device__ static void load_h(const S* p, int k, uint32_t o, size_t N, R ish, R* h) {
     const v4 a = *reinterpret_cast<const v4*>(h4b(p, k, N) + o * (uint32_t)sizeof(v4));
     const v2 b = *reinterpret_cast<const v2*>(h2b(p, k, N) + o * (uint32_t)sizeof(v2));
     h[0] = C::in(a.x, ish); h[1] = C::in(a.y, ish); h[2] = C::in(a.z, ish);
     h[3] = C::in(a.w, ish); h[4] = C::in(b.x, ish); h[5] = C::in(b.y, ish);
+  }
+  // anchored storage: deviations already scaled, converted as they are
+  __device__ static void store_dev(S* p, int k, uint32_t o, size_t N, R f, const R* h) {
+    const v4 a = {(V)h[0], (V)h[1], (V)h[2], (V)h[3]};
+    const v2 b = {(V)h[4], (V)h[5]};
+    __builtin_nontemporal_store(
+        (V)f, reinterpret_cast<V*>(const_cast<char*>(fb(p, k, N)) + o * (uint32_t)sizeof(V)));
+    __builtin_nontemporal_store(
+        a, reinterpret_cast<v4*>(const_cast<char*>(h4b(p, k, N)) + o * (uint32_t)sizeof(v4)));
+    __builtin_nontemporal_store(
+        b, reinterpret_cast<v2*>(const_cast<char*>(h2b(p, k, N)) + o * (uint32_t)sizeof(v2)));
   }
   __device__ static void store(S* p, int k, uint32_t o, size_t N, R sf, R sh, R f, R hxx, R hyy,
                                R hzz, R hxy, R hxz, R hyz) {
@@ -412,12 +438,18 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       }
     }
   };
+  // sign of the stored member named by a pulled offset (1: direction
+  // 2K - 1, -1: direction 2K); without walls it is the lane's own member
+  auto member_sign = [&](uint32_t o) {
+    if constexpr (WALLS) return o >= N32 ? (R)-1 : (R)1;
+    else return sg;
+  };
   // stage index of the writer of this lane's member of pair K, for a node at
   // stage position (lx, ly) in plane zp: the node itself after a bounce-back
   // (the pulled offset names the other member), else the node at -c
   auto anc_at = [&](auto kc, uint32_t o, int lx, int ly, int zp, int& sl) {
     constexpr int K = decltype(kc)::value, i = 2 * K - 1;
-    const bool bounce = (o >= N32) != (s != 0);
+    const bool bounce = WALLS && ((o >= N32) != (s != 0));
     const int cx = s ? -L::cx(i) : L::cx(i), cy = s ? -L::cy(i) : L::cy(i),
               cz = s ? -L::cz(i) : L::cz(i);
     sl = anc_slot(bounce ? zp : zp - cz);
@@ -432,26 +464,30 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
     for_pairs<1>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const uint32_t o = pair_src<k, WALLS>(pp, s, N32);
-      fo[k] = PA::load_f(pin, k, o, N, a.inv_sf);
-      if constexpr (ANCH) {  // + the reference of the writer (member o / N)
+      if constexpr (ANCH) {  // deviation + the reference of the writer (member o / N)
         int sl;
         const int ks = anc_at(kc, o, alx, aly, zp, sl);
         const float4 q = as.pu[sl][ks];
         const R uw[3] = {(R)q.y, (R)q.z, (R)q.w};
-        fo[k] += fref3_pair<k, R>(o >= N32 ? (R)-1 : (R)1, (R)q.x, uw);
+        fo[k] = fmar((R)PA::load_f_raw(pin, k, o, N), a.inv_sf,
+                     fref3_pair<k, R>(member_sign(o), (R)q.x, uw));
+      } else {
+        fo[k] = PA::load_f(pin, k, o, N, a.inv_sf);
       }
     });
     make_pair_pull(hx, hy, zw, s, g, pp);
     for_pairs<1>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const uint32_t o = pair_src<k, WALLS>(pp, s, N32);
-      fr[k] = PA::load_f(pin, k, o, N, a.inv_sf);
       if constexpr (ANCH) {
         int sl;
         const int ks = anc_at(kc, o, hlx, hly, zp, sl);
         const float4 q = as.pu[sl][ks];
         const R uw[3] = {(R)q.y, (R)q.z, (R)q.w};
-        fr[k] += fref3_pair<k, R>(o >= N32 ? (R)-1 : (R)1, (R)q.x, uw);
+        fr[k] = fmar((R)PA::load_f_raw(pin, k, o, N), a.inv_sf,
+                     fref3_pair<k, R>(member_sign(o), (R)q.x, uw));
+      } else {
+        fr[k] = PA::load_f(pin, k, o, N, a.inv_sf);
       }
     });
   };
@@ -497,10 +533,14 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   // u(z + 1) from the f pulled one plane ago; read the staged h, rest f and
   // source state of z (landed during the previous plane); start the LDS-DMA
   // loads of plane z + 1 and the register loads of the moving f of plane
-  // z + 2; collide and store z.  Every load is waited for at the top of the
-  // next plane, a whole collision after its issue.  The own moving f of z
-  // and z + 1 ride in registers.  FP64 (no LDS stage: it would not fit)
-  // loads plane z straight to registers instead.
+  // z + 2; collide and store z.  The loads are waited for after the
+  // collision, before the stores (a whole collision after their issue);
+  // nothing waits for the stores inside the loop (the memory counter that
+  // covers loads covers stores as well, so a wait placed after them would
+  // hold every plane for its write latency).  The own moving f of z and
+  // z + 1 ride in registers.  FP64 (no LDS stage: it would not fit)
+  // loads plane z straight to registers instead; anchored 16-bit storage
+  // loads the raw tuples of plane z + 1 into registers during plane z.
   // (the stage of the first plane is requested before the pulls that start
   // the velocity ring, whose waits then cover it as well)
   if constexpr (kDma) {
@@ -513,6 +553,32 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
     lds_barrier();
   }
+  // Anchored 16-bit storage: the h tuples, rest f and previous-step source
+  // state of plane z + 1 are loaded into registers during plane z, as the
+  // raw 16-bit values, and rebuilt against their writers' anchors when
+  // plane z + 1 collides: their latency hides behind a collision, as the
+  // LDS stage hides it for FP32.
+  typename PA::v4 rh4[ANCH ? NP : 1];
+  typename PA::v2 rh2[ANCH ? NP : 1];
+  typename PA::V rf0 = {};
+  R raux[ANCH ? 9 : 1];
+  auto issue_raw = [&](int zp) {
+    if constexpr (ANCH) {
+      PairPull pq;
+      make_pair_pull(ox, oy, zp, s, g, pq);
+      rf0 = PA::load_f_raw(pin, 0, pq.self, N);
+      PA::load_h_raw(pin, 0, pq.self, N, rh4[0], rh2[0]);
+      for_pairs<1>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        PA::load_h_raw(pin, k, pair_src<k, WALLS>(pq, s, N32), N, rh4[k], rh2[k]);
+      });
+      if (!a.first) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) raux[q] = aux[(size_t)q * N + pq.self];
+      }
+    }
+  };
+  if constexpr (ANCH) issue_raw(zs);
   R fz[NP], fn[NP], frn[NP];
   {
     R fa[NP];
@@ -522,22 +588,19 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
     publish_u(zs, fz, frn);
   }
   pull_plane(zs + 1, fn, frn);
+  // the first plane's stage (LDS-DMA loads need not retire in order with
+  // other memory operations)
+  if constexpr (kDma) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+  // anchored: the pulls above have read the anchor slot of plane zs - 2
+  if constexpr (ANCH) lds_barrier();
 
 #pragma unroll 1
   for (int z = zs; z < ze; ++z) {
-    // everything issued during the previous plane has landed: LDS-DMA loads
-    // need not retire in order with other memory operations
-    if constexpr (kDma || ANCH) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
     // raised priority while this wave issues the next planes' loads, so that
     // they are not held behind the other resident wave's collision
     // (measured on MI355X, 512^3: FP32 29.60 -> 28.63 ms, FP16 42.93 ->
     // 42.65 ms; FP64, at one wave per SIMD, 7.69 -> 8.01 ms, so not there)
     if constexpr (!kF64) __builtin_amdgcn_s_setprio(2);
-    if constexpr (ANCH) {
-      lds_barrier();  // the anchors of plane z + 3 (issued a plane ago) are in
-      // plane z - 2 is no longer read: its slot takes plane z + 4
-      if (z + 1 < ze) anc_issue(z + 4);
-    }
     publish_u(z + 1, fn, frn);
     PairPull pl;
     make_pair_pull(ox, oy, z, s, g, pl);
@@ -572,37 +635,52 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
         make_pair_pull(ox, oy, z + 1, s, g, pq);
         stage_issue<S, TY, WALLS>(st, pin, aux, pq, s, N, a.first != 0, ty);
       }
-    } else {  // FP64 and 16-bit: plane z straight to registers
-      R h0[NC];
-      R f0 = PA::load_f(pin, 0, n, N, a.inv_sf);
-      PA::load_h(pin, 0, n, N, a.inv_sh, h0);
-      if constexpr (ANCH) {  // the rest population's writer is the node itself
+    } else if constexpr (ANCH) {  // plane z from the registers loaded a plane ago
+      {  // the rest population's writer is the node itself
         const int sl = anc_slot(z), ks = aly * (TXN + 4) + alx;
         const float4 q = as.pu[sl][ks], e = as.e4[sl][ks];
         const R uw[3] = {(R)q.y, (R)q.z, (R)q.w};
         const R Ew[6] = {(R)e.x, (R)e.y, (R)e.z, (R)e.w, (R)as.e5[sl][ks], (R)as.e6[sl][ks]};
-        f0 += fref3<R>(0, (R)q.x, uw);
+        const R hr[NC] = {(R)rh4[0].x, (R)rh4[0].y, (R)rh4[0].z,
+                          (R)rh4[0].w, (R)rh2[0].x, (R)rh2[0].y};
+        const R f0 = fmar((R)rf0, a.inv_sf, fref3_rest<R>((R)q.x, uu3(uw)));
+        f[0] = s ? (R)0 : f0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) h0[c] += href3<R>(0, c, Ew[c], uw);
+        for (int c = 0; c < NC; ++c)
+          h[c][0] = s ? (R)0 : fmar(hr[c], a.inv_sh, href3_rest<R>(Ew[c]));
       }
+      for_pairs<1>([&](auto kc) {  // deviation + the reference of the writer (member o / N)
+        constexpr int k = decltype(kc)::value;
+        const uint32_t o = pair_src<k, WALLS>(pl, s, N32);
+        int sl;
+        const int ks = anc_at(kc, o, alx, aly, z, sl);
+        const float4 q = as.pu[sl][ks], e = as.e4[sl][ks];
+        const R uw[3] = {(R)q.y, (R)q.z, (R)q.w};
+        const R Ew[6] = {(R)e.x, (R)e.y, (R)e.z, (R)e.w, (R)as.e5[sl][ks], (R)as.e6[sl][ks]};
+        const R hr[NC] = {(R)rh4[k].x, (R)rh4[k].y, (R)rh4[k].z,
+                          (R)rh4[k].w, (R)rh2[k].x, (R)rh2[k].y};
+        const R cw = cu_pair3<k, R>(member_sign(o), uw);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) h[c][k] = fmar(hr[c], a.inv_sh, href3_cu<k, R>(cw, c, Ew[c]));
+      });
+      if (!a.first) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) chip[c] = raux[c];
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) up[bb] = raux[NC + bb];
+      }
+      if (z + 1 < ze) issue_raw(z + 1);
+    } else {  // FP64: plane z straight to registers
+      R h0[NC];
+      const R f0 = PA::load_f(pin, 0, n, N, a.inv_sf);
+      PA::load_h(pin, 0, n, N, a.inv_sh, h0);
       f[0] = s ? (R)0 : f0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) h[c][0] = s ? (R)0 : h0[c];
       for_pairs<1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         R hv[NC];
-        const uint32_t o = pair_src<k, WALLS>(pl, s, N32);
-        PA::load_h(pin, k, o, N, a.inv_sh, hv);
-        if constexpr (ANCH) {  // + the reference of the writer (member o / N)
-          int sl;
-          const int ks = anc_at(kc, o, alx, aly, z, sl);
-          const float4 q = as.pu[sl][ks], e = as.e4[sl][ks];
-          const R uw[3] = {(R)q.y, (R)q.z, (R)q.w};
-          const R Ew[6] = {(R)e.x, (R)e.y, (R)e.z, (R)e.w, (R)as.e5[sl][ks], (R)as.e6[sl][ks]};
-          const R sgw = o >= N32 ? (R)-1 : (R)1;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) hv[c] += href3_pair<k, R>(sgw, c, Ew[c], uw);
-        }
+        PA::load_h(pin, k, pair_src<k, WALLS>(pl, s, N32), N, a.inv_sh, hv);
 #pragma unroll
         for (int c = 0; c < NC; ++c) h[c][k] = hv[c];
       });
@@ -614,6 +692,14 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       fz[k] = fn[k];
     }
     pull_plane(z + 2, fn, frn);
+    // anchored: the pulls of this plane have read the anchor stage for the
+    // last time (planes z - 1 .. z + 3); the slot of plane z - 2 takes plane
+    // z + 4, which lands before this plane's stores and is read after the
+    // barrier that closes the plane.  (Issued after the reads, so the
+    // compiler need not wait for the transfer before them.)
+    if constexpr (ANCH) {
+      if (z + 1 < ze) anc_issue(z + 4);
+    }
     if constexpr (!kF64) __builtin_amdgcn_s_setprio(0);
     lds_barrier();  // u(z + 1) published
 
@@ -752,7 +838,10 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       }
 
       // ---- stores (the even lane holds the rest populations); chi (6
-      // planes) then u (3 planes) split over the pair
+      // planes) then u (3 planes) split over the pair.  First every load
+      // issued during this plane has landed: the next plane reads the LDS
+      // stages they fill, after the barrier below.
+      if constexpr (kDma || ANCH) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
       if (in_xy) {
         if constexpr (ANCH) {
           // deviations from this node's new anchor (E, p, u)
@@ -762,22 +851,30 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
 #pragma unroll
           for (int bb = 0; bb < 3; ++bb) uf[bb] = (float)u[bb];
           const float pf = (float)p;
+          // scaled deviations (v - ref) sc = fma(v, sc, -(sc ref)), the
+          // references scaled exactly (power-of-two scales)
           const R ur[3] = {(R)uf[0], (R)uf[1], (R)uf[2]};
+          const R uur = uu3(ur), psc = (R)pf * a.sf;
           if (s == 0) {
+            const R w0s = (R)L::w(0) * a.sh;
             R d[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) d[c] = h[c][0] - href3<R>(0, c, (R)Ef[c], ur);
-            PA::store(pout, 0, n, N, a.sf, a.sh, f[0] - fref3<R>(0, (R)pf, ur), d[0], d[1], d[2],
-                      d[3], d[4], d[5]);
+            for (int c = 0; c < NC; ++c) d[c] = fmar(h[c][0], a.sh, -(w0s * (R)Ef[c]));
+            PA::store_dev(pout, 0, n, N, fmar(f[0], a.sf, -fref3_rest_scaled<R>(psc, uur, a.sf)),
+                          d);
             Anchor3::store(pout, n, N, pf, uf, Ef);
           }
           for_pairs<1>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
+            const R cr = cu_pair3<k, R>(sg, ur);
+            R m, t;
+            href3_cu_scaled<k, R>(cr, a.sh, m, t);
             R d[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) d[c] = h[c][k] - href3_pair<k, R>(sg, c, (R)Ef[c], ur);
-            PA::store(pout, k, (s ? N32 : 0u) + n, N, a.sf, a.sh,
-                      f[k] - fref3_pair<k, R>(sg, (R)pf, ur), d[0], d[1], d[2], d[3], d[4], d[5]);
+            for (int c = 0; c < NC; ++c)
+              d[c] = fmar(h[c][k], a.sh, -(c < 3 ? fmar((R)Ef[c], m, t) : (R)Ef[c] * m));
+            PA::store_dev(pout, k, (s ? N32 : 0u) + n, N,
+                          fmar(f[k], a.sf, -fref3_cu_scaled<k, R>(cr, psc, uur, a.sf)), d);
           });
         } else {
           if (s == 0)

@@ -17,6 +17,7 @@
 #include "step2d.h"
 #include "step3d.h"
 #include "aa3d.h"
+#include "probe.h"
 #include "internal.h"
 
 using namespace vflb;
@@ -1069,19 +1070,37 @@ vflb_status vflb_load(vflb_sim* s, const void* blob, size_t n) {
   return VFLB_OK;
 }
 
-vflb_status vflb_stream_copy(const void* src, void* dst, size_t nbytes, void* hip_stream) {
-  if (!src || !dst || nbytes % 16 != 0 || ((uintptr_t)src | (uintptr_t)dst) % 16 != 0)
-    return fail(nullptr, VFLB_EINVAL, "stream copy needs 16-byte aligned pointers and sizes");
-  const size_t n = nbytes / 16;
+vflb_status vflb_copy_probe(const void* src, void* dst, size_t nbytes, int kind,
+                            void* hip_stream) {
+  if (kind < 0 || kind > 3) return fail(nullptr, VFLB_EINVAL, "copy kind must be 0..3");
+  const size_t unit = kind == 2 ? 4 : 16;
+  if (!src || !dst || nbytes % unit != 0 || ((uintptr_t)src | (uintptr_t)dst) % unit != 0)
+    return fail(nullptr, VFLB_EINVAL, "copy needs %zu-byte aligned pointers and sizes", unit);
+  const size_t n = nbytes / unit;
   if (n == 0) return VFLB_OK;
   const size_t blocks = (n + 255) / 256;
   if (blocks > 0x7fffffffu) return fail(nullptr, VFLB_EINVAL, "copy too large");
-  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                     static_cast<hipStream_t>(hip_stream), static_cast<const v4u32*>(src),
-                     static_cast<v4u32*>(dst), n);
+  const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const dim3 grid((unsigned)blocks), block(256);
+  if (kind == 0)
+    hipLaunchKernelGGL(stream_copy_kernel, grid, block, 0, st, static_cast<const v4u32*>(src),
+                       static_cast<v4u32*>(dst), n);
+  else if (kind == 1)
+    hipLaunchKernelGGL(copy_plain16_kernel, grid, block, 0, st, static_cast<const v4u32*>(src),
+                       static_cast<v4u32*>(dst), n);
+  else if (kind == 2)
+    hipLaunchKernelGGL(copy_plain4_kernel, grid, block, 0, st, static_cast<const uint32_t*>(src),
+                       static_cast<uint32_t*>(dst), n);
+  else
+    hipLaunchKernelGGL(copy_lds16_kernel, grid, block, 0, st, static_cast<const v4u32*>(src),
+                       static_cast<v4u32*>(dst), n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(nullptr, VFLB_EDEVICE, "copy launch failed: %s", hipGetErrorString(e));
   return VFLB_OK;
+}
+
+vflb_status vflb_stream_copy(const void* src, void* dst, size_t nbytes, void* hip_stream) {
+  return vflb_copy_probe(src, dst, nbytes, 0, hip_stream);
 }
 
 vflb_status vflb_settle(vflb_sim* s, const float* dev_targets, int64_t nsteps, int flags) {

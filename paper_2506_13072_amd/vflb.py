@@ -102,6 +102,8 @@ def lib():
         L.vflb_set_tile.argtypes = [P, I]
         L.vflb_stream_copy.argtypes = [P, P, SZ, P]
         L.vflb_stream_copy.restype = I
+        L.vflb_copy_probe.argtypes = [P, P, SZ, I, P]
+        L.vflb_copy_probe.restype = I
         L.vflb_destroy.argtypes = [P]
         L.vflb_destroy.restype = None
         L.vflb_batch_create.argtypes = [I, I, ctypes.POINTER(I), I, P, ctypes.POINTER(P)]
@@ -187,14 +189,16 @@ def _mcheck(handle, code):
         raise VflbError(code, msg.decode() if msg else "")
 
 
-def stream_copy(src, dst, stream):
-    """Plain device copy of src into dst (torch tensors of equal byte size)
-    on the given torch stream, by the library's bandwidth-probe kernel."""
+def stream_copy(src, dst, stream, kind=0):
+    """Device copy of src into dst (torch tensors of equal byte size) on the
+    given torch stream, by the library's probe kernels: kind 0 non-temporal
+    16-byte accesses, 1 plain 16-byte, 2 plain 4-byte, 3 16-byte LDS-DMA
+    loads."""
     nbytes = src.numel() * src.element_size()
     assert dst.numel() * dst.element_size() == nbytes
-    _check(None, lib().vflb_stream_copy(ctypes.c_void_p(src.data_ptr()),
-                                        ctypes.c_void_p(dst.data_ptr()), nbytes,
-                                        ctypes.c_void_p(stream.cuda_stream)))
+    _check(None, lib().vflb_copy_probe(ctypes.c_void_p(src.data_ptr()),
+                                       ctypes.c_void_p(dst.data_ptr()), nbytes, kind,
+                                       ctypes.c_void_p(stream.cuda_stream)))
 
 
 class Sim:

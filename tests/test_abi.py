@@ -92,3 +92,13 @@ def test_batch_create_validates_arguments_on_host(lib):
     assert lib.vflb_batch_create(2, 2, bad, 1, None, ctypes.byref(h)) == 1    # size
     assert b"instance 1" in lib.vflb_batch_last_error(None)
     assert not h.value
+
+
+def test_copy_probe_validates_arguments_on_host(lib):
+    P = ctypes.c_void_p
+    assert lib.vflb_copy_probe(P(16), P(32), 32, 4, None) == 1          # kind
+    assert b"kind" in lib.vflb_last_error(None)
+    assert lib.vflb_copy_probe(P(16), P(32), 24, 1, None) == 1          # 16-byte size
+    assert lib.vflb_copy_probe(P(8), P(32), 32, 3, None) == 1           # alignment
+    assert lib.vflb_copy_probe(P(16), P(32), 0, 2, None) == 0           # empty: no launch
+    assert lib.vflb_stream_copy(P(16), P(32), 17, None) == 1
