@@ -237,6 +237,57 @@ def run_gpu_ensemble(n, steps, warmup, storage="f32", compare_unbatched=True):
     return out
 
 
+def run_gpu_ensemble_steady(n, storage="f64", tol=1e-6, every=100, chunk=20000):
+    """The four-roll ensemble run to a steady state in one batch: every
+    instance from rest until its residual R < tol over `every` steps, capped
+    at 40 max(lambda, T_nu) steps (T_nu = 1 / (nu k^2), the viscous time),
+    compacted as instances leave.  The run is cut into windows of `chunk`
+    steps (each window one vflb_batch_run_until call, instances still short
+    of tol resume in the next) only so that progress is printed.  Returns
+    per-instance steps and outcomes and the wall time."""
+    import math
+    import tempfile
+    import torch
+    from paper_2506_13072_amd import vflb as V
+    specs = ensemble_specs(n)
+    b = V.Batch([(sp["side"], sp["side"]) for sp in specs], storage)
+    for i, sp in enumerate(specs):
+        setup_instance(V, b[i], sp)
+    tile = b.autotune(os.path.join(tempfile.gettempdir(), "vflb_autotune.txt"))
+    for i in range(n):
+        b[i].init_fields()
+    caps = []
+    for sp in specs:
+        t_nu = sp["side"] / (2 * math.pi * sp["U0"])   # 1 / (nu k^2) at Re = 1
+        lam = sp["Wi"] * t_nu
+        caps.append(int(math.ceil(min(2_000_000, 40 * max(lam, t_nu)) / every) * every))
+    status = np.zeros(n, dtype=np.int32)
+    steps = np.zeros(n, dtype=np.int64)
+    resid = np.full(n, np.inf)
+    b.synchronize()
+    t0 = time.perf_counter()
+    level = 0
+    while (status == V.RUN_ACTIVE).any():
+        run = np.flatnonzero(status == V.RUN_ACTIVE)
+        level = min(level + chunk, max(caps[i] for i in run))
+        for i in range(n):
+            b.set_active(i, int(status[i] == V.RUN_ACTIVE))
+        ms = [min(caps[i], level) for i in range(n)]
+        st, res, out = b.run_until(tol, every, ms)
+        for i in run:
+            steps[i], resid[i] = st[i], res[i]
+            if not (out[i] == V.RUN_CAPPED and st[i] < caps[i]):
+                status[i] = out[i]
+        print(f"ensemble to R < {tol:g}: step {level}, {int((status == V.RUN_ACTIVE).sum())} "
+              f"running, {int((status == V.RUN_CONVERGED).sum())} converged, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    nodes = np.array([sp["side"] ** 2 for sp in specs], dtype=np.int64)
+    del b
+    return dict(specs=specs, steps=steps, resid=resid, status=status, caps=np.array(caps),
+                wall_s=wall, lups=float((steps * nodes).sum()), nodes=int(nodes.sum()), tile=tile)
+
+
 def run_gpu_warmstart(n_train=96, n_test=16, side=64, tol=1e-6, iters=8000, K0=1000,
                       settle=0, window=5, storage="f64", settle_flags=3, geometry="four_roll"):
     """Time to a steady state (R < tol) of held-out four-roll lattices (or
@@ -464,8 +515,8 @@ def main():
                     help="copy probe access kind: 0 non-temporal 16-byte, 1 plain 16-byte, "
                          "2 plain 4-byte, 3 16-byte LDS-DMA loads")
     ap.add_argument("--workload", default="tgv",
-                    choices=["channel", "tgv", "ensemble", "warmstart", "schemes", "schemes3d",
-                             "inplace", "inplace3d"],
+                    choices=["channel", "tgv", "ensemble", "ensemble_steady", "warmstart",
+                             "schemes", "schemes3d", "inplace", "inplace3d"],
                     help="tgv (default): the 512^3 D3Q19 Taylor-Green vortex; channel: the "
                          "8192x1024 D2Q9 Poiseuille channel; ensemble: 256 four-roll "
                          "lattices of sides 64..512 as one batch")
@@ -483,8 +534,8 @@ def main():
     ap.add_argument("--ws-settle-flags", type=int, default=3,
                     help="warmstart: fields prescribed while settling (1 u, 2 A, 3 both)")
     ap.add_argument("--ws-storage", default="f64", choices=["f64", "f32"],
-                    help="warmstart: storage of the runs to R < 1e-6 (FP32 rounding stalls "
-                         "these flows near R = 1e-6)")
+                    help="warmstart and ensemble_steady: storage of the runs to R < 1e-6 (FP32 "
+                         "rounding stalls these flows near R = 1e-6)")
     ap.add_argument("--tgv-n", type=int, default=512)
     args = ap.parse_args()
     three_d = args.workload in ("tgv", "schemes3d", "inplace3d")
@@ -680,6 +731,37 @@ def main():
                               round(ip["ms_per_step"] / tb["ms_per_step"], 4),
                           "memory_ratio_in_place_over_two_buffers":
                               round(ip["buffer_bytes"] / tb["buffer_bytes"], 4)}), flush=True)
+        return
+    if args.workload == "ensemble_steady":
+        r = run_gpu_ensemble_steady(args.instances, args.ws_storage)
+        st, sides = r["status"], np.array([sp["side"] for sp in r["specs"]])
+        from paper_2506_13072_amd import vflb as V
+        by_side = {}
+        for side in sorted(set(sides.tolist())):
+            m = sides == side
+            by_side[str(side)] = dict(instances=int(m.sum()),
+                                      converged=int((st[m] == V.RUN_CONVERGED).sum()),
+                                      median_steps=int(np.median(r["steps"][m])),
+                                      max_steps=int(r["steps"][m].max()))
+        print(json.dumps({"metric": "time to steady state (R < 1e-6), batched four-roll ensemble",
+                          "value": round(r["wall_s"], 2), "unit": "s", "n_gpus": 1,
+                          "steps": int(r["steps"].max()), "warmup": 0,
+                          "ms_per_step": None, "higher_is_better": False,
+                          "scaling": "weak", "vs_baseline": None,
+                          "dtype": args.ws_storage, "data": "synthetic",
+                          "config": {"workload": f"four-roll ensemble, {args.instances} D2Q9 "
+                                                 "lattices, sides 64..512, seeded Wi and beta, "
+                                                 "each from rest to R < 1e-6",
+                                     "storage": args.ws_storage, "nodes": r["nodes"],
+                                     "tile_y": r["tile"], "check_every": 100,
+                                     "cap": "40 max(lambda, 1/(nu k^2)), at most 2e6"},
+                          "converged": int((st == V.RUN_CONVERGED).sum()),
+                          "capped": int((st == V.RUN_CAPPED).sum()),
+                          "unstable": int((st == V.RUN_UNSTABLE).sum()),
+                          "steps_total": int(r["steps"].sum()),
+                          "lattice_updates": r["lups"],
+                          "GLUPS_over_run": round(r["lups"] / r["wall_s"] / 1e9, 2),
+                          "by_side": by_side}), flush=True)
         return
     if args.workload == "ensemble":
         r = run_gpu_ensemble(args.instances, args.steps, args.warmup, args.storage)
