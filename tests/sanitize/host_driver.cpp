@@ -24,8 +24,10 @@ int main() {
   expect(vflb_create(VFLB_D3Q19, 16, 16, 16, VFLB_BF16S, nullptr, &s) == VFLB_EINVAL, "bf16 3d");
   expect(vflb_create(VFLB_D3Q19, 512, 512, 513, VFLB_F32, nullptr, &s) == VFLB_EINVAL, "3d size");
   expect(vflb_create_ex(VFLB_D2Q9, 8, 8, 1, VFLB_F32, 0, 2, nullptr, &s) == VFLB_EINVAL, "option");
-  expect(vflb_create_ex(VFLB_D3Q19, 8, 8, 8, VFLB_F32, 0, VFLB_OPT_INPLACE, nullptr, &s) ==
-             VFLB_EINVAL, "in place 3d");
+  expect(vflb_create_ex(VFLB_D3Q19, 8, 8, 8, VFLB_F16S, 0, VFLB_OPT_INPLACE, nullptr, &s) ==
+             VFLB_EINVAL, "in place 3d 16-bit");
+  expect(vflb_copy_probe(reinterpret_cast<void*>(16), reinterpret_cast<void*>(32), 32, 4,
+                         nullptr) == VFLB_EINVAL, "copy kind");
   expect(vflb_create_scheme(VFLB_D2Q9, 8, 8, 1, VFLB_F16S, VFLB_SCHEME_STRESS_DIVERGENCE, nullptr,
                             &s) == VFLB_EINVAL, "scheme 16-bit");
   expect(vflb_create(VFLB_D2Q9, 8, 8, 1, VFLB_F32, nullptr, nullptr) == VFLB_EINVAL, "out");
