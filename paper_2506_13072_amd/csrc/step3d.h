@@ -318,7 +318,10 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   constexpr bool ANCH = StoreT<S>::kAnchored;
   constexpr bool kF64 = std::is_same<S, double>::value;
   constexpr int NP = 10, NC = 6, TXN = 32, SX = TXN + 2, SY = TY + 2, NS = SX * SY;
-  constexpr int H = 2 * SX + 2 * TY;  // ring nodes
+  // ring nodes: the rows above and below the tile and the columns left and
+  // right of it, without the four corners (the gradient's stencil reads the
+  // axis neighbours only)
+  constexpr int H = 2 * TXN + 2 * TY;
   static_assert(2 * H <= 64 * TY, "ring needs more lanes than the workgroup has");
   __shared__ R ring[3][3][NS];
   __shared__ Stage3<S, TY> st;
@@ -367,10 +370,10 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   if (tid < 2 * H) {
     const int r = tid >> 1;
     int sxl, syl;
-    if (r < SX) { sxl = r; syl = 0; }
-    else if (r < 2 * SX) { sxl = r - SX; syl = SY - 1; }
-    else if (r < 2 * SX + TY) { sxl = 0; syl = 1 + r - 2 * SX; }
-    else { sxl = SX - 1; syl = 1 + r - 2 * SX - TY; }
+    if (r < TXN) { sxl = 1 + r; syl = 0; }
+    else if (r < 2 * TXN) { sxl = 1 + r - TXN; syl = SY - 1; }
+    else if (r < 2 * TXN + TY) { sxl = 0; syl = 1 + r - 2 * TXN; }
+    else { sxl = SX - 1; syl = 1 + r - 2 * TXN - TY; }
     hslot = syl * SX + sxl;
     hlx = sxl + 1;
     hly = syl + 1;
