@@ -1,7 +1,7 @@
 // step2d.h -- the fused D2Q9 step, specialised for gfx950.
 //
 // Workgroup = TY wavefronts of 64 lanes; each wavefront owns one 64-node
-// row segment of a 64 x TY tile.  The 2(64+2) + 2 TY halo nodes of the tile
+// row segment of a 64 x TY tile.  The 2 (64 + TY) halo nodes of the tile
 // are assigned to the first lanes before any load is issued, so the halo
 // pulls travel with the tile's own 36 population loads in one round trip.
 // Tiles are numbered row-major in launch order (measured faster on MI355X
@@ -84,7 +84,10 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
   using R = typename StoreT<S>::R;
   constexpr bool ANCHOR = StoreT<S>::kAnchored;
   constexpr int Q = 9, NC = 3, TX = 64, SX = TX + 2, SY = TY + 2;
-  constexpr int H = 2 * SX + 2 * TY;  // halo nodes of the tile
+  // halo nodes of the tile: the rows above and below it and the columns
+  // left and right of it, without the four corners (the gradient's stencil
+  // reads the axis neighbours only)
+  constexpr int H = 2 * TX + 2 * TY;
   constexpr int AX = TX + 4, AY = TY + 4;  // anchor region (two-node halo)
   R (*su)[SX * SY] = lds.su;
 
@@ -105,10 +108,10 @@ __device__ inline void step2d_tile(const StepArgs<S>& a, int x0, int y0,
   int hslot = 0, hx = 0, hy = 0;
   if (tid < H) {
     int sxl, syl;
-    if (tid < SX) { sxl = tid; syl = 0; }
-    else if (tid < 2 * SX) { sxl = tid - SX; syl = SY - 1; }
-    else if (tid < 2 * SX + TY) { sxl = 0; syl = 1 + tid - 2 * SX; }
-    else { sxl = SX - 1; syl = 1 + tid - 2 * SX - TY; }
+    if (tid < TX) { sxl = 1 + tid; syl = 0; }
+    else if (tid < 2 * TX) { sxl = 1 + tid - TX; syl = SY - 1; }
+    else if (tid < 2 * TX + TY) { sxl = 0; syl = 1 + tid - 2 * TX; }
+    else { sxl = SX - 1; syl = 1 + tid - 2 * TX - TY; }
     hslot = syl * SX + sxl;
     hx = x0 - 1 + sxl;
     hy = y0 - 1 + syl;
