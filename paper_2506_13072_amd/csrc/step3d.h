@@ -199,6 +199,36 @@ __device__ inline uint32_t pair_src(const PairPull& p, int s, uint32_t N) {
   return (s ? N : 0u) + (uint32_t)off;
 }
 
+// In-place (AA) streaming by pairs, the index maps of the in-place D3Q19
+// step (aa3d.h) seen from a lane's member: at even t (Geo::aa == 1) a lane
+// reads its member from the node's own slots and writes it into the
+// partner's member of the same node; at odd t it reads the partner's member
+// at x - c (the two-buffer pull with the members swapped; beyond a wall the
+// node's own member) and writes its own member at x + c (beyond a wall the
+// partner's member of the node itself).
+template <int K, bool WALLS>
+__device__ inline uint32_t aa_pair_src(const PairPull& p, int s, int aa, uint32_t N) {
+  if (aa == 1) return (s ? N : 0u) + p.self;
+  const uint32_t o = pair_src<K, WALLS>(p, s, N);
+  return o >= N ? o - N : o + N;
+}
+// p: the pull geometry of the lane (member s); the destination x + c of its
+// member is the source of the partner's member
+template <int K, bool WALLS>
+__device__ inline uint32_t aa_pair_dst(const PairPull& p, int s, int aa, uint32_t N) {
+  if (aa == 1) return (s ? 0u : N) + p.self;
+  PairPull q = p;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q.dm[a] = p.dp[a];
+    q.dp[a] = p.dm[a];
+    q.wm[a] = p.wp[a];
+    q.wp[a] = p.wm[a];
+  }
+  const uint32_t o = pair_src<K, WALLS>(q, 1 - s, N);
+  return o >= N ? o - N : o + N;
+}
+
 template <int K, class F>
 __device__ inline void for_pairs(F&& fn) {
   if constexpr (K <= 9) {
@@ -248,9 +278,10 @@ template <int TY> struct Stage3<float, TY> {
   float aux[9][TY][64];
 };
 
-template <class S, int TY, bool WALLS>
+template <class S, int TY, bool WALLS, bool AA = false>
 __device__ inline void stage_issue(Stage3<S, TY>& st, const S* pin, const typename StoreT<S>::R* aux,
-                                   const PairPull& pq, int s, size_t N, bool first, int ty) {
+                                   const PairPull& pq, int s, size_t N, bool first, int ty,
+                                   int aa = 0) {
   using PA = Pair3<S>;
   const uint32_t N32 = (uint32_t)N, n = pq.self;
   auto issue_h = [&](int k, uint32_t o) {
@@ -263,7 +294,10 @@ __device__ inline void stage_issue(Stage3<S, TY>& st, const S* pin, const typena
   issue_h(0, n);  // rest: both lanes, one address
   for_pairs<1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    issue_h(k, pair_src<k, WALLS>(pq, s, N32));
+    if constexpr (AA)
+      issue_h(k, aa_pair_src<k, WALLS>(pq, s, aa, N32));
+    else
+      issue_h(k, pair_src<k, WALLS>(pq, s, N32));
   });
   dma_to_lds<4>(pin + n, &st.f0[ty][0]);
   if (!first) {
@@ -308,15 +342,22 @@ template <int TY> struct AnchorStage<true, TY> {
 // instead of scratch memory.
 // DIV: the stress-divergence scheme (the force of every node includes
 // div tau_p of its plane, read from a.F.div; no f^B).
-template <class S, int TY, int ZC, bool WALLS, bool FULL, bool DIV = false>
+// AA: in-place streaming (FP32): one population buffer (a.pin == a.pout),
+// the pair index maps of aa_pair_src / aa_pair_dst by the parity of t, and
+// the same-time velocity of every node from the velocity pass, U [3][N]
+// (neighbours' slots are overwritten during the step, so the ring cannot
+// pull them); a lane's own f is loaded one plane ahead.
+template <class S, int TY, int ZC, bool WALLS, bool FULL, bool DIV = false, bool AA = false>
 __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchored) ? 1 : 2)
-    step3d_kernel(StepArgs<S> a, int ntx, int nty) {
+    step3d_kernel(StepArgs<S> a, int ntx, int nty,
+                  const typename StoreT<S>::R* __restrict__ U) {
   using R = typename StoreT<S>::R;
   using PA = Pair3<S>;
   using L = Lat<3>;
   constexpr bool kDma = std::is_same<S, float>::value;
   constexpr bool ANCH = StoreT<S>::kAnchored;
   constexpr bool kF64 = std::is_same<S, double>::value;
+  static_assert(!AA || kDma, "in-place z-march: FP32 storage");
   constexpr int NP = 10, NC = 6, TXN = 32, SX = TXN + 2, SY = TY + 2, NS = SX * SY;
   // ring nodes: the rows above and below the tile and the columns left and
   // right of it, without the four corners (the gradient's stencil reads the
@@ -333,6 +374,7 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   R* __restrict__ aux = a.aux;
   const size_t N = g.N;
   const uint32_t N32 = (uint32_t)N;  // N <= 2^27 (2^26 in FP64), checked on the host
+  const int aa = g.aa;               // in place: 1 at even t, 2 at odd t
 
   // Blocks are dealt to the eight XCDs in turn (block b to XCD b mod 8);
   // renumbering gives each XCD one contiguous run of tiles, so tiles that
@@ -532,6 +574,31 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
     }
   };
 
+  // in place: u of plane zp (own column and ring node) from the velocity
+  // pass, and the own f of plane zp
+  auto publish_aa = [&](int zp) {
+    const bool ok = plane_ok(zp);
+    const int rs = ring_slot(zp), zw = load_z(zp);
+    if (ok && vxy && s == 0) {
+      const size_t nd = node_of(ox, oy, zw, g);
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) ring[rs][bb][oslot] = U[(size_t)bb * N + nd];
+    }
+    if (ok && hxy && s == 0) {
+      const size_t nd = node_of(hx, hy, zw, g);
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) ring[rs][bb][hslot] = U[(size_t)bb * N + nd];
+    }
+  };
+  auto pull_aa = [&](int zp, R* fo) {
+    PairPull pp;
+    make_pair_pull(ox, oy, load_z(zp), s, g, pp);
+    for_pairs<1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      fo[k] = PA::load_f(pin, k, aa_pair_src<k, WALLS>(pp, s, aa, N32), N, a.inv_sf);
+    });
+  };
+
   // Software pipeline over the planes of the chunk.  Per plane z: publish
   // u(z + 1) from the f pulled one plane ago; read the staged h, rest f and
   // source state of z (landed during the previous plane); start the LDS-DMA
@@ -549,7 +616,7 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   if constexpr (kDma) {
     PairPull pq;
     make_pair_pull(ox, oy, zs, s, g, pq);
-    stage_issue<S, TY, WALLS>(st, pin, aux, pq, s, N, a.first != 0, ty);
+    stage_issue<S, TY, WALLS, AA>(st, pin, aux, pq, s, N, a.first != 0, ty, aa);
   }
   if constexpr (ANCH) {  // anchors of planes zs - 2 .. zs + 3
     for (int zp = zs - 2; zp <= zs + 3; ++zp) anc_issue(zp);
@@ -583,14 +650,20 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   };
   if constexpr (ANCH) issue_raw(zs);
   R fz[NP], fn[NP], frn[NP];
-  {
-    R fa[NP];
-    pull_plane(zs - 1, fa, frn);
-    publish_u(zs - 1, fa, frn);
-    pull_plane(zs, fz, frn);
-    publish_u(zs, fz, frn);
+  if constexpr (AA) {
+    publish_aa(zs - 1);
+    publish_aa(zs);
+    pull_aa(zs, fz);
+  } else {
+    {
+      R fa[NP];
+      pull_plane(zs - 1, fa, frn);
+      publish_u(zs - 1, fa, frn);
+      pull_plane(zs, fz, frn);
+      publish_u(zs, fz, frn);
+    }
+    pull_plane(zs + 1, fn, frn);
   }
-  pull_plane(zs + 1, fn, frn);
   // the first plane's stage (LDS-DMA loads need not retire in order with
   // other memory operations)
   if constexpr (kDma) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
@@ -604,7 +677,10 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
     // (measured on MI355X, 512^3: FP32 29.60 -> 28.63 ms, FP16 42.93 ->
     // 42.65 ms; FP64, at one wave per SIMD, 7.69 -> 8.01 ms, so not there)
     if constexpr (!kF64) __builtin_amdgcn_s_setprio(2);
-    publish_u(z + 1, fn, frn);
+    if constexpr (AA)
+      publish_aa(z + 1);
+    else
+      publish_u(z + 1, fn, frn);
     PairPull pl;
     make_pair_pull(ox, oy, z, s, g, pl);
     const uint32_t n = pl.self;
@@ -636,7 +712,7 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       if (z + 1 < ze) {
         PairPull pq;
         make_pair_pull(ox, oy, z + 1, s, g, pq);
-        stage_issue<S, TY, WALLS>(st, pin, aux, pq, s, N, a.first != 0, ty);
+        stage_issue<S, TY, WALLS, AA>(st, pin, aux, pq, s, N, a.first != 0, ty, aa);
       }
     } else if constexpr (ANCH) {  // plane z from the registers loaded a plane ago
       {  // the rest population's writer is the node itself
@@ -689,12 +765,18 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       });
       if (!a.first) Aux<3, R>::load(aux, n, N, chip, up);
     }
+    if constexpr (AA) {
 #pragma unroll
-    for (int k = 1; k < NP; ++k) {
-      f[k] = fz[k];
-      fz[k] = fn[k];
+      for (int k = 1; k < NP; ++k) f[k] = fz[k];
+      if (z + 1 < ze) pull_aa(z + 1, fz);
+    } else {
+#pragma unroll
+      for (int k = 1; k < NP; ++k) {
+        f[k] = fz[k];
+        fz[k] = fn[k];
+      }
+      pull_plane(z + 2, fn, frn);
     }
-    pull_plane(z + 2, fn, frn);
     // anchored: the pulls of this plane have read the anchor stage for the
     // last time (planes z - 1 .. z + 3); the slot of plane z - 2 takes plane
     // z + 4, which lands before this plane's stores and is read after the
@@ -883,10 +965,18 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
           if (s == 0)
             PA::store(pout, 0, n, N, a.sf, a.sh, f[0], h[0][0], h[1][0], h[2][0], h[3][0],
                       h[4][0], h[5][0]);
+          if constexpr (AA) {
+            for_pairs<1>([&](auto kc) {
+              constexpr int k = decltype(kc)::value;
+              PA::store(pout, k, aa_pair_dst<k, WALLS>(pl, s, aa, N32), N, a.sf, a.sh, f[k],
+                        h[0][k], h[1][k], h[2][k], h[3][k], h[4][k], h[5][k]);
+            });
+          } else {
 #pragma unroll
-          for (int k = 1; k < NP; ++k)
-            PA::store(pout, k, (s ? N32 : 0u) + n, N, a.sf, a.sh, f[k], h[0][k], h[1][k],
-                      h[2][k], h[3][k], h[4][k], h[5][k]);
+            for (int k = 1; k < NP; ++k)
+              PA::store(pout, k, (s ? N32 : 0u) + n, N, a.sf, a.sh, f[k], h[0][k], h[1][k],
+                        h[2][k], h[3][k], h[4][k], h[5][k]);
+          }
         }
         const R item[9] = {chi[0], chi[1], chi[2], chi[3], chi[4], chi[5], u[0], u[1], u[2]};
 #pragma unroll

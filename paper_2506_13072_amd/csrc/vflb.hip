@@ -105,15 +105,42 @@ void drop_graphs(vflb_sim* s) {
 }
 
 // D3Q19: 32 x tile_y node columns, tile_y 4 (two workgroups per CU) or 8
-template <class S, int TY, int ZC, bool WALLS, bool DIV = false>
+// (AA: in place, FP32; U the velocity pass's u(t) [3][N])
+template <class S, int TY, int ZC, bool WALLS, bool DIV = false, bool AA = false>
 void launch_step3d(dim3 grid, hipStream_t st, const StepArgs<S>& a, int ntx, int nty, bool any_full,
-                   bool any_ragged) {
+                   bool any_ragged, const typename StoreT<S>::R* U = nullptr) {
   if (any_full)
-    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, true, DIV>), grid, dim3(64, TY), 0, st, a,
-                       ntx, nty);
+    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, true, DIV, AA>), grid, dim3(64, TY), 0, st,
+                       a, ntx, nty, U);
   if (any_ragged)
-    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, false, DIV>), grid, dim3(64, TY), 0, st,
-                       a, ntx, nty);
+    hipLaunchKernelGGL((step3d_kernel<S, TY, ZC, WALLS, false, DIV, AA>), grid, dim3(64, TY), 0,
+                       st, a, ntx, nty, U);
+}
+
+// in-place D3Q19 step in FP32: the z-march with the in-place index maps, in
+// 32 x 4 columns, after the velocity pass has written u(t) to U
+vflb_status launch_aa3_march(const vflb_sim* s, hipStream_t st, const StepArgs<float>& a,
+                             const float* U) {
+  constexpr int ZC = kStep3dChunk, TY = 4;
+  const int ntx = (s->nx + 31) / 32, nty = (s->ny + TY - 1) / TY;
+  const int nzc = (s->nz + ZC - 1) / ZC;
+  const dim3 grid((unsigned)(ntx * nty * nzc));
+  const bool any_full = s->nx >= 32 && s->ny >= TY;
+  const bool any_ragged = s->nx % 32 != 0 || s->ny % TY != 0;
+  const bool div = s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE;
+  if (s->walls) {
+    if (div)
+      launch_step3d<float, TY, ZC, true, true, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
+    else
+      launch_step3d<float, TY, ZC, true, false, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
+  } else {
+    if (div)
+      launch_step3d<float, TY, ZC, false, true, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
+    else
+      launch_step3d<float, TY, ZC, false, false, true>(grid, st, a, ntx, nty, any_full, any_ragged,
+                                                       U);
+  }
+  return VFLB_OK;
 }
 
 // D3Q19 launches for tile height TY: walls or not, the stress-divergence
@@ -327,7 +354,10 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
       const int nb = (int)std::min<size_t>((s->N + 255) / 256, (size_t)1 << 16);
       hipLaunchKernelGGL((aa3_velocity_kernel<S>), dim3(nb), dim3(256), 0, st, a.pin, a.g, a.F,
                          a.inv_sf, U);
-      hipLaunchKernelGGL((aa3_step_kernel<S>), dim3(nb), dim3(256), 0, st, a, (const R*)U);
+      if constexpr (std::is_same<S, float>::value)  // FP32: the z-march
+        launch_aa3_march(s, st, a, U);
+      else  // FP64: one lane per node
+        hipLaunchKernelGGL((aa3_step_kernel<S>), dim3(nb), dim3(256), 0, st, a, (const R*)U);
       HIP_TRY(s, hipGetLastError());
       return VFLB_OK;
     }
