@@ -342,7 +342,7 @@ template <int TY> struct AnchorStage<true, TY> {
 // instead of scratch memory.
 // DIV: the stress-divergence scheme (the force of every node includes
 // div tau_p of its plane, read from a.F.div; no f^B).
-// AA: in-place streaming (FP32): one population buffer (a.pin == a.pout),
+// AA: in-place streaming (FP32, FP64): one population buffer (a.pin == a.pout),
 // the pair index maps of aa_pair_src / aa_pair_dst by the parity of t, and
 // the same-time velocity of every node from the velocity pass, U [3][N]
 // (neighbours' slots are overwritten during the step, so the ring cannot
@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   constexpr bool kDma = std::is_same<S, float>::value;
   constexpr bool ANCH = StoreT<S>::kAnchored;
   constexpr bool kF64 = std::is_same<S, double>::value;
-  static_assert(!AA || kDma, "in-place z-march: FP32 storage");
+  static_assert(!AA || !ANCH, "in-place z-march: FP32 or FP64 storage");
   constexpr int NP = 10, NC = 6, TXN = 32, SX = TXN + 2, SY = TY + 2, NS = SX * SY;
   // ring nodes: the rows above and below the tile and the columns left and
   // right of it, without the four corners (the gradient's stencil reads the
@@ -759,7 +759,8 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       for_pairs<1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         R hv[NC];
-        PA::load_h(pin, k, pair_src<k, WALLS>(pl, s, N32), N, a.inv_sh, hv);
+        const uint32_t o = AA ? aa_pair_src<k, WALLS>(pl, s, aa, N32) : pair_src<k, WALLS>(pl, s, N32);
+        PA::load_h(pin, k, o, N, a.inv_sh, hv);
 #pragma unroll
         for (int c = 0; c < NC; ++c) h[c][k] = hv[c];
       });

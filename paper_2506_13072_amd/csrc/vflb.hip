@@ -117,10 +117,11 @@ void launch_step3d(dim3 grid, hipStream_t st, const StepArgs<S>& a, int ntx, int
                        st, a, ntx, nty, U);
 }
 
-// in-place D3Q19 step in FP32: the z-march with the in-place index maps, in
-// 32 x 4 columns, after the velocity pass has written u(t) to U
-vflb_status launch_aa3_march(const vflb_sim* s, hipStream_t st, const StepArgs<float>& a,
-                             const float* U) {
+// in-place D3Q19 step: the z-march with the in-place index maps, in 32 x 4
+// columns, after the velocity pass has written u(t) to U
+template <class S>
+vflb_status launch_aa3_march(const vflb_sim* s, hipStream_t st, const StepArgs<S>& a,
+                             const typename StoreT<S>::R* U) {
   constexpr int ZC = kStep3dChunk, TY = 4;
   const int ntx = (s->nx + 31) / 32, nty = (s->ny + TY - 1) / TY;
   const int nzc = (s->nz + ZC - 1) / ZC;
@@ -130,15 +131,14 @@ vflb_status launch_aa3_march(const vflb_sim* s, hipStream_t st, const StepArgs<f
   const bool div = s->scheme == VFLB_SCHEME_STRESS_DIVERGENCE;
   if (s->walls) {
     if (div)
-      launch_step3d<float, TY, ZC, true, true, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
+      launch_step3d<S, TY, ZC, true, true, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
     else
-      launch_step3d<float, TY, ZC, true, false, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
+      launch_step3d<S, TY, ZC, true, false, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
   } else {
     if (div)
-      launch_step3d<float, TY, ZC, false, true, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
+      launch_step3d<S, TY, ZC, false, true, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
     else
-      launch_step3d<float, TY, ZC, false, false, true>(grid, st, a, ntx, nty, any_full, any_ragged,
-                                                       U);
+      launch_step3d<S, TY, ZC, false, false, true>(grid, st, a, ntx, nty, any_full, any_ragged, U);
   }
   return VFLB_OK;
 }
@@ -354,10 +354,7 @@ vflb_status launch_step(vflb_sim* s, int64_t t, hipStream_t st, int parity) {
       const int nb = (int)std::min<size_t>((s->N + 255) / 256, (size_t)1 << 16);
       hipLaunchKernelGGL((aa3_velocity_kernel<S>), dim3(nb), dim3(256), 0, st, a.pin, a.g, a.F,
                          a.inv_sf, U);
-      if constexpr (std::is_same<S, float>::value)  // FP32: the z-march
-        launch_aa3_march(s, st, a, U);
-      else  // FP64: one lane per node
-        hipLaunchKernelGGL((aa3_step_kernel<S>), dim3(nb), dim3(256), 0, st, a, (const R*)U);
+      launch_aa3_march<S>(s, st, a, U);
       HIP_TRY(s, hipGetLastError());
       return VFLB_OK;
     }

@@ -98,7 +98,8 @@ def test_in_place_maps_are_race_free_and_equal_two_buffer_streaming(nx, ny, wall
 # ---------------------------------------------------------------- D3Q19
 # The same two maps for the 19 velocities (order of App. A; opposite pairs
 # (2k-1, 2k)), with walls on any subset of the three axes: the in-place
-# D3Q19 step (aa3d.h) uses them through pull_index and aa_write_index<3>.
+# velocity pass (aa3d.h) reads through pull_index, the z-march uses them in
+# pair form (below).
 C3 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
       (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
       (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
@@ -185,3 +186,80 @@ def test_d3q19_in_place_maps_are_race_free_and_equal_two_buffer_streaming(n, wal
         for p, i in itertools.product(nodes, range(19)):
             assert two[read_slot3(i, p, n, walls, 0)] == one[read_slot3(i, p, n, walls, nm)], \
                 (t, p, i)
+
+
+# ------------------------------------------------- the maps in pair form
+# The D3Q19 z-march handles a node with two lanes: lane s holds member s of
+# each opposite pair K (direction 2K - 1 + s) and addresses the pair's two
+# planes with an offset member * N + node.  Its pull geometry swaps the
+# neighbour deltas with s, the two-buffer pull is pair_src, and the in-place
+# maps swap members (step3d.h: make_pair_pull, pair_src, aa_pair_src,
+# aa_pair_dst).  This model follows that code and must give, slot for slot,
+# the direct maps above (and the two-buffer pull of read_slot3 mode 0).
+def make_pair_pull(p, s, n, walls):
+    stride = (1, n[0], n[0] * n[1])
+    q = dict(dm=[0] * 3, dp=[0] * 3, wm=[False] * 3, wp=[False] * 3)
+    for a in range(3):
+        wall = bool(walls & (1 << a))
+        lo, hi = wall and p[a] == 0, wall and p[a] == n[a] - 1
+        from_minus = (n[a] - 1 if p[a] == 0 else -1) * stride[a]
+        from_plus = (1 - n[a] if p[a] == n[a] - 1 else 1) * stride[a]
+        q["dm"][a], q["dp"][a] = (from_plus, from_minus) if s else (from_minus, from_plus)
+        q["wm"][a], q["wp"][a] = (hi, lo) if s else (lo, hi)
+    q["self"] = (p[2] * n[1] + p[1]) * n[0] + p[0]
+    return q
+
+
+def pair_src(q, K, s, N, walls):
+    c = C3[2 * K - 1]
+    off = q["self"]
+    bounce = False
+    for a in range(3):
+        if c[a] > 0:
+            off += q["dm"][a]
+            bounce |= q["wm"][a]
+        elif c[a] < 0:
+            off += q["dp"][a]
+            bounce |= q["wp"][a]
+    if walls and bounce:
+        return (0 if s else N) + q["self"]
+    return (N if s else 0) + off
+
+
+def swap_members(o, N):
+    return o - N if o >= N else o + N
+
+
+def aa_pair_src(q, K, s, aa, N, walls):
+    if aa == 1:
+        return (N if s else 0) + q["self"]
+    return swap_members(pair_src(q, K, s, N, walls), N)
+
+
+def aa_pair_dst(q, K, s, aa, N, walls):
+    if aa == 1:
+        return (0 if s else N) + q["self"]
+    r = dict(q, dm=list(q["dp"]), dp=list(q["dm"]), wm=list(q["wp"]), wp=list(q["wm"]))
+    return swap_members(pair_src(r, K, 1 - s, N, walls), N)
+
+
+def slot_of(K, o, N):
+    """(direction, node) of a pair offset: member o // N of pair K."""
+    return (2 * K - 1 + o // N) * N + o % N
+
+
+@pytest.mark.parametrize("n,walls", CASES3)
+def test_d3q19_pair_maps_equal_the_slot_maps(n, walls):
+    N = n[0] * n[1] * n[2]
+    for p in itertools.product(range(n[0]), range(n[1]), range(n[2])):
+        for s in (0, 1):
+            q = make_pair_pull(p, s, n, walls)
+            for K in range(1, 10):
+                i = 2 * K - 1 + s
+                assert slot_of(K, pair_src(q, K, s, N, walls), N) == \
+                    read_slot3(i, p, n, walls, 0), (p, s, K)
+                for aa in (1, 2):
+                    assert slot_of(K, aa_pair_src(q, K, s, aa, N, walls), N) == \
+                        read_slot3(i, p, n, walls, aa), (p, s, K, aa)
+                    assert slot_of(K, aa_pair_dst(q, K, s, aa, N, walls), N) == \
+                        write_slot3(i, p, n, walls, aa), (p, s, K, aa)
