@@ -181,20 +181,43 @@ template <> struct Pops<3, double> : Pops3Split<double> {};
 template <> struct Pops<3, _Float16> : Pops3Split<_Float16> {};
 template <> struct Pops<3, bf16_t> : Pops3Split<bf16_t> {};
 
+// explicit fused multiply-add: the same rounding in every caller, whatever
+// contraction the compiler applies around it
+template <class R> __device__ inline R fmar(R a, R b, R c);
+template <> __device__ inline float fmar<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+template <> __device__ inline double fmar<double>(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+template <int C, class R> __device__ inline R csgn(R v) { return C > 0 ? v : -v; }
+
 // reference populations of direction i from an anchor (E = A - I, p, u);
-// a bounce-back pull reads the opposite direction: sgn = -1 flips c_i
+// a bounce-back pull reads the opposite direction: sgn = -1 flips c_i.
+// Factored with explicit fused multiply-adds, as the D3Q19 references
+// below: fref = fma(w_i, fma(cu, fma(cu, 9/2, 3), -3/2 u.u), lambda_i p),
+// href = E (w_i + t) + delta t with t = 3 w_i c.u; c.u sums the nonzero
+// components of c_i only (for an unrolled i the selects fold away), so that
+// a reader and a writer evaluate the same reference bitwise.
+template <class R>
+__device__ inline R cdot2(int i, R ux, R uy) {
+  const int cx = Lat<2>::cx(i), cy = Lat<2>::cy(i);
+  const R tx = cx > 0 ? ux : -ux, ty = cy > 0 ? uy : -uy;
+  return cx == 0 ? (cy == 0 ? (R)0 : ty) : (cy == 0 ? tx : tx + ty);
+}
 template <class R>
 __device__ inline R fref2(int i, R sgn, R p, R ux, R uy) {
   const R wi = (R)Lat<2>::w(i);
   const R lam_i = (R)(i == 0 ? 3.0 * (Lat<2>::w(0) - 1.0) : 3.0 * Lat<2>::w(i));
-  const R cu = sgn * ((R)Lat<2>::cx(i) * ux + (R)Lat<2>::cy(i) * uy);
-  return lam_i * p + wi * (3 * cu + (R)4.5 * cu * cu - (R)1.5 * (ux * ux + uy * uy));
+  const R cu = sgn * cdot2<R>(i, ux, uy);
+  const R uu = fmar(uy, uy, ux * ux);
+  return fmar(wi, fmar(cu, fmar(cu, (R)4.5, (R)3), (R)-1.5 * uu), lam_i * p);
 }
 template <class R>
 __device__ inline R href2(int i, int c, R sgn, R E, R ux, R uy) {
   const R wi = (R)Lat<2>::w(i);
-  const R cu = sgn * ((R)Lat<2>::cx(i) * ux + (R)Lat<2>::cy(i) * uy);
-  return wi * E + 3 * wi * (E + (c != 1 ? (R)1 : (R)0)) * cu;
+  const R t = (R)(3.0 * Lat<2>::w(i)) * (sgn * cdot2<R>(i, ux, uy));
+  return c != 1 ? fmar(E, wi + t, t) : E * (wi + t);
 }
 
 // Anchor of node n, kept in the population buffer after the 16-bit tuples
@@ -233,14 +256,6 @@ struct Anchor2 {
 // reference bitwise whatever contraction the compiler applies around them,
 // and the rebuilt value is the stored deviation plus exactly the reference
 // the writer subtracted.
-template <class R> __device__ inline R fmar(R a, R b, R c);
-template <> __device__ inline float fmar<float>(float a, float b, float c) {
-  return __builtin_fmaf(a, b, c);
-}
-template <> __device__ inline double fmar<double>(double a, double b, double c) {
-  return __builtin_fma(a, b, c);
-}
-template <int C, class R> __device__ inline R csgn(R v) { return C > 0 ? v : -v; }
 // c.u for c = (CX, CY, CZ) with components in {-1, 0, 1}
 template <int CX, int CY, int CZ, class R>
 __device__ inline R cdot3(const R* u) {
