@@ -207,10 +207,11 @@ vflb_status vflb_create_scheme(int lattice, int nx, int ny, int nz, int storage,
  *     The same-time velocity gradient then needs u of the neighbours before
  *     they are overwritten: a velocity pass per step writes u(t) (D more
  *     words per node of AUX).  D2Q9: results equal the two-buffer step's
- *     bit for bit.  D3Q19: one lane per node (the two-buffer step's z-march
- *     pulls planes ahead of the planes it writes, which in place would
- *     overwrite values not yet read), the same iteration up to rounding.
- *     FP32 or FP64 storage, single lattices; no settling.  The
+ *     bit for bit.  D3Q19: the z-march with the in-place maps, its
+ *     velocity ring read from u(t) instead of pulled from the neighbours'
+ *     slots; the same iteration up to rounding (the velocity sums in
+ *     another order).  FP32 or FP64 storage, single lattices; no
+ *     settling.  The
  *     population layout alternates with the parity of t; checkpoints record
  *     it (vflb_load refuses a checkpoint of the other layout). */
 enum { VFLB_OPT_INPLACE = 1 };
