@@ -275,7 +275,7 @@ template <int TY> struct Stage3<float, TY> {
   float4 h4[TY][10][64];
   float h2[2][TY][10][64];
   float f0[TY][64];
-  float aux[9][TY][64];
+  float aux[5][TY][64];  // previous-step state q = 2 j + s in slot j of lane s
 };
 
 template <class S, int TY, bool WALLS, bool AA = false>
@@ -301,8 +301,13 @@ __device__ inline void stage_issue(Stage3<S, TY>& st, const S* pin, const typena
   });
   dma_to_lds<4>(pin + n, &st.f0[ty][0]);
   if (!first) {
+    // the pair's lanes split the node's 9 words: lane s loads q = 2 j + s
+    // (both lanes of a pair are in one wave, whose waits cover both)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) dma_to_lds<4>(aux + (size_t)q * N + n, &st.aux[q][ty][0]);
+    for (int j = 0; j < 5; ++j) {
+      const int q = 2 * j + s;
+      if (q < 9) dma_to_lds<4>(aux + (size_t)q * N + n, &st.aux[j][ty][0]);
+    }
   }
 }
 
@@ -702,9 +707,10 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       });
       if (!a.first) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) chip[c] = st.aux[c][ty][tx];
+        for (int c = 0; c < NC; ++c) chip[c] = st.aux[c >> 1][ty][(tx & ~1) | (c & 1)];
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb) up[bb] = st.aux[NC + bb][ty][tx];
+        for (int bb = 0; bb < 3; ++bb)
+          up[bb] = st.aux[(NC + bb) >> 1][ty][(tx & ~1) | ((NC + bb) & 1)];
       }
       f[0] = s ? (R)0 : stage_read_f0<S, TY>(st, n, ty, tx, a.inv_sf);
       // every stage slot of this lane has been read before it is refilled
