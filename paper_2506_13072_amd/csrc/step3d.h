@@ -369,7 +369,11 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
   // axis neighbours only)
   constexpr int H = 2 * TXN + 2 * TY;
   static_assert(2 * H <= 64 * TY, "ring needs more lanes than the workgroup has");
-  __shared__ R ring[3][3][NS];
+  // velocity planes z - 1 .. z + 1; a fourth slot (when LDS allows: not
+  // with the anchor stage) takes plane z + 2 while other waves may still
+  // read plane z - 2, so that no barrier has to close a plane
+  constexpr int NRS = ANCH ? 3 : 4;
+  __shared__ R ring[NRS][3][NS];
   __shared__ Stage3<S, TY> st;
   __shared__ AnchorStage<ANCH, TY> as;
 
@@ -555,7 +559,7 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
 #pragma unroll
     for (int bb = 0; bb < 3; ++bb) u[bb] = pair_sum(sg * m[bb]) + (R)0.5 * F[bb];
   };
-  auto ring_slot = [](int zp) { return ((zp % 3) + 3) % 3; };
+  auto ring_slot = [](int zp) { return ((zp % NRS) + NRS) % NRS; };
   // velocity of plane zp from its pulled f into the ring slots
   // (the sums run for every lane, so that the loaded f are consumed on every
   // path; only the ring writes are conditional)
@@ -993,7 +997,13 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
         }
       }
     }
-    lds_barrier();  // ring slot of z - 1 free
+    // three ring slots: the slot of z - 1 is free for plane z + 2, and the
+    // anchor stage refilled for the next plane is visible to every wave
+    // (with four slots the barrier before the next collision suffices: a
+    // wave that publishes plane z + 2 has passed it for plane z, which
+    // every wave reached only after its collision of z - 1, the last
+    // reader of plane z - 2)
+    if constexpr (NRS == 3) lds_barrier();
   }
   // no LDS-DMA may land after the workgroup has ended
   __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
