@@ -936,7 +936,8 @@ __global__ void __launch_bounds__(64 * TY, (sizeof(S) == 8 || StoreT<S>::kAnchor
       // ---- stores (the even lane holds the rest populations); chi (6
       // planes) then u (3 planes) split over the pair.  First every load
       // issued during this plane has landed: the next plane reads the LDS
-      // stages they fill, after the barrier below.
+      // stages they fill (a lane its own slots of the pulled state; every
+      // wave the anchor stage, after the barrier that closes the plane).
       if constexpr (kDma || ANCH) __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
       if (in_xy) {
         if constexpr (ANCH) {
