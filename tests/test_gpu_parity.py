@@ -399,6 +399,22 @@ def test_stress_divergence_d3q19_fp32_parity_and_tiles(V):
         assert AN.rel_l2(h.moments()[k], g.moments()[k]) < 1e-6, k
 
 
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f64", 1e-13)])
+def test_d3q19_tile_height_invariance(V, storage, tol):
+    # 32 x 4 and 32 x 8 tiles on a walled lattice, ragged in x and y, whose
+    # z march spans three chunks (16, 16, 4 planes): the same iteration up
+    # to the last bit of a node's own fused arithmetic
+    mk = lambda: setup_pair(V, 3, (36, 10, 40), storage, (0, 1, 0), "const", init="smooth",
+                            Wi=2.0, beta=0.3, seed=21)[1]
+    a, b = mk(), mk()
+    b.set_tile(8)
+    a.step(60)
+    b.step(60)
+    ma, mb = a.moments(), b.moments()
+    for k in ("u", "tau"):
+        assert AN.rel_l2(mb[k], ma[k]) < tol, k
+
+
 def test_stress_divergence_d3q19_differs_and_equals_without_polymer(V):
     res = {}
     for beta in (0.5, 1.0):
